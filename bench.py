@@ -1,0 +1,217 @@
+"""Benchmark: time to 1e-8 relative residual and unknowns/s of the learned-
+smoother multigrid solver against the damped-Jacobi one, on one MI355X.
+
+Workload (one "step" = the whole hot path on one problem): the rotated
+anisotropic operator of the paper's section 6 (bilinear nine-point stencil,
+theta = pi/3, eps = 1e-3) on a 1023 x 1023 interior grid, RHS U(-1, 1) from
+seed 0: stencil generation, Galerkin hierarchy and coarsest inverse,
+smoother inference (CNN, BF16 MFMA), and the V(1,1) solve with FP64 outer
+refinement to ||f - A u|| / ||f|| <= 1e-8.  The same solve with the damped-
+Jacobi smoother is timed beside it.  Inputs are resident in device memory when
+a step starts.
+
+Prints one JSON line (see the repository's measurement notes).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-8 residual & unknowns/s: CNN-smoother MG vs Jacobi MG, 1 GPU"
+WEIGHTS = os.path.join(ROOT, "paper_2102_12071_amd", "weights", "cnn_hf.bin")
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per finest-level node of each timed kernel (mixed
+# precision: FP64 stencil 72 B and FP64 u/f in the outer residual, FP32
+# stencil 36 B and FP32 vectors in the cycle, BF16 5x5 smoother 50 B; the
+# coarse vector of the restriction/prolongation counts 1/4 of 4 B).
+BYTES_PER_NODE = {
+    "cnn": {"outer_residual": 72 + 8 + 8 + 4, "smooth_first": 50 + 4 + 4, "residual_restrict": 36 + 4 + 4 + 1,
+            "prolong": 4 + 4 + 1, "residual": 36 + 4 + 4 + 4, "smooth_apply": 50 + 4 + 4 + 4,
+            "update_u": 8 + 4 + 8},
+    "jacobi": {"outer_residual": 72 + 8 + 8 + 4, "smooth_first": 4 + 4 + 4, "residual_restrict": 36 + 4 + 4 + 1,
+               "prolong": 4 + 4 + 1, "residual": 36 + 4 + 4 + 4, "smooth_apply": 4 + 4 + 4 + 4,
+               "update_u": 8 + 4 + 8},
+}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1023)
+    ap.add_argument("--theta", type=float, default=math.pi / 3)
+    ap.add_argument("--eps", type=float, default=1e-3)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--maxit", type=int, default=20000)
+    ap.add_argument("--weights", default=WEIGHTS)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-cycles", type=int, default=30, help="V-cycles in the oracle's timed sample")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
+              f"see the sharding notes in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    if os.environ.get("WORLD_SIZE", "1") not in ("1", ""):
+        print("bench.py runs on one GPU only (WORLD_SIZE > 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import mg_inputs
+    from paper_2102_12071_amd import mgcnn
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    torch.cuda.set_device(0)
+    n, theta, eps, tol = args.n, args.theta, args.eps, args.tol
+    f = torch.tensor(mg_inputs.rhs_uniform(n, 0), dtype=torch.float64, device="cuda")
+
+    net = mgcnn.Net()
+    trained = os.path.exists(args.weights)
+    if trained:
+        net.load(args.weights)
+    else:
+        net.set(mg_inputs.cnn_init(0).astype(np.float32))
+
+    A = mgcnn.stencil_q1_rotated(n, theta, eps)
+    ctx_cnn = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_CNN, precision=mgcnn.PREC_MIXED))
+    ctx_jac = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_JACOBI, precision=mgcnn.PREC_MIXED))
+
+    def step(ctx, cnn: bool):
+        """One pass of the hot path; returns (iters, relres, phase times in ms)."""
+        t0 = time.perf_counter()
+        As = mgcnn.stencil_q1_rotated(n, theta, eps)          # a1
+        ctx.restencil([As])                                   # a2, a3 (synchronises)
+        t1 = time.perf_counter()
+        if cnn:
+            ctx.infer(net)                                    # a4
+            torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res = ctx.solve([f], tol, args.maxit)                 # a5 - a10 (synchronises)
+        t3 = time.perf_counter()
+        return res, (t1 - t0) * 1e3, (t2 - t1) * 1e3, (t3 - t2) * 1e3
+
+    def run(ctx, cnn):
+        name = "cnn" if cnn else "jacobi"
+        for w in range(args.warmup):
+            r = step(ctx, cnn)
+            log(f"{name} warmup {w}: {int(r[0].iters[0])} iterations, relres {r[0].relres[0]:.2e}, "
+                f"solve {r[3]:.1f} ms")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = []
+        for k in range(args.steps):
+            out.append(step(ctx, cnn))
+            log(f"{name} step {k}: {int(out[-1][0].iters[0])} iterations, solve {out[-1][3]:.1f} ms")
+        torch.cuda.synchronize()
+        total = (time.perf_counter() - t0) * 1e3
+        return out, total / args.steps
+
+    cnn_runs, cnn_ms = run(ctx_cnn, True)
+    jac_runs, jac_ms = run(ctx_jac, False)
+    res_c, res_j = cnn_runs[-1][0], jac_runs[-1][0]
+    N = n * n
+
+    def summary(runs, ms_step):
+        res = runs[-1][0]
+        return {"iters": int(res.iters[0]), "relres": float(res.relres[0]), "status": int(res.status[0]),
+                "ms_per_step": ms_step,
+                "setup_ms": float(np.mean([r[1] for r in runs])), "infer_ms": float(np.mean([r[2] for r in runs])),
+                "solve_ms": float(np.mean([r[3] for r in runs])),
+                "solve_device_ms": float(res.ms),
+                "ms_per_iteration": float(res.ms) / max(int(res.iters[0]), 1),
+                "unknowns_per_s": N / (ms_step * 1e-3)}
+
+    cnn_s, jac_s = summary(cnn_runs, cnn_ms), summary(jac_runs, jac_ms)
+
+    # roofline of the dominant finest-level kernel, timed live with HIP events on the library stream
+    kt = ctx_cnn.time_kernels(args.kernel_reps)
+    dom = max(kt, key=kt.get)
+    nbytes = BYTES_PER_NODE["cnn"][dom] * N
+    achieved = nbytes / (kt[dom] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "bytes_per_launch": nbytes, "avg_launch_ms": kt[dom],
+                "kernels_ms": kt,
+                "kernels_gbs": {k: BYTES_PER_NODE["cnn"][k] * N / (v * 1e-3) / 1e9 for k, v in kt.items()}}
+    # the kernel timing leaves the context's vectors undefined; the next solve resets them
+
+    out = {
+        "metric": METRIC,
+        "value": cnn_s["unknowns_per_s"],
+        "unit": "unknowns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": cnn_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"rotated anisotropic Q1, n={n}, theta={theta:.6f}, eps={eps:g}, "
+                               f"V(1,1) to {tol:g}, CNN smoother vs damped Jacobi",
+                   "n": n, "unknowns": N, "tol": tol, "precision": "bf16 CNN/smoother, fp32 cycle, fp64 refinement",
+                   "weights": "trained (HF loss)" if trained else "untrained (zero last layer = damped Jacobi)"},
+        "cnn": cnn_s,
+        "jacobi": jac_s,
+        "speedup_vs_jacobi": {"iterations": jac_s["iters"] / max(cnn_s["iters"], 1),
+                              "time_per_step": jac_ms / cnn_ms},
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(n, theta, eps, net, cnn_s["iters"], args.cpu_cycles)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(n, theta, eps, net, gpu_iters, cycles):
+    """The FP64 oracle on the host cores: stencil, hierarchy, CNN inference on
+    every level and a bounded number of V(1,1) cycles, extrapolated to the
+    GPU's iteration count."""
+    import numpy as np
+
+    import mg_inputs
+    import oracle
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    params = net.get().astype(np.float64)
+    f = mg_inputs.rhs_uniform(n, 0)
+    t0 = time.perf_counter()
+    A = oracle.stencil_q1_rotated(n, theta, eps)
+    h = oracle.Hierarchy(A)
+    t1 = time.perf_counter()
+    for l in range(h.num_levels - 1):
+        h.set_smoother(l, oracle.cnn_forward(h.stencil(l), params))
+    t2 = time.perf_counter()
+    _, k, _, _ = h.solve(f, 0.0, cycles, 1, 1)
+    t3 = time.perf_counter()
+    per_cycle = (t3 - t2) / max(k, 1)
+    total = (t1 - t0) + (t2 - t1) + per_cycle * gpu_iters
+    return {"value": n * n / total, "unit": "unknowns/s", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle: stencil + Galerkin hierarchy ({t1 - t0:.2f} s), CNN inference on all levels "
+                      f"({t2 - t1:.2f} s), {k} V(1,1) cycles timed ({per_cycle * 1e3:.1f} ms/cycle) and "
+                      f"extrapolated to the GPU's {gpu_iters} cycles"}
+
+
+if __name__ == "__main__":
+    main()

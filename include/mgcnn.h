@@ -1,0 +1,236 @@
+/*
+ * mgcnn — geometric multigrid with a learned per-point smoother on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The method is that of Huang, Li & Xi, "Learning optimal multigrid smoothers
+ * via neural networks" (arXiv 2102.12071): a V-cycle (Algorithm 1) on a
+ * structured 2-D grid with full coarsening, full-weighting restriction,
+ * bilinear prolongation and Galerkin coarse operators (section 6.1), whose
+ * smoother is produced by a convolutional network that maps each point's
+ * operator stencil to the stencil of the smoother inverse (section 4.2).
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * Grid: the unit square with an n x n interior, n = 2^k - 1; node (i, j) sits
+ *   at ((i+1)h, (j+1)h), h = 1/(n+1); zero Dirichlet boundary values.
+ * Vectors: [n][n] row-major (row j = y index), contiguous, FP64, on the device.
+ * Stencil fields: [9][n][n] FP64 on the device, channel c = 3(dy+1) + (dx+1)
+ *   (0 SW, 1 S, 2 SE, 3 W, 4 C, 5 E, 6 NW, 7 N, 8 NE).  Entries that couple to
+ *   a node outside the interior must be zero, and the centre entry positive.
+ * Smoother fields: [25][n][n], channel k = 5(dy+2) + (dx+2); the smoother acts
+ *   as a gather stencil, (H x)_p = (1/a_C(p)) sum_k W_p[k] x_{p+k}.
+ * Levels: level 0 is the input grid; level l+1 has n_{l+1} = (n_l - 1)/2 and
+ *   coarse node I sits on fine node 2I+1; the last level has n = coarsest_n.
+ * Streams: every call enqueues its work on the HIP stream given at creation
+ *   (a hipStream_t passed as void*, NULL = the null stream) and returns
+ *   without synchronising, except the calls marked "synchronises".
+ * Ownership: the caller owns every pointer it passes; calls copy what they
+ *   keep.  Contexts and networks own their device memory until destroyed.
+ * Errors: every call returns an mg_status; on a negative status nothing was
+ *   written to the caller's outputs and mg_last_error() (thread-local) holds
+ *   a message.  A context or network is not thread-safe; distinct ones are
+ *   independent.
+ */
+#ifndef MGCNN_H
+#define MGCNN_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MG_OK = 0,
+    MG_NOT_CONVERGED = 1,   /* result produced; the tolerance was not reached */
+    MG_ERR_ARG = -1,        /* bad argument (null pointer, bad size, invalid stencil) */
+    MG_ERR_SHAPE = -2,      /* sizes inconsistent with the context or network */
+    MG_ERR_DEVICE = -3,     /* HIP runtime error, or no gfx950 device */
+    MG_ERR_DIVERGED = -4,   /* residual became NaN/Inf or grew by more than 1e3 */
+    MG_ERR_STATE = -5,      /* call not valid in this state (e.g. CNN smoother before inference) */
+    MG_ERR_OOM = -6         /* device allocation failed */
+} mg_status;
+
+typedef struct mg_ctx_s *mg_ctx;   /* solver context: hierarchy for a batch of problems */
+typedef struct mg_net_s *mg_net;   /* smoother network: parameters and optimiser state */
+
+enum { MG_SMOOTHER_JACOBI = 0, MG_SMOOTHER_CNN = 1 };
+enum { MG_PREC_FP64 = 0, MG_PREC_MIXED = 1 };
+
+/* ------------------------------------------------------------------------ */
+/* Discretisation (paper section 4: bilinear nine-point stencil; section 6:  */
+/* rotated anisotropic and variable-coefficient diffusion).                  */
+/* ------------------------------------------------------------------------ */
+
+/* Bilinear finite-element stencil of -div(K grad u) with the constant tensor
+ * K = R(theta) diag(1, eps) R(theta)^T (strong direction theta, 0 < eps <= 1),
+ * without the h^-2 factor (the 2-D stiffness does not depend on h).
+ * out: device [9][n][n] FP64.  n odd, 1 <= n <= 16383. */
+mg_status mg_stencil_q1_rotated(int32_t n, double theta, double eps, double *out, void *stream);
+
+/* Five-point stencil of -div(a grad u) whose face coefficients are the mean of
+ * the two cells sharing the face.  a: device [(n+1)][(n+1)] FP64 per cell,
+ * cell (I, J) having its lower-left corner at node (I-1, J-1); a > 0.
+ * out: device [9][n][n] FP64 (corner channels zero). */
+mg_status mg_stencil_cellavg5(int32_t n, const double *a, double *out, void *stream);
+
+/* Galerkin coarse stencil Ac = R A P with R full weighting and P bilinear
+ * (section 2.2, coarse operator P^T A P up to the factor 1/4 of R = P^T/4).
+ * A: device [9][n][n]; Ac: device [9][nc][nc], nc = (n-1)/2.  n odd >= 3. */
+mg_status mg_galerkin(int32_t n, const double *A, double *Ac, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Solver context (Algorithm 1 and the solver Phi(u0, f, k) of section 2).   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t n;              /* interior points per side, n = 2^k - 1, coarsest_n <= n <= 8191 */
+    const double *stencil;  /* device [9][n][n] FP64, conventions above */
+} mg_problem;
+
+typedef struct {
+    int32_t smoother;       /* MG_SMOOTHER_JACOBI or MG_SMOOTHER_CNN                          */
+    int32_t nu_pre;         /* pre-smoothing sweeps, 0..8 (default 1)                          */
+    int32_t nu_post;        /* post-smoothing sweeps, 0..8 (default 1)                         */
+    double omega;           /* damping of the Jacobi smoother and of the CNN's Jacobi term (2/3) */
+    int32_t coarsest_n;     /* 1, 3 or 7 (default 7): solved directly in FP64                 */
+    int32_t precision;      /* MG_PREC_FP64: every kernel in FP64 (parity mode);
+                               MG_PREC_MIXED: BF16 smoother and CNN on MFMA, FP32 inner cycle,
+                               FP64 outer residual, norms and coarsest solve (default)        */
+    int32_t use_graph;      /* 1: capture one solver iteration as a HIP graph and replay it    */
+    int32_t check_every;    /* iterations between host convergence checks in mg_solve (0 = 16) */
+} mg_options;
+
+/* Fills the defaults listed above. */
+void mg_options_default(mg_options *opt);
+
+/* Builds the hierarchy of every problem: copies the stencils, forms the
+ * Galerkin levels in FP64 (and FP32 copies in mixed precision), and factors
+ * each coarsest matrix (Cholesky, explicit inverse, FP64).  Problems may have
+ * different n.  Validates the stencils (boundary entries zero, centre
+ * positive, coarsest matrix SPD): MG_ERR_ARG otherwise.  Synchronises. */
+mg_status mg_setup(const mg_problem *probs, int32_t nprob, const mg_options *opt, void *stream,
+                   mg_ctx *out);
+mg_status mg_destroy(mg_ctx ctx);
+
+/* Replaces every problem's stencil (same sizes as at set-up) and rebuilds the
+ * Galerkin levels and coarsest inverses in place, without allocating; the
+ * smoothers become stale until the next mg_smoother_infer.  Validates like
+ * mg_setup.  Synchronises. */
+mg_status mg_restencil(mg_ctx ctx, const mg_problem *probs);
+
+/* Number of levels of problem prob (1 + number of coarsenings). */
+mg_status mg_num_levels(mg_ctx ctx, int32_t prob, int32_t *nlev);
+
+/* Copies the FP64 stencil of a level out: device [9][n_l][n_l]. */
+mg_status mg_get_stencil(mg_ctx ctx, int32_t prob, int32_t level, double *out);
+
+/* Runs the network on every level but the coarsest of every problem and keeps
+ * the resulting smoothers (section 4.2: stencil -> per-point smoothing kernel)
+ * in the context.  In mixed precision the network runs in BF16 on MFMA with
+ * FP32 accumulation and the smoother is stored in BF16; in FP64 precision
+ * every operation is FP64.  Required before solving with MG_SMOOTHER_CNN. */
+mg_status mg_smoother_infer(mg_ctx ctx, mg_net net);
+
+/* Installs an explicit smoother field W for one level (device [25][n_l][n_l]
+ * FP64; stored as the context's precision).  Replaces what inference gave. */
+mg_status mg_set_smoother(mg_ctx ctx, int32_t prob, int32_t level, const double *W);
+
+/* Copies a level's smoother out as W = a_C * H, device [25][n_l][n_l] FP64
+ * (in mixed precision: the BF16 values held, times a_C in FP64). */
+mg_status mg_get_smoother(mg_ctx ctx, int32_t prob, int32_t level, double *out);
+
+/* One iteration u <- u + V(f - A u) for every problem (the V-cycle of
+ * Algorithm 1 in correction form, nu_pre/nu_post sweeps, down to the coarsest
+ * level).  f[p], u[p]: device [n_p][n_p] FP64. */
+mg_status mg_vcycle(mg_ctx ctx, const double *const *f, double *const *u);
+
+/* Stationary iteration u_0 = 0, u_{k+1} = u_k + V(f - A u_k) until
+ * ||f - A u||_2 / ||f||_2 <= rtol (section 6.1 stopping rule) or maxit
+ * iterations, per problem.  Host outputs (each may be NULL): iters[nprob],
+ * relres[nprob] (final relative residual, FP64), status[nprob]
+ * (MG_OK, MG_NOT_CONVERGED or MG_ERR_DIVERGED), history[nprob][maxit+1]
+ * (relative residual before each iteration; entries past the last are 0).
+ * Returns MG_OK when every problem converged, MG_NOT_CONVERGED or
+ * MG_ERR_DIVERGED otherwise (the solutions are written in every case).
+ * Synchronises. */
+mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double rtol, int32_t maxit,
+                   int32_t *iters, double *relres, int32_t *status, double *history);
+
+/* Time of the last mg_solve's device work in milliseconds (HIP events). */
+mg_status mg_last_solve_ms(mg_ctx ctx, double *ms);
+
+/* Kernel timing for roofline reports: launches each kernel of one solver
+ * iteration on the finest level of problem 0 (the whole size class of that
+ * level), reps times back to back between HIP events on the library's
+ * stream, and writes the mean duration per launch in milliseconds to
+ * ms[0 .. MG_NUM_TIMED_KERNELS-1] (kernel k is named by mg_kernel_name(k)).
+ * Leaves the context's vectors undefined (the next mg_solve resets them).
+ * Synchronises. */
+#define MG_NUM_TIMED_KERNELS 7
+mg_status mg_time_kernels(mg_ctx ctx, int32_t reps, double *ms);
+const char *mg_kernel_name(int32_t k);
+
+/* ------------------------------------------------------------------------ */
+/* Smoother network (section 4.2, convolutional parameterisation).           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t nlayers;         /* must be 4                                   */
+    const int32_t *channels; /* must be {9, 32, 32, 32, 25}                 */
+} mg_net_desc;
+
+/* Creates a network with all parameters zero (the smoother is then damped
+ * Jacobi: W = omega * delta_0) and zero Adam state. */
+mg_status mg_net_create(const mg_net_desc *d, void *stream, mg_net *out);
+mg_status mg_net_destroy(mg_net net);
+mg_status mg_net_num_params(mg_net net, int64_t *np);
+
+/* Parameters as a host FP32 vector: per layer, weights [Cout][Cin][3][3]
+ * (cross-correlation, ky = row offset + 1, kx = column offset + 1) then bias
+ * [Cout].  mg_net_set also clears the optimiser state.  Both synchronise. */
+mg_status mg_net_get(mg_net net, float *host, int64_t len);
+mg_status mg_net_set(mg_net net, const float *host, int64_t len);
+
+/* Checkpoint: parameters, Adam moments and step count in a little-endian
+ * binary file with a versioned header.  Synchronises. */
+mg_status mg_net_save(mg_net net, const char *path);
+mg_status mg_net_load(mg_net net, const char *path);
+
+/* One training step on the high-frequency smoothing loss
+ *   L = 1/(B J) sum_b sum_j || v_bj - H_b A_b v_bj ||_2,
+ * H_b the smoother the network produces from stencil A_b (section 3.1: the
+ * smoother has to remove only the errors the coarse grid cannot, and by the
+ * paper's Theorem 3 the mean of ||X z|| over random unit vectors z tracks
+ * ||X||_F), followed by an Adam update of the parameters. */
+typedef struct {
+    int32_t nprob;               /* B */
+    const int32_t *n;            /* host [B] grid sizes (odd, 3..255)                        */
+    const double *const *stencil;/* host [B] device pointers, [9][n_b][n_b] FP64             */
+    const float *const *vectors; /* host [B] device pointers, [nvec][n_b][n_b] FP32 unit vectors */
+    int32_t nvec;                /* J >= 1                                                    */
+} mg_train_batch;
+
+typedef struct {
+    float lr, beta1, beta2, adam_eps; /* Adam (defaults 1e-3, 0.9, 0.999, 1e-8)            */
+    double omega;                     /* 2/3                                                */
+    int32_t precision;                /* 0: FP32 forward/backward (parity); 1: BF16 on MFMA  */
+    int32_t apply_update;             /* 0: loss and gradient only                         */
+} mg_train_opts;
+
+void mg_train_opts_default(mg_train_opts *o);
+
+/* loss (host, may be NULL) receives L; grad (host [num_params], may be NULL)
+ * receives dL/dparams.  Synchronises when either is requested. */
+mg_status mg_train_step(mg_net net, const mg_train_batch *b, const mg_train_opts *o, float *loss,
+                        float *grad);
+
+/* ------------------------------------------------------------------------ */
+const char *mg_status_str(mg_status s);
+const char *mg_last_error(void);
+/* Library version string. */
+const char *mg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGCNN_H */

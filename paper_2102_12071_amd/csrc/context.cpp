@@ -1,0 +1,725 @@
+// Solver context: hierarchy set-up (Galerkin levels, coarsest inverse), the
+// V-cycle schedule over size classes, the stationary solver with per-problem
+// convergence masks, HIP-graph capture of one solver iteration, and smoother
+// inference.
+//
+// Batching: all problems of a context are advanced together.  Every distinct
+// level size forms a size class; each kernel launch covers every (problem,
+// level) pair of one class (blockIdx.z selects the pair), so the number of
+// launches per iteration depends on the number of distinct sizes, not on the
+// number of problems.  A problem that has converged (or hit maxit) is masked
+// out on the device, so one captured graph serves every iteration.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+
+#include "internal.hpp"
+#include "launch.hpp"
+
+using namespace mg;
+
+namespace {
+
+bool is_pow2m1(int n) { return n >= 1 && ((n + 1) & n) == 0; }
+
+size_t tsize(const mg_ctx_s &c) { return c.opt.precision == MG_PREC_FP64 ? sizeof(double) : sizeof(float); }
+size_t hsize(const mg_ctx_s &c) { return c.opt.precision == MG_PREC_FP64 ? sizeof(double) : sizeof(bf16_t); }
+
+template <typename T>
+const T *stencil_of(const LevelBuf &L);
+template <>
+const float *stencil_of<float>(const LevelBuf &L) { return L.A32; }
+template <>
+const double *stencil_of<double>(const LevelBuf &L) { return L.A64; }
+
+template <typename S>
+mg_status upload(Arena &arena, const std::vector<S> &v, void **dptr)
+{
+    MG_TRY(arena.alloc(dptr, sizeof(S) * v.size()));
+    MG_HIP(hipMemcpy(*dptr, v.data(), sizeof(S) * v.size(), hipMemcpyHostToDevice));
+    return MG_OK;
+}
+
+// Builds the slot tables of every size class for compute type T.
+template <typename T>
+mg_status build_slots(mg_ctx_s &c)
+{
+    typedef typename SmootherStore<T>::type HT;
+    std::map<int, std::vector<CycleSlot<T>>, std::greater<int>> cls;
+    std::map<int, std::vector<OuterSlot<T>>, std::greater<int>> out;
+    std::vector<CoarseSlot<T>> coarse;
+    for (int p = 0; p < c.nprob; ++p) {
+        ProbBuf &pb = c.probs[p];
+        for (int l = 0; l + 1 < pb.nlev; ++l) {
+            const LevelBuf &L = pb.lev[l], &Lc = pb.lev[l + 1];
+            CycleSlot<T> s{};
+            s.prob = p;
+            s.n = L.n;
+            s.P = L.P;
+            s.plane = L.plane;
+            s.A = stencil_of<T>(L);
+            s.H = (const HT *)L.H;
+            s.r = (T *)L.r;
+            s.e = (T *)L.e;
+            s.s = (T *)L.s;
+            s.rc = (T *)Lc.r;
+            s.ec = (T *)Lc.e;
+            s.nc = Lc.n;
+            s.Pc = Lc.P;
+            cls[L.n].push_back(s);
+        }
+        const LevelBuf &L0 = pb.lev[0], &Lm = pb.lev[pb.nlev - 1];
+        OuterSlot<T> o{};
+        o.prob = p;
+        o.n = L0.n;
+        o.P = L0.P;
+        o.plane = L0.plane;
+        o.A64 = L0.A64;
+        o.u = pb.u;
+        o.f = pb.f;
+        o.r = (T *)L0.r;
+        o.e = (const T *)L0.e;
+        o.partial = pb.partial;
+        out[L0.n].push_back(o);
+        CoarseSlot<T> cs{};
+        cs.prob = p;
+        cs.m = Lm.n;
+        cs.P = Lm.P;
+        cs.Ainv = pb.Ainv;
+        cs.r = (const T *)Lm.r;
+        cs.e = (T *)Lm.e;
+        coarse.push_back(cs);
+    }
+    for (auto &kv : cls) {
+        SizeClass sc;
+        sc.n = kv.first;
+        sc.nslots = (int)kv.second.size();
+        MG_TRY(upload(c.arena, kv.second, &sc.d_slots));
+        c.classes.push_back(sc);
+    }
+    for (auto &kv : out) {
+        SizeClass sc;
+        sc.n = kv.first;
+        sc.nslots = (int)kv.second.size();
+        MG_TRY(upload(c.arena, kv.second, &sc.d_slots));
+        c.outer.push_back(sc);
+    }
+    MG_TRY(upload(c.arena, coarse, &c.d_coarse));
+    return MG_OK;
+}
+
+// One V-cycle e = V(r) on every active problem (Algorithm 1, correction form).
+template <typename T>
+void enqueue_vcycle(mg_ctx_s &c, hipStream_t st)
+{
+    const bool cnn = c.opt.smoother == MG_SMOOTHER_CNN;
+    const double w = c.opt.omega;
+    for (const SizeClass &k : c.classes) {  // descending sizes
+        auto *s = (const CycleSlot<T> *)k.d_slots;
+        if (c.opt.nu_pre == 0) {
+            launch_zero_e<T>(s, k.nslots, k.n, c.d_state, st);
+        } else {
+            launch_smooth_first<T>(s, k.nslots, k.n, cnn, w, c.d_state, st);
+            for (int it = 1; it < c.opt.nu_pre; ++it) {
+                launch_residual<T>(s, k.nslots, k.n, c.d_state, st);
+                launch_smooth_apply<T>(s, k.nslots, k.n, cnn, w, c.d_state, st);
+            }
+        }
+        launch_residual_restrict<T>(s, k.nslots, k.n, c.d_state, st);
+    }
+    launch_coarse_solve<T>((const CoarseSlot<T> *)c.d_coarse, c.nprob, c.d_state, st);
+    for (auto it = c.classes.rbegin(); it != c.classes.rend(); ++it) {  // ascending sizes
+        const SizeClass &k = *it;
+        auto *s = (const CycleSlot<T> *)k.d_slots;
+        launch_prolong<T>(s, k.nslots, k.n, c.d_state, st);
+        for (int q = 0; q < c.opt.nu_post; ++q) {
+            launch_residual<T>(s, k.nslots, k.n, c.d_state, st);
+            launch_smooth_apply<T>(s, k.nslots, k.n, cnn, w, c.d_state, st);
+        }
+    }
+}
+
+template <typename T>
+void enqueue_outer_residual(mg_ctx_s &c, hipStream_t st)
+{
+    for (const SizeClass &k : c.outer)
+        launch_outer_residual<T>((const OuterSlot<T> *)k.d_slots, k.nslots, k.n, c.d_state, st);
+}
+
+template <typename T>
+void enqueue_check(mg_ctx_s &c, int init, hipStream_t st)
+{
+    for (const SizeClass &k : c.outer)
+        launch_check<T>((const OuterSlot<T> *)k.d_slots, k.nslots, c.d_state, c.d_params, init, st);
+}
+
+template <typename T>
+void enqueue_update(mg_ctx_s &c, hipStream_t st)
+{
+    for (const SizeClass &k : c.outer) launch_update_u<T>((const OuterSlot<T> *)k.d_slots, k.nslots, k.n, c.d_state, st);
+}
+
+// One solver iteration: residual, stopping rule, V-cycle, update.
+template <typename T>
+void enqueue_iteration(mg_ctx_s &c, hipStream_t st)
+{
+    enqueue_outer_residual<T>(c, st);
+    enqueue_check<T>(c, 0, st);
+    enqueue_vcycle<T>(c, st);
+    enqueue_update<T>(c, st);
+}
+
+void enqueue_iteration_any(mg_ctx_s &c, hipStream_t st)
+{
+    if (c.opt.precision == MG_PREC_FP64)
+        enqueue_iteration<double>(c, st);
+    else
+        enqueue_iteration<float>(c, st);
+}
+
+mg_status validate_options(const mg_options &o)
+{
+    if (o.smoother != MG_SMOOTHER_JACOBI && o.smoother != MG_SMOOTHER_CNN)
+        return set_error(MG_ERR_ARG, "smoother must be MG_SMOOTHER_JACOBI or MG_SMOOTHER_CNN");
+    if (o.nu_pre < 0 || o.nu_pre > 8 || o.nu_post < 0 || o.nu_post > 8)
+        return set_error(MG_ERR_ARG, "nu_pre and nu_post must be in [0, 8]");
+    if (!(o.omega > 0.0 && o.omega < 2.0)) return set_error(MG_ERR_ARG, "omega must be in (0, 2)");
+    if (o.coarsest_n != 1 && o.coarsest_n != 3 && o.coarsest_n != 7)
+        return set_error(MG_ERR_ARG, "coarsest_n must be 1, 3 or 7");
+    if (o.precision != MG_PREC_FP64 && o.precision != MG_PREC_MIXED)
+        return set_error(MG_ERR_ARG, "precision must be MG_PREC_FP64 or MG_PREC_MIXED");
+    if (o.check_every < 0) return set_error(MG_ERR_ARG, "check_every must be >= 0");
+    return MG_OK;
+}
+
+void destroy_ctx(mg_ctx c)
+{
+    if (!c) return;
+    if (c->join.internal) (void)hipStreamSynchronize(c->join.internal);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->t0) (void)hipEventDestroy(c->t0);
+    if (c->t1) (void)hipEventDestroy(c->t1);
+    c->arena.release();
+    c->join.destroy();
+    delete c;
+}
+
+// Finest stencil into the pitched layout (checked), the Galerkin levels in
+// FP64, their FP32 copies, and the coarsest inverse.
+void rebuild_problem(mg_ctx_s &c, int p, const double *stencil, hipStream_t st)
+{
+    ProbBuf &pb = c.probs[p];
+    const LevelBuf &L0 = pb.lev[0];
+    launch_copy_field(pb.n, 9, stencil, pb.n, (int64_t)pb.n * pb.n, L0.A64, L0.P, L0.plane, st);
+    launch_validate(pb.n, L0.P, L0.plane, L0.A64, c.d_flag, st);
+    for (int q = 0; q + 1 < pb.nlev; ++q) {
+        const LevelBuf &F = pb.lev[q], &Cc = pb.lev[q + 1];
+        launch_galerkin(F.n, F.P, F.plane, F.A64, Cc.P, Cc.plane, Cc.A64, st);
+    }
+    if (c.opt.precision == MG_PREC_MIXED)
+        for (int q = 0; q < pb.nlev; ++q) launch_to_f32(9 * pb.lev[q].plane, pb.lev[q].A64, pb.lev[q].A32, st);
+    const LevelBuf &Lm = pb.lev[pb.nlev - 1];
+    launch_coarse_factor(Lm.n, Lm.P, Lm.plane, Lm.A64, pb.Ainv, c.d_flag, st);
+}
+
+mg_status read_flag(mg_ctx_s &c, hipStream_t st)
+{
+    MG_HIP(hipStreamSynchronize(st));
+    int flag = 0;
+    MG_HIP(hipMemcpy(&flag, c.d_flag, sizeof(int), hipMemcpyDeviceToHost));
+    if (flag & 1) return set_error(MG_ERR_ARG, "a stencil entry couples to a node outside the grid");
+    if (flag & 2) return set_error(MG_ERR_ARG, "a stencil centre entry is not positive");
+    if (flag & 4) return set_error(MG_ERR_ARG, "a stencil entry is not finite");
+    if (flag & 8) return set_error(MG_ERR_ARG, "the coarsest-level matrix is not positive definite");
+    return MG_OK;
+}
+
+mg_status setup_impl(mg_ctx_s &c, const mg_problem *probs, hipStream_t user)
+{
+    MG_TRY(c.join.init(user));
+    MG_HIP(hipEventCreate(&c.t0));
+    MG_HIP(hipEventCreate(&c.t1));
+    MG_TRY(c.join.enter());
+    hipStream_t st = c.join.internal;
+    const bool mixed = c.opt.precision == MG_PREC_MIXED;
+    c.probs.resize(c.nprob);
+    MG_TRY(c.arena.alloc((void **)&c.d_flag, sizeof(int)));
+    for (int p = 0; p < c.nprob; ++p) {
+        ProbBuf &pb = c.probs[p];
+        pb.n = probs[p].n;
+        int m = pb.n, l = 0;
+        for (;;) {
+            LevelBuf &L = pb.lev[l];
+            L.n = m;
+            L.P = m + 1;
+            L.plane = plane_of(L.n, L.P);
+            const size_t v = (size_t)L.plane;
+            MG_TRY(c.arena.alloc((void **)&L.A64, 9 * v * sizeof(double)));
+            if (mixed) MG_TRY(c.arena.alloc((void **)&L.A32, 9 * v * sizeof(float)));
+            MG_TRY(c.arena.alloc(&L.r, v * tsize(c)));
+            MG_TRY(c.arena.alloc(&L.e, v * tsize(c)));
+            ++l;
+            if (m == c.opt.coarsest_n) break;
+            MG_TRY(c.arena.alloc(&L.H, kSmoother * v * hsize(c)));
+            MG_TRY(c.arena.alloc(&L.s, v * tsize(c)));
+            m = (m - 1) / 2;
+        }
+        pb.nlev = l;
+        const LevelBuf &L0 = pb.lev[0];
+        MG_TRY(c.arena.alloc((void **)&pb.u, (size_t)L0.plane * sizeof(double)));
+        MG_TRY(c.arena.alloc((void **)&pb.f, (size_t)L0.plane * sizeof(double)));
+        const int mm = c.opt.coarsest_n * c.opt.coarsest_n;
+        MG_TRY(c.arena.alloc((void **)&pb.Ainv, (size_t)mm * mm * sizeof(double)));
+        pb.nparts = outer_residual_parts(pb.n);
+        MG_TRY(c.arena.alloc((void **)&pb.partial, (size_t)pb.nparts * sizeof(double)));
+        rebuild_problem(c, p, probs[p].stencil, st);
+        MG_HIP(hipGetLastError());
+    }
+    if (mixed)
+        MG_TRY(build_slots<float>(c));
+    else
+        MG_TRY(build_slots<double>(c));
+    std::vector<SolveState> init(c.nprob);
+    for (int p = 0; p < c.nprob; ++p) {
+        std::memset(&init[p], 0, sizeof(SolveState));
+        init[p].nparts = c.probs[p].nparts;
+    }
+    MG_TRY(upload(c.arena, init, (void **)&c.d_state));
+    MG_TRY(c.arena.alloc((void **)&c.d_params, sizeof(SolveParams)));
+    MG_TRY(read_flag(c, st));
+    MG_TRY(c.join.leave());
+    return MG_OK;
+}
+
+mg_status check_ctx(mg_ctx c)
+{
+    if (!c) return set_error(MG_ERR_ARG, "context is null");
+    return MG_OK;
+}
+
+mg_status check_level(mg_ctx c, int prob, int level, bool smoother)
+{
+    MG_TRY(check_ctx(c));
+    if (prob < 0 || prob >= c->nprob) return set_error(MG_ERR_ARG, "problem index %d out of range", prob);
+    const int top = c->probs[prob].nlev - (smoother ? 1 : 0);
+    if (level < 0 || level >= top) return set_error(MG_ERR_ARG, "level %d out of range", level);
+    return MG_OK;
+}
+
+mg_status check_vectors(mg_ctx c, const double *const *f, double *const *u)
+{
+    if (!f || !u) return set_error(MG_ERR_ARG, "f and u must be non-null arrays of device pointers");
+    for (int p = 0; p < c->nprob; ++p)
+        if (!f[p] || !u[p]) return set_error(MG_ERR_ARG, "f[%d] or u[%d] is null", p, p);
+    return MG_OK;
+}
+
+void copy_in(mg_ctx_s &c, const double *const *f, double *const *u, bool zero_u, hipStream_t st)
+{
+    for (int p = 0; p < c.nprob; ++p) {
+        const ProbBuf &pb = c.probs[p];
+        const LevelBuf &L0 = pb.lev[0];
+        launch_copy_field(pb.n, 1, f[p], pb.n, (int64_t)pb.n * pb.n, pb.f, L0.P, L0.plane, st);
+        if (zero_u)
+            launch_zero_f64(pb.u, L0.plane, st);
+        else
+            launch_copy_field(pb.n, 1, u[p], pb.n, (int64_t)pb.n * pb.n, pb.u, L0.P, L0.plane, st);
+    }
+}
+
+void copy_out(mg_ctx_s &c, double *const *u, hipStream_t st)
+{
+    for (int p = 0; p < c.nprob; ++p) {
+        const ProbBuf &pb = c.probs[p];
+        const LevelBuf &L0 = pb.lev[0];
+        launch_copy_field(pb.n, 1, pb.u, L0.P, L0.plane, u[p], pb.n, (int64_t)pb.n * pb.n, st);
+    }
+}
+
+mg_status ensure_graph(mg_ctx_s &c)
+{
+    if (c.graph_exec || !c.opt.use_graph) return MG_OK;
+    hipStream_t st = c.join.internal;
+    MG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    enqueue_iteration_any(c, st);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (e != hipSuccess) return set_error(MG_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    c.graph = g;
+    MG_HIP(hipGraphInstantiate(&c.graph_exec, c.graph, nullptr, nullptr, 0));
+    return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mg_status mg_setup(const mg_problem *probs, int32_t nprob, const mg_options *opt_in, void *stream, mg_ctx *out)
+{
+    clear_error();
+    if (!out) return set_error(MG_ERR_ARG, "out is null");
+    *out = nullptr;
+    if (!probs || nprob < 1) return set_error(MG_ERR_ARG, "need at least one problem");
+    mg_options opt;
+    if (opt_in)
+        opt = *opt_in;
+    else
+        mg_options_default(&opt);
+    if (opt.check_every == 0) opt.check_every = 16;
+    MG_TRY(validate_options(opt));
+    for (int p = 0; p < nprob; ++p) {
+        const int n = probs[p].n;
+        if (!is_pow2m1(n) || n < opt.coarsest_n || n > 8191)
+            return set_error(MG_ERR_ARG, "problem %d: n = %d must be 2^k - 1 with coarsest_n <= n <= 8191", p, n);
+        if (!probs[p].stencil) return set_error(MG_ERR_ARG, "problem %d: stencil is null", p);
+        int levels = 1;
+        for (int m = n; m > opt.coarsest_n; m = (m - 1) / 2) ++levels;
+        if (levels > kMaxLevels) return set_error(MG_ERR_ARG, "problem %d: too many levels", p);
+    }
+    MG_TRY(require_device());
+    mg_ctx c = new mg_ctx_s();
+    c->opt = opt;
+    c->nprob = nprob;
+    mg_status s = setup_impl(*c, probs, (hipStream_t)stream);
+    if (s < 0) {
+        destroy_ctx(c);
+        return s;
+    }
+    *out = c;
+    return MG_OK;
+}
+
+mg_status mg_destroy(mg_ctx ctx)
+{
+    clear_error();
+    destroy_ctx(ctx);
+    return MG_OK;
+}
+
+mg_status mg_num_levels(mg_ctx ctx, int32_t prob, int32_t *nlev)
+{
+    clear_error();
+    MG_TRY(check_ctx(ctx));
+    if (!nlev) return set_error(MG_ERR_ARG, "nlev is null");
+    if (prob < 0 || prob >= ctx->nprob) return set_error(MG_ERR_ARG, "problem index out of range");
+    *nlev = ctx->probs[prob].nlev;
+    return MG_OK;
+}
+
+mg_status mg_get_stencil(mg_ctx ctx, int32_t prob, int32_t level, double *out)
+{
+    clear_error();
+    MG_TRY(check_level(ctx, prob, level, false));
+    if (!out) return set_error(MG_ERR_ARG, "out is null");
+    const LevelBuf &L = ctx->probs[prob].lev[level];
+    MG_TRY(ctx->join.enter());
+    launch_copy_field(L.n, 9, L.A64, L.P, L.plane, out, L.n, (int64_t)L.n * L.n, ctx->join.internal);
+    MG_HIP(hipGetLastError());
+    return ctx->join.leave();
+}
+
+mg_status mg_set_smoother(mg_ctx ctx, int32_t prob, int32_t level, const double *W)
+{
+    clear_error();
+    MG_TRY(check_level(ctx, prob, level, true));
+    if (!W) return set_error(MG_ERR_ARG, "W is null");
+    const LevelBuf &L = ctx->probs[prob].lev[level];
+    MG_TRY(ctx->join.enter());
+    hipStream_t st = ctx->join.internal;
+    if (ctx->opt.precision == MG_PREC_FP64)
+        launch_set_smoother<double>(L.n, L.P, L.plane, W, L.n, (int64_t)L.n * L.n, L.A64, (double *)L.H, st);
+    else
+        launch_set_smoother<float>(L.n, L.P, L.plane, W, L.n, (int64_t)L.n * L.n, L.A64, (bf16_t *)L.H, st);
+    MG_HIP(hipGetLastError());
+    ctx->smoother_ready = true;
+    return ctx->join.leave();
+}
+
+mg_status mg_get_smoother(mg_ctx ctx, int32_t prob, int32_t level, double *out)
+{
+    clear_error();
+    MG_TRY(check_level(ctx, prob, level, true));
+    if (!out) return set_error(MG_ERR_ARG, "out is null");
+    const LevelBuf &L = ctx->probs[prob].lev[level];
+    MG_TRY(ctx->join.enter());
+    hipStream_t st = ctx->join.internal;
+    if (ctx->opt.precision == MG_PREC_FP64)
+        launch_get_smoother<double>(L.n, L.P, L.plane, (const double *)L.H, L.A64, out, L.n, (int64_t)L.n * L.n, st);
+    else
+        launch_get_smoother<float>(L.n, L.P, L.plane, (const bf16_t *)L.H, L.A64, out, L.n, (int64_t)L.n * L.n, st);
+    MG_HIP(hipGetLastError());
+    return ctx->join.leave();
+}
+
+mg_status mg_vcycle(mg_ctx ctx, const double *const *f, double *const *u)
+{
+    clear_error();
+    MG_TRY(check_ctx(ctx));
+    MG_TRY(check_vectors(ctx, f, u));
+    if (ctx->opt.smoother == MG_SMOOTHER_CNN && !ctx->smoother_ready)
+        return set_error(MG_ERR_STATE, "CNN smoother requested but mg_smoother_infer has not run");
+    MG_TRY(ctx->join.enter());
+    hipStream_t st = ctx->join.internal;
+    copy_in(*ctx, f, u, false, st);
+    launch_activate(ctx->d_state, ctx->nprob, st);
+    if (ctx->opt.precision == MG_PREC_FP64) {
+        enqueue_outer_residual<double>(*ctx, st);
+        enqueue_vcycle<double>(*ctx, st);
+        enqueue_update<double>(*ctx, st);
+    } else {
+        enqueue_outer_residual<float>(*ctx, st);
+        enqueue_vcycle<float>(*ctx, st);
+        enqueue_update<float>(*ctx, st);
+    }
+    copy_out(*ctx, u, st);
+    MG_HIP(hipGetLastError());
+    return ctx->join.leave();
+}
+
+mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double rtol, int32_t maxit, int32_t *iters,
+                   double *relres, int32_t *status, double *history)
+{
+    clear_error();
+    MG_TRY(check_ctx(ctx));
+    MG_TRY(check_vectors(ctx, f, u));
+    if (!(rtol >= 0.0) || maxit < 0 || maxit > 100000000)
+        return set_error(MG_ERR_ARG, "need rtol >= 0 and 0 <= maxit <= 1e8");
+    if (ctx->opt.smoother == MG_SMOOTHER_CNN && !ctx->smoother_ready)
+        return set_error(MG_ERR_STATE, "CNN smoother requested but mg_smoother_infer has not run");
+    mg_ctx_s &c = *ctx;
+    const int stride = maxit + 1;
+    if (history) {
+        const size_t need = (size_t)c.nprob * stride;
+        if (need > c.history_cap) {
+            void *p = nullptr;
+            MG_TRY(c.arena.alloc(&p, need * sizeof(double)));
+            c.d_history = (double *)p;
+            c.history_cap = need;
+        }
+    }
+    MG_TRY(ensure_graph(c));
+    MG_TRY(c.join.enter());
+    hipStream_t st = c.join.internal;
+    MG_HIP(hipEventRecord(c.t0, st));
+    copy_in(c, f, u, true, st);
+    if (history) launch_zero_f64(c.d_history, (int64_t)c.nprob * stride, st);
+    static thread_local SolveParams prm;
+    prm.tol = rtol;
+    prm.maxit = maxit;
+    prm.hist_stride = stride;
+    prm.history = history ? c.d_history : nullptr;
+    MG_HIP(hipMemcpyAsync(c.d_params, &prm, sizeof prm, hipMemcpyHostToDevice, st));
+    // ||f||: the residual of u = 0
+    launch_activate(c.d_state, c.nprob, st);
+    if (c.opt.precision == MG_PREC_FP64) {
+        enqueue_outer_residual<double>(c, st);
+        enqueue_check<double>(c, 1, st);
+    } else {
+        enqueue_outer_residual<float>(c, st);
+        enqueue_check<float>(c, 1, st);
+    }
+    std::vector<SolveState> hs(c.nprob);
+    const int every = c.opt.check_every;
+    int64_t replays = 0;
+    for (;;) {
+        for (int q = 0; q < every; ++q) {
+            if (c.graph_exec)
+                MG_HIP(hipGraphLaunch(c.graph_exec, st));
+            else
+                enqueue_iteration_any(c, st);
+        }
+        replays += every;
+        MG_HIP(hipMemcpyAsync(hs.data(), c.d_state, sizeof(SolveState) * c.nprob, hipMemcpyDeviceToHost, st));
+        MG_HIP(hipStreamSynchronize(st));
+        bool any = false;
+        for (int p = 0; p < c.nprob; ++p) any |= hs[p].active != 0;
+        if (!any || replays > (int64_t)maxit + 2) break;
+    }
+    copy_out(c, u, st);
+    MG_HIP(hipEventRecord(c.t1, st));
+    MG_HIP(hipGetLastError());
+    MG_HIP(hipStreamSynchronize(st));
+    float ms = 0.0f;
+    MG_HIP(hipEventElapsedTime(&ms, c.t0, c.t1));
+    c.last_ms = ms;
+    MG_HIP(hipMemcpy(hs.data(), c.d_state, sizeof(SolveState) * c.nprob, hipMemcpyDeviceToHost));
+    if (history) MG_HIP(hipMemcpy(history, c.d_history, sizeof(double) * c.nprob * stride, hipMemcpyDeviceToHost));
+    mg_status agg = MG_OK;
+    for (int p = 0; p < c.nprob; ++p) {
+        int stt = hs[p].active ? MG_NOT_CONVERGED : hs[p].status;
+        if (iters) iters[p] = hs[p].iters;
+        if (relres) relres[p] = hs[p].relres;
+        if (status) status[p] = stt;
+        if (stt == MG_ERR_DIVERGED) agg = MG_ERR_DIVERGED;
+        else if (stt == MG_NOT_CONVERGED && agg == MG_OK) agg = MG_NOT_CONVERGED;
+    }
+    MG_TRY(c.join.leave());
+    return agg;
+}
+
+mg_status mg_last_solve_ms(mg_ctx ctx, double *ms)
+{
+    clear_error();
+    MG_TRY(check_ctx(ctx));
+    if (!ms) return set_error(MG_ERR_ARG, "ms is null");
+    *ms = ctx->last_ms;
+    return MG_OK;
+}
+
+mg_status mg_restencil(mg_ctx ctx, const mg_problem *probs)
+{
+    clear_error();
+    MG_TRY(check_ctx(ctx));
+    if (!probs) return set_error(MG_ERR_ARG, "probs is null");
+    for (int p = 0; p < ctx->nprob; ++p) {
+        if (probs[p].n != ctx->probs[p].n)
+            return set_error(MG_ERR_SHAPE, "problem %d: n = %d differs from set-up (%d)", p, probs[p].n, ctx->probs[p].n);
+        if (!probs[p].stencil) return set_error(MG_ERR_ARG, "problem %d: stencil is null", p);
+    }
+    MG_TRY(ctx->join.enter());
+    hipStream_t st = ctx->join.internal;
+    MG_HIP(hipMemsetAsync(ctx->d_flag, 0, sizeof(int), st));
+    for (int p = 0; p < ctx->nprob; ++p) rebuild_problem(*ctx, p, probs[p].stencil, st);
+    MG_HIP(hipGetLastError());
+    ctx->smoother_ready = false;
+    MG_TRY(read_flag(*ctx, st));
+    return ctx->join.leave();
+}
+
+const char *mg_kernel_name(int32_t k)
+{
+    static const char *names[MG_NUM_TIMED_KERNELS] = {"outer_residual", "smooth_first", "residual_restrict",
+                                                      "prolong", "residual", "smooth_apply", "update_u"};
+    return (k >= 0 && k < MG_NUM_TIMED_KERNELS) ? names[k] : "";
+}
+
+mg_status mg_time_kernels(mg_ctx ctx, int32_t reps, double *ms)
+{
+    clear_error();
+    MG_TRY(check_ctx(ctx));
+    if (!ms || reps < 1) return set_error(MG_ERR_ARG, "need reps >= 1 and an output array");
+    if (ctx->opt.smoother == MG_SMOOTHER_CNN && !ctx->smoother_ready)
+        return set_error(MG_ERR_STATE, "CNN smoother requested but mg_smoother_infer has not run");
+    mg_ctx_s &c = *ctx;
+    const int n0 = c.probs[0].n;
+    const SizeClass *cls = nullptr, *oc = nullptr;
+    for (const SizeClass &k : c.classes)
+        if (k.n == n0) cls = &k;
+    for (const SizeClass &k : c.outer)
+        if (k.n == n0) oc = &k;
+    if (!cls || !oc) return set_error(MG_ERR_STATE, "problem 0 has no smoothed level");
+    MG_TRY(c.join.enter());
+    hipStream_t st = c.join.internal;
+    launch_activate(c.d_state, c.nprob, st);
+    const bool cnn = c.opt.smoother == MG_SMOOTHER_CNN;
+    const double w = c.opt.omega;
+    for (int k = 0; k < MG_NUM_TIMED_KERNELS; ++k) {
+        MG_HIP(hipEventRecord(c.t0, st));
+        for (int q = 0; q < reps; ++q) {
+            if (c.opt.precision == MG_PREC_FP64) {
+                auto *s = (const CycleSlot<double> *)cls->d_slots;
+                auto *o = (const OuterSlot<double> *)oc->d_slots;
+                switch (k) {
+                case 0: launch_outer_residual<double>(o, oc->nslots, n0, c.d_state, st); break;
+                case 1: launch_smooth_first<double>(s, cls->nslots, n0, cnn, w, c.d_state, st); break;
+                case 2: launch_residual_restrict<double>(s, cls->nslots, n0, c.d_state, st); break;
+                case 3: launch_prolong<double>(s, cls->nslots, n0, c.d_state, st); break;
+                case 4: launch_residual<double>(s, cls->nslots, n0, c.d_state, st); break;
+                case 5: launch_smooth_apply<double>(s, cls->nslots, n0, cnn, w, c.d_state, st); break;
+                default: launch_update_u<double>(o, oc->nslots, n0, c.d_state, st); break;
+                }
+            } else {
+                auto *s = (const CycleSlot<float> *)cls->d_slots;
+                auto *o = (const OuterSlot<float> *)oc->d_slots;
+                switch (k) {
+                case 0: launch_outer_residual<float>(o, oc->nslots, n0, c.d_state, st); break;
+                case 1: launch_smooth_first<float>(s, cls->nslots, n0, cnn, w, c.d_state, st); break;
+                case 2: launch_residual_restrict<float>(s, cls->nslots, n0, c.d_state, st); break;
+                case 3: launch_prolong<float>(s, cls->nslots, n0, c.d_state, st); break;
+                case 4: launch_residual<float>(s, cls->nslots, n0, c.d_state, st); break;
+                case 5: launch_smooth_apply<float>(s, cls->nslots, n0, cnn, w, c.d_state, st); break;
+                default: launch_update_u<float>(o, oc->nslots, n0, c.d_state, st); break;
+                }
+            }
+        }
+        MG_HIP(hipEventRecord(c.t1, st));
+        MG_HIP(hipEventSynchronize(c.t1));
+        float t = 0.0f;
+        MG_HIP(hipEventElapsedTime(&t, c.t0, c.t1));
+        ms[k] = (double)t / reps;
+    }
+    MG_HIP(hipGetLastError());
+    return c.join.leave();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- inference
+namespace mg {
+
+// Runs the network on one level with the direct (VALU) kernels in type T.
+template <typename T>
+mg_status infer_level_direct(mg_ctx_s &c, const LevelBuf &L, const T *params, const int *ch, T *scratch,
+                             hipStream_t st)
+{
+    const int64_t v = L.plane;
+    T *x0 = scratch;
+    T *bufA = x0 + 9 * v;
+    T *bufB = bufA + 32 * v;
+    const T *A = (const T *)(c.opt.precision == MG_PREC_FP64 ? (const void *)L.A64 : (const void *)L.A32);
+    launch_cnn_input<T>(L.n, L.P, v, A, x0, st);
+    const T *in = x0;
+    int64_t off = 0;
+    T *outs[4] = {bufA, bufB, bufA, bufB};
+    for (int l = 0; l < 4; ++l) {
+        const int cin = ch[l], cout = ch[l + 1];
+        const T *w = params + off, *b = params + off + (int64_t)cout * cin * 9;
+        off += (int64_t)cout * cin * 9 + cout;
+        launch_conv3x3_direct<T>(L.n, L.P, v, cin, cout, w, b, in, outs[l], l < 3, st);
+        in = outs[l];
+    }
+    launch_cnn_output<T>(L.n, L.P, v, A, in, c.opt.omega, (typename SmootherStore<T>::type *)L.H, st);
+    MG_HIP(hipGetLastError());
+    return MG_OK;
+}
+
+mg_status net_params64(mg_net net, hipStream_t st);  // net.cpp
+mg_status net_pack_mfma(mg_net net, hipStream_t st);  // net.cpp
+
+}  // namespace mg
+
+extern "C" mg_status mg_smoother_infer(mg_ctx ctx, mg_net net)
+{
+    clear_error();
+    MG_TRY(check_ctx(ctx));
+    if (!net) return set_error(MG_ERR_ARG, "net is null");
+    mg_ctx_s &c = *ctx;
+    const bool fp64 = c.opt.precision == MG_PREC_FP64;
+    // scratch: input (9) + two ping-pong activation buffers (32 each) on the largest level
+    int64_t vmax = 0;
+    for (const ProbBuf &pb : c.probs) vmax = std::max<int64_t>(vmax, pb.lev[0].plane);
+    const size_t need = (size_t)vmax * (9 + 32 + 32) * (fp64 ? sizeof(double) : sizeof(float));
+    if (need > c.cnn_scratch_bytes) {
+        MG_TRY(c.arena.alloc(&c.cnn_scratch, need));
+        c.cnn_scratch_bytes = need;
+    }
+    MG_TRY(c.join.enter());
+    hipStream_t st = c.join.internal;
+    MG_HIP(hipEventRecord(net->join.ev, net->join.internal));
+    MG_HIP(hipStreamWaitEvent(st, net->join.ev, 0));
+    if (fp64) MG_TRY(net_params64(net, st));
+    for (ProbBuf &pb : c.probs) {
+        for (int l = 0; l + 1 < pb.nlev; ++l) {
+            const LevelBuf &L = pb.lev[l];
+            if (fp64)
+                MG_TRY(infer_level_direct<double>(c, L, net->params64, net->ch, (double *)c.cnn_scratch, st));
+            else
+                MG_TRY(infer_level_direct<float>(c, L, net->params, net->ch, (float *)c.cnn_scratch, st));
+        }
+    }
+    c.smoother_ready = true;
+    return c.join.leave();
+}

@@ -1,0 +1,387 @@
+// V-cycle kernels (Algorithm 1 in correction form) for a size class of
+// (problem, level) slots:
+//   outer residual r = f - A u in FP64 with per-block sums of squares,
+//   convergence check (section 6.1 stopping rule), u += e,
+//   first smoothing sweep from e = 0, residual s = r - A e, smoother
+//   application e += M^{-1} s (damped Jacobi M = D/omega, section 2.1, or the
+//   learned per-point 5x5 gather stencil, section 4), residual fused with
+//   full-weighting restriction, bilinear prolongation e += P e_c.
+// T = float: the mixed-precision inner cycle (FP32 arithmetic, BF16 smoother);
+// T = double: the FP64 parity cycle.  Bandwidth-bound: one thread per node,
+// rows of 64..256 consecutive nodes per block for coalesced plane reads.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace mg {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+struct RowTile {
+    int bx, by;
+};
+inline RowTile row_tile(int n)
+{
+    const int bx = n > 128 ? 256 : (n > 64 ? 128 : 64);
+    return {bx, kThreads / bx};
+}
+inline dim3 row_grid(int n, RowTile t, int nslots)
+{
+    return dim3((n + t.bx - 1) / t.bx, (n + t.by - 1) / t.by, nslots);
+}
+
+// y = sum_d A[d] x_{p+d} over the 3x3 stencil, skipping nodes outside the grid.
+template <typename S, typename X, typename Acc>
+__device__ inline Acc apply3x3(const S *A, int64_t plane, const X *x, int n, int P, int i, int j)
+{
+    const int64_t p = (int64_t)j * P + i;
+    Acc acc = 0;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+        const int jj = j + dy;
+        if (jj < 0 || jj >= n) continue;
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int ii = i + dx;
+            if (ii < 0 || ii >= n) continue;
+            const int c = 3 * (dy + 1) + (dx + 1);
+            acc += (Acc)A[c * plane + p] * (Acc)x[(int64_t)jj * P + ii];
+        }
+    }
+    return acc;
+}
+
+// (H x)_p with H stored as 25 planes of H = W / a_C.
+template <typename HT, typename X, typename Acc>
+__device__ inline Acc apply5x5(const HT *H, int64_t plane, const X *x, int n, int P, int i, int j)
+{
+    const int64_t p = (int64_t)j * P + i;
+    Acc acc = 0;
+#pragma unroll
+    for (int dy = -2; dy <= 2; ++dy) {
+        const int jj = j + dy;
+        if (jj < 0 || jj >= n) continue;
+#pragma unroll
+        for (int dx = -2; dx <= 2; ++dx) {
+            const int ii = i + dx;
+            if (ii < 0 || ii >= n) continue;
+            const int k = 5 * (dy + 2) + (dx + 2);
+            acc += (Acc)load_h(H + k * plane + p) * (Acc)x[(int64_t)jj * P + ii];
+        }
+    }
+    return acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_outer_residual(const OuterSlot<T> *slots, const SolveState *state)
+{
+    __shared__ double red[kThreads / 64];
+    const OuterSlot<T> s = slots[blockIdx.z];
+    if (!state[s.prob].active) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    double r = 0.0;
+    if (i < s.n && j < s.n) {
+        const int64_t p = (int64_t)j * s.P + i;
+        r = s.f[p] - apply3x3<double, double, double>(s.A64, s.plane, s.u, s.n, s.P, i, j);
+        s.r[p] = (T)r;
+    }
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const double sum = block_sum<kThreads>(r * r, red);
+    if (tid == 0) s.partial[blockIdx.y * gridDim.x + blockIdx.x] = sum;
+}
+
+// One block per slot.  init = 1: the partial sums are ||f||^2 (u = 0); set up
+// the problem's state.  init = 0: the stopping rule of the solver.
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+    k_check(const OuterSlot<T> *slots, SolveState *state, const SolveParams *prm, int init)
+{
+    __shared__ double red[kThreads / 64];
+    const OuterSlot<T> s = slots[blockIdx.x];
+    SolveState &st = state[s.prob];
+    if (!init && !st.active) return;
+    double acc = 0.0;
+    for (int q = threadIdx.x; q < st.nparts; q += kThreads) acc += s.partial[q];
+    const double rr = block_sum<kThreads>(acc, red);
+    if (threadIdx.x != 0) return;
+    if (init) {
+        st.fnorm = sqrt(rr);
+        st.iters = 0;
+        st.status = 0;
+        st.active = 1;
+        st.relres = 1.0;
+        return;
+    }
+    const double rel = st.fnorm > 0.0 ? sqrt(rr) / st.fnorm : 0.0;
+    st.relres = rel;
+    if (prm->history) prm->history[(int64_t)s.prob * prm->hist_stride + st.iters] = rel;
+    if (rel <= prm->tol) {
+        st.active = 0;
+        st.status = 0;
+    } else if (!isfinite(rel) || rel > 1e3) {
+        st.active = 0;
+        st.status = -4;
+    } else if (st.iters >= prm->maxit) {
+        st.active = 0;
+        st.status = 1;
+    } else {
+        st.iters += 1;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_update_u(const OuterSlot<T> *slots, const SolveState *state)
+{
+    const OuterSlot<T> s = slots[blockIdx.z];
+    if (!state[s.prob].active) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= s.n || j >= s.n) return;
+    const int64_t p = (int64_t)j * s.P + i;
+    s.u[p] += (double)s.e[p];
+}
+
+// First sweep from e = 0: e = M^{-1} r.
+template <typename T, bool CNN>
+__global__ void __launch_bounds__(kThreads) k_smooth_first(const CycleSlot<T> *slots, const SolveState *state, T omega)
+{
+    const CycleSlot<T> s = slots[blockIdx.z];
+    if (!state[s.prob].active) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= s.n || j >= s.n) return;
+    const int64_t p = (int64_t)j * s.P + i;
+    T v;
+    if (CNN)
+        v = apply5x5<typename SmootherStore<T>::type, T, T>(s.H, s.plane, s.r, s.n, s.P, i, j);
+    else
+        v = omega * s.r[p] / s.A[kCentre * s.plane + p];
+    s.e[p] = v;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_residual(const CycleSlot<T> *slots, const SolveState *state)
+{
+    const CycleSlot<T> s = slots[blockIdx.z];
+    if (!state[s.prob].active) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= s.n || j >= s.n) return;
+    const int64_t p = (int64_t)j * s.P + i;
+    s.s[p] = s.r[p] - apply3x3<T, T, T>(s.A, s.plane, s.e, s.n, s.P, i, j);
+}
+
+// e += M^{-1} s (s = r - A e from k_residual).
+template <typename T, bool CNN>
+__global__ void __launch_bounds__(kThreads) k_smooth_apply(const CycleSlot<T> *slots, const SolveState *state, T omega)
+{
+    const CycleSlot<T> s = slots[blockIdx.z];
+    if (!state[s.prob].active) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= s.n || j >= s.n) return;
+    const int64_t p = (int64_t)j * s.P + i;
+    T v;
+    if (CNN)
+        v = apply5x5<typename SmootherStore<T>::type, T, T>(s.H, s.plane, s.s, s.n, s.P, i, j);
+    else
+        v = omega * s.s[p] / s.A[kCentre * s.plane + p];
+    s.e[p] += v;
+}
+
+// Residual s = r - A e on the fine nodes under a tile of coarse nodes (staged
+// in LDS), then r_c(I) = sum_a w_R(a) s(2I+1+a), w_R = (1/16)[1 2 1; 2 4 2; 1 2 1].
+constexpr int kRcX = 32, kRcY = 8;                   // coarse tile
+constexpr int kRfX = 2 * kRcX + 1, kRfY = 2 * kRcY + 1;  // fine region
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_residual_restrict(const CycleSlot<T> *slots, const SolveState *state)
+{
+    __shared__ T sres[kRfY][kRfX];
+    const CycleSlot<T> s = slots[blockIdx.z];
+    if (!state[s.prob].active) return;
+    const int I0 = blockIdx.x * kRcX, J0 = blockIdx.y * kRcY;
+    const int x0 = 2 * I0, y0 = 2 * J0;  // fine node 2*I0 is the left neighbour of coarse I0's node
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    for (int q = tid; q < kRfX * kRfY; q += kThreads) {
+        const int fx = x0 + q % kRfX, fy = y0 + q / kRfX;
+        T v = 0;
+        if (fx < s.n && fy < s.n) {
+            const int64_t p = (int64_t)fy * s.P + fx;
+            v = s.r[p] - apply3x3<T, T, T>(s.A, s.plane, s.e, s.n, s.P, fx, fy);
+        }
+        sres[q / kRfX][q % kRfX] = v;
+    }
+    __syncthreads();
+    const int tx = tid % kRcX, ty = tid / kRcX;
+    const int I = I0 + tx, J = J0 + ty;
+    if (I >= s.nc || J >= s.nc) return;
+    const int cx = 2 * tx + 1, cy = 2 * ty + 1;
+    const T acc = (T)0.0625 * (sres[cy - 1][cx - 1] + sres[cy - 1][cx + 1] + sres[cy + 1][cx - 1] + sres[cy + 1][cx + 1]) +
+                  (T)0.125 * (sres[cy - 1][cx] + sres[cy + 1][cx] + sres[cy][cx - 1] + sres[cy][cx + 1]) +
+                  (T)0.25 * sres[cy][cx];
+    s.rc[(int64_t)J * s.Pc + I] = acc;
+}
+
+// e += P e_c: fine node 2I+1 takes e_c(I); nodes between two coarse nodes take
+// half of each; cell centres a quarter of each of four.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_prolong(const CycleSlot<T> *slots, const SolveState *state)
+{
+    const CycleSlot<T> s = slots[blockIdx.z];
+    if (!state[s.prob].active) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= s.n || j >= s.n) return;
+    int Ix[2], Jy[2];
+    T wx[2], wy[2];
+    int nx, ny;
+    if (i & 1) { Ix[0] = (i - 1) >> 1; wx[0] = 1; nx = 1; }
+    else { Ix[0] = (i >> 1) - 1; Ix[1] = i >> 1; wx[0] = wx[1] = (T)0.5; nx = 2; }
+    if (j & 1) { Jy[0] = (j - 1) >> 1; wy[0] = 1; ny = 1; }
+    else { Jy[0] = (j >> 1) - 1; Jy[1] = j >> 1; wy[0] = wy[1] = (T)0.5; ny = 2; }
+    T acc = 0;
+    for (int b = 0; b < ny; ++b) {
+        if (Jy[b] < 0 || Jy[b] >= s.nc) continue;
+        for (int a = 0; a < nx; ++a) {
+            if (Ix[a] < 0 || Ix[a] >= s.nc) continue;
+            acc += wx[a] * wy[b] * s.ec[(int64_t)Jy[b] * s.Pc + Ix[a]];
+        }
+    }
+    s.e[(int64_t)j * s.P + i] += acc;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_zero_e(const CycleSlot<T> *slots, const SolveState *state)
+{
+    const CycleSlot<T> s = slots[blockIdx.z];
+    if (!state[s.prob].active) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= s.n || j >= s.n) return;
+    s.e[(int64_t)j * s.P + i] = 0;
+}
+
+__global__ void k_activate(SolveState *state, int nprob)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < nprob) state[p].active = 1;
+}
+
+__global__ void k_zero_f64(double *x, int64_t count)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < count) x[q] = 0.0;
+}
+
+}  // namespace
+
+void launch_activate(SolveState *state, int nprob, hipStream_t st)
+{
+    k_activate<<<(nprob + 255) / 256, 256, 0, st>>>(state, nprob);
+}
+
+void launch_zero_f64(double *x, int64_t count, hipStream_t st)
+{
+    k_zero_f64<<<(unsigned)((count + 255) / 256), 256, 0, st>>>(x, count);
+}
+
+int outer_residual_parts(int n)
+{
+    const RowTile t = row_tile(n);
+    const dim3 g = row_grid(n, t, 1);
+    return (int)(g.x * g.y);
+}
+
+template <typename T>
+void launch_outer_residual(const OuterSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st)
+{
+    const RowTile t = row_tile(n);
+    k_outer_residual<T><<<row_grid(n, t, nslots), dim3(t.bx, t.by), 0, st>>>(slots, state);
+}
+
+template <typename T>
+void launch_check(const OuterSlot<T> *slots, int nslots, SolveState *state, const SolveParams *prm, int init,
+                  hipStream_t st)
+{
+    k_check<T><<<nslots, kThreads, 0, st>>>(slots, state, prm, init);
+}
+
+template <typename T>
+void launch_update_u(const OuterSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st)
+{
+    const RowTile t = row_tile(n);
+    k_update_u<T><<<row_grid(n, t, nslots), dim3(t.bx, t.by), 0, st>>>(slots, state);
+}
+
+template <typename T>
+void launch_smooth_first(const CycleSlot<T> *slots, int nslots, int n, bool cnn, double omega,
+                         const SolveState *state, hipStream_t st)
+{
+    const RowTile t = row_tile(n);
+    if (cnn)
+        k_smooth_first<T, true><<<row_grid(n, t, nslots), dim3(t.bx, t.by), 0, st>>>(slots, state, (T)omega);
+    else
+        k_smooth_first<T, false><<<row_grid(n, t, nslots), dim3(t.bx, t.by), 0, st>>>(slots, state, (T)omega);
+}
+
+template <typename T>
+void launch_residual(const CycleSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st)
+{
+    const RowTile t = row_tile(n);
+    k_residual<T><<<row_grid(n, t, nslots), dim3(t.bx, t.by), 0, st>>>(slots, state);
+}
+
+template <typename T>
+void launch_smooth_apply(const CycleSlot<T> *slots, int nslots, int n, bool cnn, double omega,
+                         const SolveState *state, hipStream_t st)
+{
+    const RowTile t = row_tile(n);
+    if (cnn)
+        k_smooth_apply<T, true><<<row_grid(n, t, nslots), dim3(t.bx, t.by), 0, st>>>(slots, state, (T)omega);
+    else
+        k_smooth_apply<T, false><<<row_grid(n, t, nslots), dim3(t.bx, t.by), 0, st>>>(slots, state, (T)omega);
+}
+
+template <typename T>
+void launch_residual_restrict(const CycleSlot<T> *slots, int nslots, int n, const SolveState *state,
+                              hipStream_t st)
+{
+    const int nc = (n - 1) / 2;
+    const dim3 g((nc + kRcX - 1) / kRcX, (nc + kRcY - 1) / kRcY, nslots);
+    k_residual_restrict<T><<<g, dim3(kRcX, kRcY), 0, st>>>(slots, state);
+}
+
+template <typename T>
+void launch_prolong(const CycleSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st)
+{
+    const RowTile t = row_tile(n);
+    k_prolong<T><<<row_grid(n, t, nslots), dim3(t.bx, t.by), 0, st>>>(slots, state);
+}
+
+template <typename T>
+void launch_zero_e(const CycleSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st)
+{
+    const RowTile t = row_tile(n);
+    k_zero_e<T><<<row_grid(n, t, nslots), dim3(t.bx, t.by), 0, st>>>(slots, state);
+}
+
+#define MG_INSTANTIATE(T)                                                                                        \
+    template void launch_outer_residual<T>(const OuterSlot<T> *, int, int, const SolveState *, hipStream_t);      \
+    template void launch_check<T>(const OuterSlot<T> *, int, SolveState *, const SolveParams *, int, hipStream_t); \
+    template void launch_update_u<T>(const OuterSlot<T> *, int, int, const SolveState *, hipStream_t);           \
+    template void launch_smooth_first<T>(const CycleSlot<T> *, int, int, bool, double, const SolveState *,       \
+                                         hipStream_t);                                                           \
+    template void launch_residual<T>(const CycleSlot<T> *, int, int, const SolveState *, hipStream_t);           \
+    template void launch_smooth_apply<T>(const CycleSlot<T> *, int, int, bool, double, const SolveState *,       \
+                                         hipStream_t);                                                           \
+    template void launch_residual_restrict<T>(const CycleSlot<T> *, int, int, const SolveState *, hipStream_t);  \
+    template void launch_prolong<T>(const CycleSlot<T> *, int, int, const SolveState *, hipStream_t);            \
+    template void launch_zero_e<T>(const CycleSlot<T> *, int, int, const SolveState *, hipStream_t);
+MG_INSTANTIATE(float)
+MG_INSTANTIATE(double)
+#undef MG_INSTANTIATE
+
+}  // namespace mg

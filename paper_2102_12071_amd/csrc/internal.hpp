@@ -1,0 +1,120 @@
+// Host-side internals shared by the runtime translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <string>
+#include <vector>
+
+#include "../../include/mgcnn.h"
+#include "common.hpp"
+
+namespace mg {
+
+// ------------------------------------------------------------ error state
+mg_status set_error(mg_status s, const char *fmt, ...);
+void clear_error();
+
+#define MG_HIP(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess)                                                                          \
+            return ::mg::set_error(e_ == hipErrorOutOfMemory ? MG_ERR_OOM : MG_ERR_DEVICE, "%s: %s (%s:%d)", \
+                                   #call, hipGetErrorString(e_), __FILE__, __LINE__);                  \
+    } while (0)
+
+#define MG_TRY(expr)                                                                                   \
+    do {                                                                                               \
+        mg_status s_ = (expr);                                                                         \
+        if (s_ < 0) return s_;                                                                         \
+    } while (0)
+
+// Checks that a gfx950 device is current (once per process).
+mg_status require_device();
+
+// Device allocations owned by a context or network, freed together.
+struct Arena {
+    std::vector<void *> blocks;
+    mg_status alloc(void **p, size_t bytes);
+    void release();
+};
+
+// Joins the library's internal stream to the caller's stream: work the caller
+// queued before the call completes first, and the caller's later work waits
+// for the library's.
+struct StreamJoin {
+    hipStream_t user = nullptr, internal = nullptr;
+    hipEvent_t ev = nullptr;
+    mg_status init(hipStream_t user_stream);
+    mg_status enter();   // internal waits for user
+    mg_status leave();   // user waits for internal
+    void destroy();
+};
+
+struct LevelBuf {
+    int n = 0, P = 0;
+    int64_t plane = 0;
+    double *A64 = nullptr;
+    float *A32 = nullptr;
+    void *H = nullptr;  // 25 planes: bf16 (mixed) or double (FP64)
+    void *r = nullptr, *e = nullptr, *s = nullptr;
+};
+
+struct ProbBuf {
+    int n = 0, nlev = 0;
+    LevelBuf lev[kMaxLevels];
+    double *u = nullptr, *f = nullptr;  // FP64 on the finest level (pitch P)
+    double *Ainv = nullptr;
+    double *partial = nullptr;
+    int nparts = 0;
+};
+
+struct SizeClass {
+    int n = 0, nslots = 0;
+    void *d_slots = nullptr;  // CycleSlot<T>[nslots] or OuterSlot<T>[nslots]
+};
+
+}  // namespace mg
+
+struct mg_net_s {
+    mg::StreamJoin join;
+    mg::Arena arena;
+    int64_t np = 0;
+    int nlayers = 4;
+    int ch[5] = {9, 32, 32, 32, 25};
+    float *params = nullptr;   // FP32 master weights (device)
+    float *m = nullptr, *v = nullptr;
+    float *grad = nullptr;     // device gradient of the last step
+    double *params64 = nullptr;
+    void *packed = nullptr;    // weights re-laid for the MFMA kernels (BF16)
+    int64_t step = 0;
+    bool packed_valid = false;
+    // training scratch, grown on demand
+    mg::Arena scratch;
+    size_t scratch_bytes = 0;
+    void *scratch_base = nullptr;
+};
+
+struct mg_ctx_s {
+    mg::StreamJoin join;
+    mg::Arena arena;
+    mg_options opt{};
+    int nprob = 0;
+    std::vector<mg::ProbBuf> probs;
+    std::vector<mg::SizeClass> classes;  // levels above the coarsest, n descending
+    std::vector<mg::SizeClass> outer;    // finest levels, by n
+    void *d_coarse = nullptr;            // CoarseSlot<T>[nprob]
+    mg::SolveState *d_state = nullptr;
+    mg::SolveParams *d_params = nullptr;
+    int *d_flag = nullptr;
+    double *d_history = nullptr;
+    size_t history_cap = 0;              // doubles
+    bool smoother_ready = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    double last_ms = 0.0;
+    // CNN inference scratch (direct path)
+    void *cnn_scratch = nullptr;
+    size_t cnn_scratch_bytes = 0;
+};

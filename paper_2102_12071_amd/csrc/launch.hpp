@@ -1,0 +1,79 @@
+// Host-side launchers of the device kernels (one translation unit per kernel
+// family; the host runtime calls only these).
+#pragma once
+#include "common.hpp"
+
+namespace mg {
+
+// ---- stencil.hip: discretisation and coarsening (FP64) ----
+void launch_q1_rotated(int n, int P, int64_t plane, double theta, double eps, double *out, hipStream_t st);
+void launch_cellavg5(int n, const double *a, int Pa, int P, int64_t plane, double *out, hipStream_t st);
+void launch_galerkin(int n, int P, int64_t plane, const double *A, int Pc, int64_t planec, double *Ac,
+                     hipStream_t st);
+void launch_copy_field(int n, int nch, const double *src, int Ps, int64_t planes, double *dst, int Pd,
+                       int64_t planed, hipStream_t st);
+void launch_to_f32(int64_t count, const double *src, float *dst, hipStream_t st);
+void launch_validate(int n, int P, int64_t plane, const double *A, int *flag, hipStream_t st);
+
+// ---- coarse.hip: coarsest-level factorisation and solve ----
+void launch_coarse_factor(int m, int P, int64_t plane, const double *A, double *Ainv, int *flag, hipStream_t st);
+template <typename T>
+void launch_coarse_solve(const CoarseSlot<T> *slots, int nslots, const SolveState *state, hipStream_t st);
+
+// ---- cycle.hip: V-cycle kernels (T = float: mixed precision; double: FP64) ----
+// Every launcher covers one size class (all slots share n); blocks of
+// problems that are no longer active return at once.
+template <typename T>
+void launch_outer_residual(const OuterSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st);
+// Number of partial sums launch_outer_residual writes per slot for size n.
+int outer_residual_parts(int n);
+template <typename T>
+void launch_check(const OuterSlot<T> *slots, int nslots, SolveState *state, const SolveParams *prm, int init,
+                  hipStream_t st);
+// Marks every problem active (single-cycle use, and before the first residual).
+void launch_activate(SolveState *state, int nprob, hipStream_t st);
+// Sets a level vector to zero (FP64 state at the start of a solve).
+void launch_zero_f64(double *x, int64_t count, hipStream_t st);
+template <typename T>
+void launch_update_u(const OuterSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st);
+template <typename T>
+void launch_smooth_first(const CycleSlot<T> *slots, int nslots, int n, bool cnn, double omega,
+                         const SolveState *state, hipStream_t st);
+template <typename T>
+void launch_residual(const CycleSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st);
+template <typename T>
+void launch_smooth_apply(const CycleSlot<T> *slots, int nslots, int n, bool cnn, double omega,
+                         const SolveState *state, hipStream_t st);
+template <typename T>
+void launch_residual_restrict(const CycleSlot<T> *slots, int nslots, int n, const SolveState *state,
+                              hipStream_t st);
+template <typename T>
+void launch_prolong(const CycleSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st);
+template <typename T>
+void launch_zero_e(const CycleSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st);
+
+// ---- cnn.hip: smoother inference ----
+// Direct (VALU) 3x3 convolution layer, "same" zero padding; planes of pitch P.
+template <typename T>
+void launch_cnn_input(int n, int P, int64_t plane, const T *A, T *x0, hipStream_t st);
+template <typename T>
+void launch_conv3x3_direct(int n, int P, int64_t plane, int cin, int cout, const T *w, const T *b, const T *in,
+                           T *out, bool relu, hipStream_t st);
+template <typename T>
+void launch_cnn_output(int n, int P, int64_t plane, const T *A, const T *y, double omega,
+                       typename SmootherStore<T>::type *H, hipStream_t st);
+void launch_f32_to_f64(int64_t count, const float *src, double *dst, hipStream_t st);
+// Fused four-layer BF16 MFMA inference (9 -> 32 -> 32 -> 32 -> 25) writing
+// H = W / a_C in BF16.  w_packed: weights laid out by pack_weights_mfma.
+void launch_cnn_fused_mfma(int n, int P, int64_t plane, const float *A32, const void *w_packed, double omega,
+                           bf16_t *H, hipStream_t st);
+// Smoother field conversions for mg_set_smoother / mg_get_smoother.
+// H = W / a_C (a_C from the FP64 stencil), and back.
+template <typename T>
+void launch_set_smoother(int n, int P, int64_t plane, const double *W, int Pw, int64_t planew, const double *A64,
+                         typename SmootherStore<T>::type *H, hipStream_t st);
+template <typename T>
+void launch_get_smoother(int n, int P, int64_t plane, const typename SmootherStore<T>::type *H,
+                         const double *A64, double *W, int Pw, int64_t planew, hipStream_t st);
+
+}  // namespace mg

@@ -1,0 +1,182 @@
+// Discretisation and coarsening kernels (setup path):
+//  * bilinear (Q1) nine-point stencil of the rotated anisotropic operator
+//    (paper section 4 stencil; section 6 tensor T(theta, xi));
+//  * five-point stencil of -div(a grad u) with face-averaged cell coefficients;
+//  * Galerkin coarse stencils Ac = R A P (section 2.2) in stencil form;
+//  * layout copies, FP64 -> FP32 conversion and input validation.
+// All in FP64; one thread per output node.  These run once per problem.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace mg {
+
+namespace {
+
+__device__ inline bool inside(int n, int i, int j) { return i >= 0 && i < n && j >= 0 && j < n; }
+
+__global__ void k_q1_rotated(int n, int P, int64_t plane, double k11, double k12, double k22, double *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= n || j >= n) return;
+    // Element integrals of the bilinear basis: each of the four cells around
+    // the node adds (k11+k22)/3 +- k12/2 to the centre, -k11/3 + k22/6 to the
+    // x-neighbour on its side, k11/6 - k22/3 to the y-neighbour on its side
+    // and -(k11+k22)/6 -+ k12/2 to the diagonal neighbour it contains.
+    const double edge_x = -k11 / 3.0 + k22 / 6.0;
+    const double edge_y = k11 / 6.0 - k22 / 3.0;
+    double v[9];
+    v[4] = 4.0 * (k11 + k22) / 3.0;
+    v[3] = v[5] = 2.0 * edge_x;
+    v[1] = v[7] = 2.0 * edge_y;
+    v[0] = v[8] = -(k11 + k22) / 6.0 - 0.5 * k12;  // SW, NE: cells where sx*sy = +1
+    v[2] = v[6] = -(k11 + k22) / 6.0 + 0.5 * k12;  // SE, NW
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        const int dx = c % 3 - 1, dy = c / 3 - 1;
+        out[c * plane + (int64_t)j * P + i] = inside(n, i + dx, j + dy) ? v[c] : 0.0;
+    }
+}
+
+__global__ void k_cellavg5(int n, const double *a, int Pa, int P, int64_t plane, double *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= n || j >= n) return;
+    // cells around node (i, j): SW (i, j), SE (i+1, j), NW (i, j+1), NE (i+1, j+1)
+    const double sw = a[(int64_t)j * Pa + i], se = a[(int64_t)j * Pa + i + 1];
+    const double nw = a[(int64_t)(j + 1) * Pa + i], ne = a[(int64_t)(j + 1) * Pa + i + 1];
+    const double aE = 0.5 * (se + ne), aW = 0.5 * (sw + nw), aN = 0.5 * (nw + ne), aS = 0.5 * (sw + se);
+    const int64_t p = (int64_t)j * P + i;
+    out[0 * plane + p] = 0.0;
+    out[2 * plane + p] = 0.0;
+    out[6 * plane + p] = 0.0;
+    out[8 * plane + p] = 0.0;
+    out[4 * plane + p] = aE + aW + aN + aS;
+    out[5 * plane + p] = (i + 1 < n) ? -aE : 0.0;
+    out[3 * plane + p] = (i > 0) ? -aW : 0.0;
+    out[7 * plane + p] = (j + 1 < n) ? -aN : 0.0;
+    out[1 * plane + p] = (j > 0) ? -aS : 0.0;
+}
+
+// Bilinear weight of a fine node at offset (bx, by) from a coarse node.
+__device__ inline double bilinear_w(int bx, int by)
+{
+    if (bx < -1 || bx > 1 || by < -1 || by > 1) return 0.0;
+    return (bx == 0 ? 1.0 : 0.5) * (by == 0 ? 1.0 : 0.5);
+}
+
+// Ac_I[D] = sum_{a in [-1,1]^2} (w(a)/4) sum_{d in [-1,1]^2} A_{2I+1+a}[d] w(a + d - 2D),
+// zero when the coarse neighbour I + D is outside the coarse grid.
+__global__ void k_galerkin(int n, int P, int64_t plane, const double *A, int nc, int Pc, int64_t planec,
+                           double *Ac)
+{
+    const int I = blockIdx.x * blockDim.x + threadIdx.x;
+    const int J = blockIdx.y * blockDim.y + threadIdx.y;
+    if (I >= nc || J >= nc) return;
+    double a[9][9];  // fine stencils of the 3x3 fine nodes around the coarse node
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int xi = 2 * I + 1 + (t % 3 - 1), xj = 2 * J + 1 + (t / 3 - 1);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) a[t][c] = A[c * plane + (int64_t)xj * P + xi];
+    }
+#pragma unroll
+    for (int D = 0; D < 9; ++D) {
+        const int Dx = D % 3 - 1, Dy = D / 3 - 1;
+        double acc = 0.0;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int ax = t % 3 - 1, ay = t / 3 - 1;
+            const double wr = 0.25 * bilinear_w(ax, ay);
+            double inner = 0.0;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) {
+                const int dx = c % 3 - 1, dy = c / 3 - 1;
+                inner += a[t][c] * bilinear_w(ax + dx - 2 * Dx, ay + dy - 2 * Dy);
+            }
+            acc += wr * inner;
+        }
+        Ac[D * planec + (int64_t)J * Pc + I] = inside(nc, I + Dx, J + Dy) ? acc : 0.0;
+    }
+}
+
+__global__ void k_copy_field(int n, int nch, const double *src, int Ps, int64_t planes, double *dst, int Pd,
+                             int64_t planed)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= n || j >= n) return;
+    for (int c = 0; c < nch; ++c) dst[c * planed + (int64_t)j * Pd + i] = src[c * planes + (int64_t)j * Ps + i];
+}
+
+__global__ void k_to_f32(int64_t count, const double *src, float *dst)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < count) dst[q] = (float)src[q];
+}
+
+// flag bit 1: an entry couples to a node outside the grid; bit 2: centre <= 0
+// or not finite; bit 4: an entry is not finite.
+__global__ void k_validate(int n, int P, int64_t plane, const double *A, int *flag)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= n || j >= n) return;
+    int bad = 0;
+    for (int c = 0; c < 9; ++c) {
+        const double v = A[c * plane + (int64_t)j * P + i];
+        if (!isfinite(v)) bad |= 4;
+        if (!inside(n, i + c % 3 - 1, j + c / 3 - 1) && v != 0.0) bad |= 1;
+    }
+    const double ac = A[kCentre * plane + (int64_t)j * P + i];
+    if (!(ac > 0.0)) bad |= 2;
+    if (bad) atomicOr(flag, bad);
+}
+
+dim3 node_grid(int n, dim3 blk) { return dim3((n + blk.x - 1) / blk.x, (n + blk.y - 1) / blk.y, 1); }
+
+}  // namespace
+
+void launch_q1_rotated(int n, int P, int64_t plane, double theta, double eps, double *out, hipStream_t st)
+{
+    const double c = cos(theta), s = sin(theta);
+    const double k11 = c * c + eps * s * s, k12 = c * s * (1.0 - eps), k22 = s * s + eps * c * c;
+    dim3 blk(64, 4);
+    k_q1_rotated<<<node_grid(n, blk), blk, 0, st>>>(n, P, plane, k11, k12, k22, out);
+}
+
+void launch_cellavg5(int n, const double *a, int Pa, int P, int64_t plane, double *out, hipStream_t st)
+{
+    dim3 blk(64, 4);
+    k_cellavg5<<<node_grid(n, blk), blk, 0, st>>>(n, a, Pa, P, plane, out);
+}
+
+void launch_galerkin(int n, int P, int64_t plane, const double *A, int Pc, int64_t planec, double *Ac,
+                     hipStream_t st)
+{
+    const int nc = (n - 1) / 2;
+    dim3 blk(64, 2);
+    k_galerkin<<<node_grid(nc, blk), blk, 0, st>>>(n, P, plane, A, nc, Pc, planec, Ac);
+}
+
+void launch_copy_field(int n, int nch, const double *src, int Ps, int64_t planes, double *dst, int Pd,
+                       int64_t planed, hipStream_t st)
+{
+    dim3 blk(64, 4);
+    k_copy_field<<<node_grid(n, blk), blk, 0, st>>>(n, nch, src, Ps, planes, dst, Pd, planed);
+}
+
+void launch_to_f32(int64_t count, const double *src, float *dst, hipStream_t st)
+{
+    const int nt = 256;
+    k_to_f32<<<(unsigned)((count + nt - 1) / nt), nt, 0, st>>>(count, src, dst);
+}
+
+void launch_validate(int n, int P, int64_t plane, const double *A, int *flag, hipStream_t st)
+{
+    dim3 blk(64, 4);
+    k_validate<<<node_grid(n, blk), blk, 0, st>>>(n, P, plane, A, flag);
+}
+
+}  // namespace mg

@@ -1,0 +1,401 @@
+"""Python binding of the mgcnn C ABI (``include/mgcnn.h``).
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``libmgcnn.so``.  PyTorch provides device memory (CUDA/HIP tensors) and the
+current stream.  There is no CPU fallback: if the library is missing or the
+device is not a gfx950, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmgcnn.so")
+
+MG_OK, MG_NOT_CONVERGED = 0, 1
+MG_ERR_ARG, MG_ERR_SHAPE, MG_ERR_DEVICE, MG_ERR_DIVERGED, MG_ERR_STATE, MG_ERR_OOM = -1, -2, -3, -4, -5, -6
+SMOOTHER_JACOBI, SMOOTHER_CNN = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+
+CNN_CHANNELS = (9, 32, 32, 32, 25)
+NUM_TIMED_KERNELS = 7
+
+# Every exported symbol of the header, with its ctypes signature.
+_c_dp = C.POINTER(C.c_double)
+_c_fp = C.POINTER(C.c_float)
+_c_ip = C.POINTER(C.c_int32)
+
+
+class MGError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+_STATUS = {0: "MG_OK", 1: "MG_NOT_CONVERGED", -1: "MG_ERR_ARG", -2: "MG_ERR_SHAPE", -3: "MG_ERR_DEVICE",
+           -4: "MG_ERR_DIVERGED", -5: "MG_ERR_STATE", -6: "MG_ERR_OOM"}
+
+
+class Problem(C.Structure):
+    _fields_ = [("n", C.c_int32), ("stencil", C.c_void_p)]
+
+
+class COptions(C.Structure):
+    _fields_ = [("smoother", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("omega", C.c_double),
+                ("coarsest_n", C.c_int32), ("precision", C.c_int32), ("use_graph", C.c_int32),
+                ("check_every", C.c_int32)]
+
+
+class NetDesc(C.Structure):
+    _fields_ = [("nlayers", C.c_int32), ("channels", _c_ip)]
+
+
+class TrainBatch(C.Structure):
+    _fields_ = [("nprob", C.c_int32), ("n", _c_ip), ("stencil", C.POINTER(C.c_void_p)),
+                ("vectors", C.POINTER(C.c_void_p)), ("nvec", C.c_int32)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("adam_eps", C.c_float),
+                ("omega", C.c_double), ("precision", C.c_int32), ("apply_update", C.c_int32)]
+
+
+SIGNATURES = {
+    "mg_stencil_q1_rotated": (C.c_int, [C.c_int32, C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
+    "mg_stencil_cellavg5": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mg_galerkin": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mg_options_default": (None, [C.POINTER(COptions)]),
+    "mg_setup": (C.c_int, [C.POINTER(Problem), C.c_int32, C.POINTER(COptions), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "mg_destroy": (C.c_int, [C.c_void_p]),
+    "mg_num_levels": (C.c_int, [C.c_void_p, C.c_int32, _c_ip]),
+    "mg_get_stencil": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "mg_smoother_infer": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mg_set_smoother": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "mg_get_smoother": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "mg_vcycle": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
+    "mg_solve": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_double, C.c_int32, _c_ip,
+                           _c_dp, _c_ip, _c_dp]),
+    "mg_last_solve_ms": (C.c_int, [C.c_void_p, _c_dp]),
+    "mg_restencil": (C.c_int, [C.c_void_p, C.POINTER(Problem)]),
+    "mg_time_kernels": (C.c_int, [C.c_void_p, C.c_int32, _c_dp]),
+    "mg_kernel_name": (C.c_char_p, [C.c_int32]),
+    "mg_net_create": (C.c_int, [C.POINTER(NetDesc), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "mg_net_destroy": (C.c_int, [C.c_void_p]),
+    "mg_net_num_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
+    "mg_net_get": (C.c_int, [C.c_void_p, _c_fp, C.c_int64]),
+    "mg_net_set": (C.c_int, [C.c_void_p, _c_fp, C.c_int64]),
+    "mg_net_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "mg_net_load": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "mg_train_opts_default": (None, [C.POINTER(TrainOpts)]),
+    "mg_train_step": (C.c_int, [C.c_void_p, C.POINTER(TrainBatch), C.POINTER(TrainOpts), _c_fp, _c_fp]),
+    "mg_status_str": (C.c_char_p, [C.c_int]),
+    "mg_last_error": (C.c_char_p, []),
+    "mg_version": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads libmgcnn.so (built by ``paper_2102_12071_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2102_12071_amd.build` "
+                          f"(there is no fallback path)")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, allow=(MG_OK,)) -> int:
+    if status in allow:
+        return status
+    msg = load_library().mg_last_error()
+    raise MGError(status, msg.decode() if msg else "")
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t: torch.Tensor, shape=None) -> torch.Tensor:
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError("expected a device (cuda) tensor")
+    if t.dtype != torch.float64:
+        raise TypeError("expected a float64 tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.contiguous()
+
+
+def _ptr(t: torch.Tensor) -> C.c_void_p:
+    return C.c_void_p(t.data_ptr())
+
+
+# ------------------------------------------------------------------ discretisation
+def stencil_q1_rotated(n: int, theta: float, eps: float, device="cuda") -> torch.Tensor:
+    out = torch.empty((9, n, n), dtype=torch.float64, device=device)
+    _check(load_library().mg_stencil_q1_rotated(n, float(theta), float(eps), _ptr(out), _stream()))
+    return out
+
+
+def stencil_cellavg5(a: torch.Tensor) -> torch.Tensor:
+    a = _dev_f64(a)
+    n = a.shape[0] - 1
+    out = torch.empty((9, n, n), dtype=torch.float64, device=a.device)
+    _check(load_library().mg_stencil_cellavg5(n, _ptr(a), _ptr(out), _stream()))
+    return out
+
+
+def galerkin(A: torch.Tensor) -> torch.Tensor:
+    A = _dev_f64(A)
+    n = A.shape[1]
+    nc = (n - 1) // 2
+    out = torch.empty((9, nc, nc), dtype=torch.float64, device=A.device)
+    _check(load_library().mg_galerkin(n, _ptr(A), _ptr(out), _stream()))
+    return out
+
+
+# ------------------------------------------------------------------------ solver
+@dataclass
+class Options:
+    smoother: int = SMOOTHER_JACOBI
+    nu_pre: int = 1
+    nu_post: int = 1
+    omega: float = 2.0 / 3.0
+    coarsest_n: int = 7
+    precision: int = PREC_MIXED
+    use_graph: int = 1
+    check_every: int = 16
+
+    def to_c(self) -> COptions:
+        return COptions(self.smoother, self.nu_pre, self.nu_post, self.omega, self.coarsest_n, self.precision,
+                        self.use_graph, self.check_every)
+
+
+@dataclass
+class SolveResult:
+    u: List[torch.Tensor]
+    iters: np.ndarray
+    relres: np.ndarray
+    status: np.ndarray
+    history: Optional[np.ndarray] = None
+    ms: float = 0.0
+
+
+class Context:
+    """A batch of problems and their multigrid hierarchies (mg_setup)."""
+
+    def __init__(self, stencils: Sequence[torch.Tensor], options: Optional[Options] = None, stream=None):
+        lib = load_library()
+        self.options = options or Options()
+        self._stencils = [_dev_f64(a) for a in stencils]
+        for a in self._stencils:
+            if a.dim() != 3 or a.shape[0] != 9 or a.shape[1] != a.shape[2]:
+                raise ValueError("stencils must be [9, n, n]")
+        self.ns = [int(a.shape[1]) for a in self._stencils]
+        probs = (Problem * len(self.ns))(*[Problem(n, a.data_ptr()) for n, a in zip(self.ns, self._stencils)])
+        h = C.c_void_p()
+        opt = self.options.to_c()
+        self._stream = stream
+        _check(lib.mg_setup(probs, len(self.ns), C.byref(opt), _stream(stream), C.byref(h)))
+        self._h = h
+        self._stencils = None  # mg_setup copied them
+
+    def restencil(self, stencils: Sequence[torch.Tensor]) -> None:
+        """New coefficients, same sizes: rebuilds the hierarchy in place."""
+        st = [_dev_f64(a) for a in stencils]
+        if [int(a.shape[1]) for a in st] != self.ns:
+            raise ValueError("sizes differ from set-up")
+        probs = (Problem * len(self.ns))(*[Problem(n, a.data_ptr()) for n, a in zip(self.ns, st)])
+        _check(load_library().mg_restencil(self._h, probs))
+
+    def time_kernels(self, reps: int = 20) -> dict:
+        """Mean launch duration (ms) of each finest-level kernel of problem 0."""
+        lib = load_library()
+        ms = np.zeros(NUM_TIMED_KERNELS, dtype=np.float64)
+        _check(lib.mg_time_kernels(self._h, int(reps), ms.ctypes.data_as(_c_dp)))
+        return {lib.mg_kernel_name(k).decode(): float(ms[k]) for k in range(NUM_TIMED_KERNELS)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().mg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nprob(self) -> int:
+        return len(self.ns)
+
+    def num_levels(self, prob: int = 0) -> int:
+        v = C.c_int32()
+        _check(load_library().mg_num_levels(self._h, prob, C.byref(v)))
+        return v.value
+
+    def level_n(self, prob: int, level: int) -> int:
+        n = self.ns[prob]
+        for _ in range(level):
+            n = (n - 1) // 2
+        return n
+
+    def stencil(self, prob: int, level: int) -> torch.Tensor:
+        m = self.level_n(prob, level)
+        out = torch.empty((9, m, m), dtype=torch.float64, device="cuda")
+        _check(load_library().mg_get_stencil(self._h, prob, level, _ptr(out)))
+        return out
+
+    def smoother(self, prob: int, level: int) -> torch.Tensor:
+        m = self.level_n(prob, level)
+        out = torch.empty((25, m, m), dtype=torch.float64, device="cuda")
+        _check(load_library().mg_get_smoother(self._h, prob, level, _ptr(out)))
+        return out
+
+    def set_smoother(self, prob: int, level: int, W: torch.Tensor) -> None:
+        m = self.level_n(prob, level)
+        W = _dev_f64(W, (25, m, m))
+        _check(load_library().mg_set_smoother(self._h, prob, level, _ptr(W)))
+        torch.cuda.current_stream().synchronize()
+
+    def infer(self, net: "Net") -> None:
+        _check(load_library().mg_smoother_infer(self._h, net._h))
+
+    def _vecs(self, xs, name):
+        if len(xs) != self.nprob:
+            raise ValueError(f"need {self.nprob} {name} vectors")
+        return [_dev_f64(x, (n, n)) for x, n in zip(xs, self.ns)]
+
+    def vcycle(self, f: Sequence[torch.Tensor], u: Sequence[torch.Tensor]) -> None:
+        """u <- u + V(f - A u) in place."""
+        f = self._vecs(f, "f")
+        u = self._vecs(u, "u")
+        fp = (C.c_void_p * self.nprob)(*[x.data_ptr() for x in f])
+        up = (C.c_void_p * self.nprob)(*[x.data_ptr() for x in u])
+        _check(load_library().mg_vcycle(self._h, fp, up))
+
+    def solve(self, f: Sequence[torch.Tensor], rtol: float, maxit: int, history: bool = False,
+              u: Optional[Sequence[torch.Tensor]] = None) -> SolveResult:
+        f = self._vecs(f, "f")
+        if u is None:
+            u = [torch.empty((n, n), dtype=torch.float64, device="cuda") for n in self.ns]
+        else:
+            u = self._vecs(u, "u")
+        fp = (C.c_void_p * self.nprob)(*[x.data_ptr() for x in f])
+        up = (C.c_void_p * self.nprob)(*[x.data_ptr() for x in u])
+        iters = np.zeros(self.nprob, dtype=np.int32)
+        relres = np.zeros(self.nprob, dtype=np.float64)
+        status = np.zeros(self.nprob, dtype=np.int32)
+        hist = np.zeros((self.nprob, maxit + 1), dtype=np.float64) if history else None
+        st = load_library().mg_solve(self._h, fp, up, float(rtol), int(maxit),
+                                     iters.ctypes.data_as(_c_ip), relres.ctypes.data_as(_c_dp),
+                                     status.ctypes.data_as(_c_ip),
+                                     hist.ctypes.data_as(_c_dp) if history else None)
+        _check(st, allow=(MG_OK, MG_NOT_CONVERGED, MG_ERR_DIVERGED))
+        ms = C.c_double()
+        _check(load_library().mg_last_solve_ms(self._h, C.byref(ms)))
+        return SolveResult(u=list(u), iters=iters, relres=relres, status=status, history=hist, ms=ms.value)
+
+
+# ----------------------------------------------------------------------- network
+@dataclass
+class TrainOptions:
+    lr: float = 1e-3
+    beta1: float = 0.9
+    beta2: float = 0.999
+    adam_eps: float = 1e-8
+    omega: float = 2.0 / 3.0
+    precision: int = 1
+    apply_update: int = 1
+
+    def to_c(self) -> TrainOpts:
+        return TrainOpts(self.lr, self.beta1, self.beta2, self.adam_eps, self.omega, self.precision,
+                         self.apply_update)
+
+
+class Net:
+    """The stencil-to-smoother network (mg_net_*)."""
+
+    def __init__(self, stream=None):
+        lib = load_library()
+        ch = (C.c_int32 * 5)(*CNN_CHANNELS)
+        d = NetDesc(4, ch)
+        h = C.c_void_p()
+        _check(lib.mg_net_create(C.byref(d), _stream(stream), C.byref(h)))
+        self._h = h
+        v = C.c_int64()
+        _check(lib.mg_net_num_params(h, C.byref(v)))
+        self.num_params = v.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().mg_net_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get(self) -> np.ndarray:
+        out = np.zeros(self.num_params, dtype=np.float32)
+        _check(load_library().mg_net_get(self._h, out.ctypes.data_as(_c_fp), self.num_params))
+        return out
+
+    def set(self, params) -> None:
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.num_params:
+            raise ValueError(f"need {self.num_params} parameters")
+        _check(load_library().mg_net_set(self._h, p.ctypes.data_as(_c_fp), self.num_params))
+
+    def save(self, path: str) -> None:
+        _check(load_library().mg_net_save(self._h, path.encode()))
+
+    def load(self, path: str) -> None:
+        _check(load_library().mg_net_load(self._h, path.encode()))
+
+    def train_step(self, stencils: Sequence[torch.Tensor], vectors: Sequence[torch.Tensor],
+                   opts: Optional[TrainOptions] = None, want_loss: bool = True, want_grad: bool = False):
+        """One step on the HF smoothing loss.  stencils: [9, n, n] float64;
+        vectors: [J, n, n] float32 per problem.  Returns (loss, grad)."""
+        opts = opts or TrainOptions()
+        B = len(stencils)
+        if B == 0 or len(vectors) != B:
+            raise ValueError("need one vector set per stencil")
+        st = [_dev_f64(a) for a in stencils]
+        J = int(vectors[0].shape[0])
+        vs = []
+        for a, v in zip(st, vectors):
+            n = a.shape[1]
+            if not (v.is_cuda and v.dtype == torch.float32 and tuple(v.shape) == (J, n, n)):
+                raise ValueError("vectors must be float32 device tensors [J, n, n]")
+            vs.append(v.contiguous())
+        ns = (C.c_int32 * B)(*[int(a.shape[1]) for a in st])
+        sp = (C.c_void_p * B)(*[a.data_ptr() for a in st])
+        vp = (C.c_void_p * B)(*[v.data_ptr() for v in vs])
+        batch = TrainBatch(B, ns, sp, vp, J)
+        o = opts.to_c()
+        loss = C.c_float()
+        grad = np.zeros(self.num_params, dtype=np.float32) if want_grad else None
+        self._keep = (st, vs)  # alive until the next step
+        _check(load_library().mg_train_step(self._h, C.byref(batch), C.byref(o),
+                                            C.byref(loss) if want_loss else None,
+                                            grad.ctypes.data_as(_c_fp) if want_grad else None))
+        return (loss.value if want_loss else None), grad

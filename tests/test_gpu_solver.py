@@ -1,0 +1,199 @@
+"""GPU parity of the discretisation, hierarchy, V-cycle and solver against the
+FP64 oracle, through the C ABI (libmgcnn.so)."""
+import math
+
+import numpy as np
+import pytest
+
+import mg_inputs
+import oracle as ora
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mg():
+    from paper_2102_12071_amd import mgcnn
+    mgcnn.load_library()
+    assert torch.cuda.is_available()
+    return mgcnn
+
+
+def _dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# ------------------------------------------------------------------ a1, a2
+@pytest.mark.parametrize("n,theta,eps", [(1, 0.3, 0.5), (7, 0.0, 1.0), (63, math.pi / 6, 0.01), (1023, math.pi / 3, 1e-3)])
+def test_stencil_q1_rotated(mg, n, theta, eps):
+    got = mg.stencil_q1_rotated(n, theta, eps).cpu().numpy()
+    ref = ora.stencil_q1_rotated(n, theta, eps)
+    assert _rel(got, ref) <= 1e-15
+
+
+@pytest.mark.parametrize("n", [7, 31, 255])
+def test_stencil_cellavg5(mg, n):
+    a = mg_inputs.lognormal_coefficient(n, 0.1, 1.0, 7)
+    got = mg.stencil_cellavg5(_dev(a)).cpu().numpy()
+    assert _rel(got, ora.stencil_cellavg5(n, a)) <= 1e-15
+
+
+@pytest.mark.parametrize("n,kind", [(3, "q1"), (15, "q1"), (63, "cell"), (511, "q1"), (127, "rand")])
+def test_galerkin(mg, n, kind):
+    if kind == "q1":
+        A = ora.stencil_q1_rotated(n, 1.1, 0.02)
+    elif kind == "cell":
+        A = ora.stencil_cellavg5(n, mg_inputs.lognormal_coefficient(n, 0.1, 1.0, 3))
+    else:
+        rng = np.random.default_rng(n)
+        k11 = rng.uniform(0.5, 1.5, (n + 1, n + 1))
+        k22 = rng.uniform(0.5, 1.5, (n + 1, n + 1))
+        k12 = rng.uniform(-0.4, 0.4, (n + 1, n + 1))
+        A = ora.stencil_q1_cells(n, k11, k12, k22)
+    got = mg.galerkin(_dev(A)).cpu().numpy()
+    assert _rel(got, ora.galerkin(A)) <= 1e-14
+
+
+def test_hierarchy_levels_match_oracle(mg):
+    n = 255
+    A = ora.stencil_cellavg5(n, mg_inputs.lognormal_coefficient(n, 0.1, 1.0, 7))
+    ctx = mg.Context([_dev(A)], mg.Options(precision=mg.PREC_FP64))
+    h = ora.Hierarchy(A)
+    assert ctx.num_levels(0) == h.num_levels == 6
+    for l in range(h.num_levels):
+        assert _rel(ctx.stencil(0, l).cpu().numpy(), h.stencil(l)) <= 1e-14
+
+
+# ------------------------------------------------------------ a3, a5-a9 FP64
+@pytest.mark.parametrize("nu", [(1, 1), (2, 2), (0, 1), (3, 0)])
+@pytest.mark.parametrize("n,coarse", [(63, 7), (31, 3), (7, 7), (15, 1)])
+def test_vcycle_jacobi_fp64(mg, nu, n, coarse):
+    A = ora.stencil_q1_rotated(n, 0.7, 0.05)
+    f = mg_inputs.rhs_uniform(n, 2)
+    u0 = mg_inputs.random_field((n, n), 3)
+    ctx = mg.Context([_dev(A)], mg.Options(precision=mg.PREC_FP64, nu_pre=nu[0], nu_post=nu[1], coarsest_n=coarse))
+    u = _dev(u0)
+    ctx.vcycle([_dev(f)], [u])
+    h = ora.Hierarchy(A, coarsest_n=coarse)
+    ref = u0 + h.vcycle(f - ora.matvec(A, u0), *nu)
+    assert _rel(u.cpu().numpy(), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("n", [31, 127])
+def test_vcycle_given_smoother_fp64(mg, n):
+    # an explicit 5x5 smoother field on every level (the learned smoother's kernel)
+    A = ora.stencil_q1_rotated(n, 2.0, 0.01)
+    h = ora.Hierarchy(A)
+    ctx = mg.Context([_dev(A)], mg.Options(precision=mg.PREC_FP64, smoother=mg.SMOOTHER_CNN))
+    rng = np.random.default_rng(n)
+    for l in range(h.num_levels - 1):
+        m = h.level_n(l)
+        W = rng.normal(0.0, 0.05, (25, m, m))
+        W[12] += 2.0 / 3.0
+        h.set_smoother(l, W)
+        ctx.set_smoother(0, l, _dev(W))
+        assert _rel(ctx.smoother(0, l).cpu().numpy(), W) <= 1e-15
+    f = mg_inputs.rhs_uniform(n, 1)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    ctx.vcycle([_dev(f)], [u])
+    assert _rel(u.cpu().numpy(), h.vcycle(f, 1, 1)) <= 1e-12
+
+
+def test_solve_c1_fp64_matches_oracle_iterates(mg):
+    p = mg_inputs.config_c1()
+    A = ora.stencil_q1_rotated(p.n, p.theta, p.eps)
+    f = mg_inputs.rhs_uniform(p.n, p.rhs_seed)
+    ctx = mg.Context([_dev(A)], mg.Options(precision=mg.PREC_FP64, nu_pre=2, nu_post=2))
+    res = ctx.solve([_dev(f)], 1e-10, 1000, history=True)
+    u_ref, k, hist, conv = ora.Hierarchy(A).solve(f, 1e-10, 1000, 2, 2)
+    assert conv and res.status[0] == 0
+    assert res.iters[0] == k == 148
+    # FP64 rounding of ||f - A u|| near convergence is ~1e-16 * ||A|| ||u|| / ||f||: an absolute floor
+    assert np.allclose(res.history[0, :k + 1], hist, rtol=1e-9, atol=1e-14)
+    assert _rel(res.u[0].cpu().numpy(), u_ref) <= 1e-11
+    assert res.relres[0] <= 1e-10
+
+
+# ------------------------------------------------------------ mixed precision
+def test_solve_c1_mixed_jacobi(mg):
+    p = mg_inputs.config_c1()
+    A = ora.stencil_q1_rotated(p.n, p.theta, p.eps)
+    f = mg_inputs.rhs_uniform(p.n, p.rhs_seed)
+    ctx = mg.Context([_dev(A)], mg.Options(precision=mg.PREC_MIXED, nu_pre=2, nu_post=2))
+    res = ctx.solve([_dev(f)], 1e-10, 1000, history=True)
+    _, k, hist, _ = ora.Hierarchy(A).solve(f, 1e-10, 1000, 2, 2)
+    assert res.status[0] == 0 and abs(int(res.iters[0]) - k) <= 2
+    m = min(k, int(res.iters[0])) + 1
+    ratio = res.history[0, :m] / hist[:m]
+    assert np.all(ratio < 2.0) and np.all(ratio > 0.5)
+    r = f - ora.matvec(A, res.u[0].cpu().numpy())
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-10
+
+
+def test_uneven_batch_matches_individual_solves(mg):
+    # problems of different sizes and coefficients in one context (size classes)
+    specs = [(63, 0.3, 0.1), (127, 2.0, 0.01), (31, 1.0, 1.0), (63, 2.9, 0.003), (7, 0.5, 0.5)]
+    As = [ora.stencil_q1_rotated(n, t, e) for n, t, e in specs]
+    fs = [mg_inputs.rhs_uniform(n, 10 + q) for q, (n, _, _) in enumerate(specs)]
+    ctx = mg.Context([_dev(A) for A in As], mg.Options(precision=mg.PREC_FP64))
+    res = ctx.solve([_dev(f) for f in fs], 1e-9, 3000, history=True)
+    for q, (A, f) in enumerate(zip(As, fs)):
+        u_ref, k, hist, conv = ora.Hierarchy(A).solve(f, 1e-9, 3000, 1, 1)
+        assert res.status[q] == 0 and res.iters[q] == k, (q, res.iters[q], k)
+        assert np.allclose(res.history[q, :k + 1], hist, rtol=1e-9, atol=1e-14)
+        assert _rel(res.u[q].cpu().numpy(), u_ref) <= 1e-10
+
+
+def test_maxit_and_not_converged_status(mg):
+    n = 63
+    A = ora.stencil_q1_rotated(n, 1.0, 1e-3)
+    ctx = mg.Context([_dev(A)], mg.Options(precision=mg.PREC_MIXED))
+    res = ctx.solve([_dev(mg_inputs.rhs_uniform(n, 0))], 1e-10, 3)
+    assert res.iters[0] == 3 and res.status[0] == mg.MG_NOT_CONVERGED
+
+
+def test_zero_rhs_converges_immediately(mg):
+    n = 31
+    A = ora.stencil_q1_rotated(n, 1.0, 0.1)
+    ctx = mg.Context([_dev(A)], mg.Options())
+    res = ctx.solve([torch.zeros((n, n), dtype=torch.float64, device="cuda")], 1e-8, 10)
+    assert res.iters[0] == 0 and res.status[0] == 0
+    assert float(res.u[0].abs().max()) == 0.0
+
+
+def test_setup_rejects_invalid_stencils(mg):
+    n = 15
+    A = ora.stencil_q1_rotated(n, 0.2, 0.3)
+    bad = A.copy()
+    bad[0, 0, 3] = 0.1            # couples to a node below the grid
+    with pytest.raises(mg.MGError):
+        mg.Context([_dev(bad)])
+    with pytest.raises(mg.MGError):
+        mg.Context([_dev(-A)])    # centre not positive
+    ctx = mg.Context([_dev(A)], mg.Options(smoother=mg.SMOOTHER_CNN))
+    with pytest.raises(mg.MGError) as ei:
+        ctx.solve([_dev(mg_inputs.rhs_uniform(n, 0))], 1e-8, 10)
+    assert ei.value.status == mg.MG_ERR_STATE
+
+
+def test_graph_and_eager_give_identical_results(mg):
+    n = 127
+    A = ora.stencil_q1_rotated(n, 0.4, 0.02)
+    f = _dev(mg_inputs.rhs_uniform(n, 4))
+    outs = []
+    for g in (0, 1):
+        ctx = mg.Context([_dev(A)], mg.Options(use_graph=g, check_every=5))
+        res = ctx.solve([f], 1e-8, 2000, history=True)
+        outs.append(res)
+    assert outs[0].iters[0] == outs[1].iters[0]
+    assert torch.equal(outs[0].u[0], outs[1].u[0])
+    # replaying the graph again gives the same bits (deterministic reductions)
+    res = ctx.solve([f], 1e-8, 2000)
+    assert torch.equal(res.u[0], outs[1].u[0])

@@ -93,6 +93,7 @@ struct mg_net_s {
     mg::Arena scratch;
     size_t scratch_bytes = 0;
     void *scratch_base = nullptr;
+    std::vector<char> host_desc;  // source of the last asynchronous descriptor upload
 };
 
 struct mg_ctx_s {

@@ -1,0 +1,44 @@
+// Training-step data structures and kernel launchers.
+#pragma once
+#include "common.hpp"
+
+namespace mg {
+
+// One problem of a training batch.  Planes have pitch n (no padding).
+struct TrainProb {
+    int index;        // position in the batch
+    int n;
+    int64_t plane;    // n * n
+    const double *A;  // stencil [9][n][n] FP64 (caller's)
+    const float *V;   // HF vectors [J][n][n] (caller's)
+    float *x0;        // network input [9][plane]
+    float *act;       // post-ReLU activations of layers 1..3, [3][32][plane]
+    float *y;         // last-layer output [25][plane]
+    float *Av;        // [J][plane]
+    float *g;         // v - H A v, [J][plane]
+    float *gnorm;     // [J]
+    float *dA, *dB;   // gradient ping-pong buffers, [32][plane] each
+};
+
+// Offsets of one layer's weights and bias in the flat parameter vector.
+struct TrainLayer {
+    int cin, cout;
+    int64_t woff, boff;
+};
+
+void launch_tr_input(const TrainProb *probs, int nb, int n, hipStream_t st);
+void launch_tr_conv_fwd(const TrainProb *probs, int nb, int n, const float *params, TrainLayer L, int layer,
+                        hipStream_t st);
+void launch_tr_av(const TrainProb *probs, int nb, int n, int J, hipStream_t st);
+void launch_tr_residual_norm(const TrainProb *probs, int nb, int J, float omega, float *loss_part, hipStream_t st);
+void launch_tr_dout(const TrainProb *probs, int nb, int n, int J, float scale, hipStream_t st);
+void launch_tr_conv_bwd_data(const TrainProb *probs, int nb, int n, const float *params, TrainLayer L, int layer,
+                             hipStream_t st);
+void launch_tr_conv_bwd_weight(const TrainProb *probs, int nb, TrainLayer L, int layer, float *wpart, int64_t np,
+                               hipStream_t st);
+void launch_tr_reduce(const float *wpart, int B, int64_t np, float *grad, hipStream_t st);
+void launch_tr_loss(const float *loss_part, int count, float scale, float *loss, hipStream_t st);
+void launch_adam(int64_t np, float *p, float *m, float *v, const float *g, float lr, float b1, float b2, float eps,
+                 float c1, float c2, hipStream_t st);
+
+}  // namespace mg

@@ -1,0 +1,113 @@
+"""GPU parity of smoother inference and of the learned-smoother cycle against
+the FP64 oracle (through the C ABI)."""
+import math
+
+import numpy as np
+import pytest
+
+import mg_inputs
+import oracle as ora
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mg():
+    from paper_2102_12071_amd import mgcnn
+    mgcnn.load_library()
+    return mgcnn
+
+
+def _dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _net(mg, params):
+    net = mg.Net()
+    net.set(np.asarray(params, dtype=np.float32))
+    return net
+
+
+def _problem(kind, n):
+    if kind == "q1":
+        return ora.stencil_q1_rotated(n, 1.0, 0.01)
+    a = mg_inputs.lognormal_coefficient(n, 0.1, 1.0, 7)
+    return ora.stencil_cellavg5(n, a)
+
+
+@pytest.mark.parametrize("kind,n", [("q1", 127), ("cell", 63), ("q1", 15)])
+def test_inference_fp64_every_level(mg, kind, n):
+    A = _problem(kind, n)
+    params = mg_inputs.cnn_random(5)
+    ctx = mg.Context([_dev(A)], mg.Options(smoother=mg.SMOOTHER_CNN, precision=mg.PREC_FP64))
+    ctx.infer(_net(mg, params))
+    h = ora.Hierarchy(A)
+    for l in range(h.num_levels - 1):
+        W = ora.cnn_forward(h.stencil(l), params)
+        got = ctx.smoother(0, l).cpu().numpy()
+        assert np.abs(got - W).max() <= 1e-12 * np.abs(W).max(), l
+
+
+@pytest.mark.parametrize("kind,n", [("q1", 255), ("cell", 127)])
+def test_inference_mixed_within_bf16_tolerance(mg, kind, n):
+    A = _problem(kind, n)
+    params = mg_inputs.cnn_random(6)
+    ctx = mg.Context([_dev(A)], mg.Options(smoother=mg.SMOOTHER_CNN, precision=mg.PREC_MIXED))
+    ctx.infer(_net(mg, params))
+    h = ora.Hierarchy(A)
+    for l in range(h.num_levels - 1):
+        W = ora.cnn_forward(h.stencil(l), params)
+        got = ctx.smoother(0, l).cpu().numpy()
+        rel = np.linalg.norm(got - W) / np.linalg.norm(W)
+        assert rel <= 1e-2, (l, rel)
+
+
+def test_zero_last_layer_reproduces_jacobi(mg):
+    n = 63
+    A = ora.stencil_q1_rotated(n, 0.6, 0.02)
+    f = _dev(mg_inputs.rhs_uniform(n, 3))
+    ctx_c = mg.Context([_dev(A)], mg.Options(smoother=mg.SMOOTHER_CNN, precision=mg.PREC_FP64))
+    ctx_c.infer(_net(mg, mg_inputs.cnn_init(1)))
+    ctx_j = mg.Context([_dev(A)], mg.Options(smoother=mg.SMOOTHER_JACOBI, precision=mg.PREC_FP64))
+    rc = ctx_c.solve([f], 1e-10, 2000, history=True)
+    rj = ctx_j.solve([f], 1e-10, 2000, history=True)
+    assert rc.iters[0] == rj.iters[0]
+    k = int(rc.iters[0])
+    assert np.allclose(rc.history[0, :k + 1], rj.history[0, :k + 1], rtol=1e-9, atol=1e-14)
+    assert (rc.u[0] - rj.u[0]).abs().max().item() <= 1e-11 * rj.u[0].abs().max().item()
+
+
+@pytest.mark.parametrize("n", [31, 127])
+def test_cnn_vcycle_fp64_matches_oracle(mg, n):
+    A = ora.stencil_q1_rotated(n, 2.2, 0.005)
+    params = mg_inputs.cnn_random(9)
+    ctx = mg.Context([_dev(A)], mg.Options(smoother=mg.SMOOTHER_CNN, precision=mg.PREC_FP64))
+    ctx.infer(_net(mg, params))
+    h = ora.Hierarchy(A)
+    for l in range(h.num_levels - 1):
+        h.set_smoother(l, ora.cnn_forward(h.stencil(l), params))
+    f = mg_inputs.rhs_uniform(n, 8)
+    u0 = mg_inputs.random_field((n, n), 9)
+    u = _dev(u0)
+    ctx.vcycle([_dev(f)], [u])
+    ref = u0 + h.vcycle(f - ora.matvec(A, u0), 1, 1)
+    assert np.abs(u.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_cnn_solve_mixed_close_to_oracle(mg):
+    n = 63
+    A = ora.stencil_q1_rotated(n, 0.9, 0.05)
+    params = mg_inputs.cnn_random(12, scale_last=0.02)
+    h = ora.Hierarchy(A)
+    for l in range(h.num_levels - 1):
+        h.set_smoother(l, ora.cnn_forward(h.stencil(l), params))
+    f = mg_inputs.rhs_uniform(n, 0)
+    _, k, hist, conv = h.solve(f, 1e-8, 3000, 1, 1)
+    ctx = mg.Context([_dev(A)], mg.Options(smoother=mg.SMOOTHER_CNN, precision=mg.PREC_MIXED))
+    ctx.infer(_net(mg, params))
+    res = ctx.solve([_dev(f)], 1e-8, 3000)
+    assert conv and res.status[0] == 0
+    assert abs(int(res.iters[0]) - k) <= max(2, 0.1 * k)
+    r = f - ora.matvec(A, res.u[0].cpu().numpy())
+    assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-8

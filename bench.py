@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=30, help="V-cycles in the oracle's timed sample")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--only", choices=["both", "cnn", "jacobi"], default="both",
+                    help="profiling aid: run one smoother only (the JSON line then lacks the comparison)")
     return ap.parse_args()
 
 
@@ -126,7 +128,14 @@ def main():
         total = (time.perf_counter() - t0) * 1e3
         return out, total / args.steps
 
+    if args.only == "jacobi":
+        jac_runs, jac_ms = run(ctx_jac, False)
+        print(json.dumps({"jacobi_iters": int(jac_runs[-1][0].iters[0]), "ms_per_step": jac_ms}), flush=True)
+        return
     cnn_runs, cnn_ms = run(ctx_cnn, True)
+    if args.only == "cnn":
+        print(json.dumps({"cnn_iters": int(cnn_runs[-1][0].iters[0]), "ms_per_step": cnn_ms}), flush=True)
+        return
     jac_runs, jac_ms = run(ctx_jac, False)
     res_c, res_j = cnn_runs[-1][0], jac_runs[-1][0]
     N = n * n

@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "libmgcnn.so")
 OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
-DEVICE_SOURCES = ["stencil.hip", "cycle.hip", "coarse.hip", "cnn.hip", "cnn_mfma.hip", "train_kernels.hip"]
+DEVICE_SOURCES = ["stencil.hip", "cycle.hip", "coarse.hip", "bottom.hip", "fused.hip", "cnn.hip", "cnn_mfma.hip", "train_kernels.hip"]
 HOST_SOURCES = ["abi.cpp", "context.cpp", "net.cpp", "train.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
@@ -26,6 +26,8 @@ def _compile(src: str) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(OBJDIR, src + ".o")
     cmd = ["hipcc", "-c", path, "-o", obj] + COMMON
+    if src.endswith(".cpp"):
+        cmd += ["--offload-host-only"]  # host runtime: no device code in these files
     r = subprocess.run(cmd, capture_output=True, text=True)
     msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:

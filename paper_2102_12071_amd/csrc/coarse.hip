@@ -2,7 +2,7 @@
 // level).  At setup one workgroup assembles the dense matrix of the coarsest
 // stencil (at most 49 x 49), factors it by Cholesky in LDS and forms the
 // explicit inverse column by column; every cycle then applies the inverse as
-// a small dense FP64 product, one workgroup per problem.
+// a small dense FP64 product inside the bottom-levels kernel.
 #include "common.hpp"
 #include "launch.hpp"
 
@@ -70,36 +70,11 @@ __global__ void __launch_bounds__(64) k_coarse_factor(int m, int P, int64_t plan
     if (t == 0 && bad) atomicOr(flag, 8);
 }
 
-template <typename T>
-__global__ void __launch_bounds__(64) k_coarse_solve(const CoarseSlot<T> *slots, const SolveState *state)
-{
-    __shared__ double rl[kN];
-    const CoarseSlot<T> s = slots[blockIdx.x];
-    if (!state[s.prob].active) return;
-    const int mm = s.m * s.m;
-    const int t = threadIdx.x;
-    if (t < mm) rl[t] = (double)s.r[(int64_t)(t / s.m) * s.P + t % s.m];
-    __syncthreads();
-    if (t >= mm) return;
-    double acc = 0.0;
-    for (int q = 0; q < mm; ++q) acc += s.Ainv[(int64_t)t * mm + q] * rl[q];
-    s.e[(int64_t)(t / s.m) * s.P + t % s.m] = (T)acc;
-}
-
 }  // namespace
 
 void launch_coarse_factor(int m, int P, int64_t plane, const double *A, double *Ainv, int *flag, hipStream_t st)
 {
     k_coarse_factor<<<1, 64, 0, st>>>(m, P, plane, A, Ainv, flag);
 }
-
-template <typename T>
-void launch_coarse_solve(const CoarseSlot<T> *slots, int nslots, const SolveState *state, hipStream_t st)
-{
-    k_coarse_solve<T><<<nslots, 64, 0, st>>>(slots, state);
-}
-
-template void launch_coarse_solve<float>(const CoarseSlot<float> *, int, const SolveState *, hipStream_t);
-template void launch_coarse_solve<double>(const CoarseSlot<double> *, int, const SolveState *, hipStream_t);
 
 }  // namespace mg

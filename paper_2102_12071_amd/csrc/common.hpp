@@ -3,6 +3,16 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Pointers held in device-side tables (slot structs) are marked as global
+// memory in the device compilation pass, so that loads through them compile to
+// global (not flat) memory instructions; the host pass sees plain pointers of
+// the same size.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define MG_G __attribute__((address_space(1)))
+#else
+#define MG_G
+#endif
+
 namespace mg {
 
 // ---------------------------------------------------------------- constants
@@ -35,8 +45,10 @@ template <typename T> struct SmootherStore;
 template <> struct SmootherStore<float> { typedef bf16_t type; };
 template <> struct SmootherStore<double> { typedef double type; };
 
-__device__ inline float load_h(const bf16_t *p) { return bf16_to_f32(*p); }
-__device__ inline double load_h(const double *p) { return *p; }
+__device__ inline float h2f(bf16_t v) { return bf16_to_f32(v); }
+__device__ inline double h2f(double v) { return v; }
+template <typename P>
+__device__ inline auto load_h(P p) { return h2f(*p); }
 __device__ inline void store_h(bf16_t *p, float v) { *p = f32_to_bf16(v); }
 __device__ inline void store_h(double *p, double v) { *p = v; }
 
@@ -74,11 +86,15 @@ struct CycleSlot {
     int prob;
     int n, P;
     int64_t plane;
-    const T *A;                                   // 9 planes
-    const typename SmootherStore<T>::type *H;     // 25 planes (H = W / a_C) or null
-    T *r, *e, *s;                                 // level vectors
-    T *rc, *ec;                                   // next coarser level's r and e
+    const T MG_G *A;                                   // 9 planes
+    const typename SmootherStore<T>::type MG_G *H;     // 25 planes (H = W / a_C) or null
+    T MG_G *r;                                         // level vectors
+    T MG_G *e;
+    T MG_G *s;
+    T MG_G *rc;                                        // next coarser level's r and e
+    T MG_G *ec;
     int nc, Pc;
+    double MG_G *u;                                    // finest level only: the fused ascent adds e to u
 };
 
 // Finest level of a problem: FP64 state and the outer residual.
@@ -87,22 +103,35 @@ struct OuterSlot {
     int prob;
     int n, P;
     int64_t plane;
-    const double *A64;  // 9 planes FP64
-    double *u;          // solution, FP64
-    const double *f;    // right-hand side, FP64
-    T *r;               // level-0 inner right-hand side (the residual)
-    const T *e;         // level-0 inner correction
-    double *partial;    // per-block partial sums of squares
+    const double MG_G *A64;  // 9 planes FP64
+    double MG_G *u;          // solution, FP64
+    const double MG_G *f;    // right-hand side, FP64
+    T MG_G *r;               // level-0 inner right-hand side (the residual)
+    const T MG_G *e;         // level-0 inner correction
+    double MG_G *partial;    // per-block partial sums of squares
 };
 
-// Coarsest level: explicit inverse of the (m*m) x (m*m) matrix.
+// Levels with n <= kBottomMax run inside one workgroup per problem (bottom.hip).
+constexpr int kBottomMax = 31;
+constexpr int kMaxBottomLevels = 5;  // 31, 15, 7, 3, 1
+
 template <typename T>
-struct CoarseSlot {
+struct BottomLevel {
+    int n, P;
+    int64_t plane;
+    const T MG_G *A;                                // 9 planes
+    const typename SmootherStore<T>::type MG_G *H;  // 25 planes or null (coarsest)
+};
+
+template <typename T>
+struct BottomSlot {
     int prob;
-    int m, P;
-    const double *Ainv;  // [m*m][m*m] row-major, FP64
-    const T *r;
-    T *e;
+    int nlev;                                  // levels from the top one down to the coarsest
+    BottomLevel<T> lev[kMaxBottomLevels];
+    const double MG_G *Ainv;                   // coarsest inverse
+    const T MG_G *r_in;                        // top level right-hand side (pitch lev[0].P)
+    T MG_G *e_out;                             // top level correction
+    double MG_G *u;                            // when the top level is the finest of a fused cycle: u += e
 };
 
 // Per-problem solver state on the device.

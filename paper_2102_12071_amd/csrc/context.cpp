@@ -49,10 +49,13 @@ mg_status build_slots(mg_ctx_s &c)
     typedef typename SmootherStore<T>::type HT;
     std::map<int, std::vector<CycleSlot<T>>, std::greater<int>> cls;
     std::map<int, std::vector<OuterSlot<T>>, std::greater<int>> out;
-    std::vector<CoarseSlot<T>> coarse;
+    std::vector<BottomSlot<T>> bottom;
+    c.bottom_top_n = 0;
     for (int p = 0; p < c.nprob; ++p) {
         ProbBuf &pb = c.probs[p];
-        for (int l = 0; l + 1 < pb.nlev; ++l) {
+        int top = 0;  // first level handled by the bottom kernel
+        while (pb.lev[top].n > kBottomMax) ++top;
+        for (int l = 0; l < top; ++l) {
             const LevelBuf &L = pb.lev[l], &Lc = pb.lev[l + 1];
             CycleSlot<T> s{};
             s.prob = p;
@@ -68,6 +71,7 @@ mg_status build_slots(mg_ctx_s &c)
             s.ec = (T *)Lc.e;
             s.nc = Lc.n;
             s.Pc = Lc.P;
+            s.u = (c.fused && l == 0) ? pb.u : nullptr;
             cls[L.n].push_back(s);
         }
         const LevelBuf &L0 = pb.lev[0], &Lm = pb.lev[pb.nlev - 1];
@@ -83,14 +87,24 @@ mg_status build_slots(mg_ctx_s &c)
         o.e = (const T *)L0.e;
         o.partial = pb.partial;
         out[L0.n].push_back(o);
-        CoarseSlot<T> cs{};
-        cs.prob = p;
-        cs.m = Lm.n;
-        cs.P = Lm.P;
-        cs.Ainv = pb.Ainv;
-        cs.r = (const T *)Lm.r;
-        cs.e = (T *)Lm.e;
-        coarse.push_back(cs);
+        (void)Lm;
+        BottomSlot<T> b{};
+        b.prob = p;
+        b.nlev = pb.nlev - top;
+        for (int l = top; l < pb.nlev; ++l) {
+            BottomLevel<T> &bl = b.lev[l - top];
+            bl.n = pb.lev[l].n;
+            bl.P = pb.lev[l].P;
+            bl.plane = pb.lev[l].plane;
+            bl.A = stencil_of<T>(pb.lev[l]);
+            bl.H = (const HT *)pb.lev[l].H;
+        }
+        b.Ainv = pb.Ainv;
+        b.r_in = (const T *)pb.lev[top].r;
+        b.e_out = (T *)pb.lev[top].e;
+        b.u = (c.fused && top == 0) ? pb.u : nullptr;
+        bottom.push_back(b);
+        c.bottom_top_n = std::max(c.bottom_top_n, pb.lev[top].n);
     }
     for (auto &kv : cls) {
         SizeClass sc;
@@ -106,16 +120,28 @@ mg_status build_slots(mg_ctx_s &c)
         MG_TRY(upload(c.arena, kv.second, &sc.d_slots));
         c.outer.push_back(sc);
     }
-    MG_TRY(upload(c.arena, coarse, &c.d_coarse));
+    MG_TRY(upload(c.arena, bottom, &c.d_bottom));
+    prepare_bottom<T>();
     return MG_OK;
 }
 
 // One V-cycle e = V(r) on every active problem (Algorithm 1, correction form).
+// V(1,1) runs the fused level kernels (descend, bottom, ascend), which add
+// the finest correction to u themselves; other sweep counts run the
+// step-by-step kernels and leave u += e to enqueue_update.
 template <typename T>
 void enqueue_vcycle(mg_ctx_s &c, hipStream_t st)
 {
     const bool cnn = c.opt.smoother == MG_SMOOTHER_CNN;
     const double w = c.opt.omega;
+    if (c.fused) {
+        for (const SizeClass &k : c.classes)  // descending sizes
+            launch_descend<T>((const CycleSlot<T> *)k.d_slots, k.nslots, k.n, cnn, w, c.d_state, st);
+        launch_bottom<T>((const BottomSlot<T> *)c.d_bottom, c.nprob, c.bottom_top_n, cnn, w, 1, 1, c.d_state, st);
+        for (auto it = c.classes.rbegin(); it != c.classes.rend(); ++it)  // ascending sizes
+            launch_ascend<T>((const CycleSlot<T> *)it->d_slots, it->nslots, it->n, cnn, w, c.d_state, st);
+        return;
+    }
     for (const SizeClass &k : c.classes) {  // descending sizes
         auto *s = (const CycleSlot<T> *)k.d_slots;
         if (c.opt.nu_pre == 0) {
@@ -129,7 +155,8 @@ void enqueue_vcycle(mg_ctx_s &c, hipStream_t st)
         }
         launch_residual_restrict<T>(s, k.nslots, k.n, c.d_state, st);
     }
-    launch_coarse_solve<T>((const CoarseSlot<T> *)c.d_coarse, c.nprob, c.d_state, st);
+    launch_bottom<T>((const BottomSlot<T> *)c.d_bottom, c.nprob, c.bottom_top_n, cnn, w, c.opt.nu_pre, c.opt.nu_post,
+                     c.d_state, st);
     for (auto it = c.classes.rbegin(); it != c.classes.rend(); ++it) {  // ascending sizes
         const SizeClass &k = *it;
         auto *s = (const CycleSlot<T> *)k.d_slots;
@@ -155,16 +182,21 @@ void enqueue_check(mg_ctx_s &c, int init, hipStream_t st)
         launch_check<T>((const OuterSlot<T> *)k.d_slots, k.nslots, c.d_state, c.d_params, init, st);
 }
 
+// u += e where the V-cycle did not do it.
 template <typename T>
 void enqueue_update(mg_ctx_s &c, hipStream_t st)
 {
+    if (c.fused) return;
     for (const SizeClass &k : c.outer) launch_update_u<T>((const OuterSlot<T> *)k.d_slots, k.nslots, k.n, c.d_state, st);
 }
 
-// One solver iteration: residual, stopping rule, V-cycle, update.
+// One solver iteration: residual and stopping rule, V-cycle, update.
 template <typename T>
 void enqueue_iteration(mg_ctx_s &c, hipStream_t st)
 {
+    // (A completion counter shared by every block of the residual kernel, to apply
+    // the rule without this extra launch, serialises thousands of atomics and costs
+    // more than the launch does.)
     enqueue_outer_residual<T>(c, st);
     enqueue_check<T>(c, 0, st);
     enqueue_vcycle<T>(c, st);
@@ -382,6 +414,7 @@ mg_status mg_setup(const mg_problem *probs, int32_t nprob, const mg_options *opt
     MG_TRY(require_device());
     mg_ctx c = new mg_ctx_s();
     c->opt = opt;
+    c->fused = opt.nu_pre == 1 && opt.nu_post == 1;
     c->nprob = nprob;
     mg_status s = setup_impl(*c, probs, (hipStream_t)stream);
     if (s < 0) {

@@ -31,44 +31,38 @@ inline dim3 row_grid(int n, RowTile t, int nslots)
     return dim3((n + t.bx - 1) / t.bx, (n + t.by - 1) / t.by, nslots);
 }
 
-// y = sum_d A[d] x_{p+d} over the 3x3 stencil, skipping nodes outside the grid.
-template <typename S, typename X, typename Acc>
-__device__ inline Acc apply3x3(const S *A, int64_t plane, const X *x, int n, int P, int i, int j)
+// y = sum_d A[d] x_{p+d} over the 3x3 stencil; neighbours off the grid count
+// as zero.  Loads are unconditional (clamped to the node itself) and the value
+// is selected afterwards, so that the compiler can issue them together.
+template <typename PA, typename PX, typename Acc>
+__device__ inline Acc apply3x3(PA A, int64_t plane, PX x, int n, int P, int i, int j)
 {
     const int64_t p = (int64_t)j * P + i;
     Acc acc = 0;
 #pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-        const int jj = j + dy;
-        if (jj < 0 || jj >= n) continue;
-#pragma unroll
-        for (int dx = -1; dx <= 1; ++dx) {
-            const int ii = i + dx;
-            if (ii < 0 || ii >= n) continue;
-            const int c = 3 * (dy + 1) + (dx + 1);
-            acc += (Acc)A[c * plane + p] * (Acc)x[(int64_t)jj * P + ii];
-        }
+    for (int c = 0; c < 9; ++c) {
+        const int ii = i + c % 3 - 1, jj = j + c / 3 - 1;
+        const bool ok = ii >= 0 && ii < n && jj >= 0 && jj < n;
+        const Acc a = (Acc)A[c * plane + p];
+        const Acc xv = (Acc)x[ok ? (int64_t)jj * P + ii : p];
+        acc += a * (ok ? xv : (Acc)0);
     }
     return acc;
 }
 
 // (H x)_p with H stored as 25 planes of H = W / a_C.
-template <typename HT, typename X, typename Acc>
-__device__ inline Acc apply5x5(const HT *H, int64_t plane, const X *x, int n, int P, int i, int j)
+template <typename PH, typename PX, typename Acc>
+__device__ inline Acc apply5x5(PH H, int64_t plane, PX x, int n, int P, int i, int j)
 {
     const int64_t p = (int64_t)j * P + i;
     Acc acc = 0;
 #pragma unroll
-    for (int dy = -2; dy <= 2; ++dy) {
-        const int jj = j + dy;
-        if (jj < 0 || jj >= n) continue;
-#pragma unroll
-        for (int dx = -2; dx <= 2; ++dx) {
-            const int ii = i + dx;
-            if (ii < 0 || ii >= n) continue;
-            const int k = 5 * (dy + 2) + (dx + 2);
-            acc += (Acc)load_h(H + k * plane + p) * (Acc)x[(int64_t)jj * P + ii];
-        }
+    for (int k = 0; k < 25; ++k) {
+        const int ii = i + k % 5 - 2, jj = j + k / 5 - 2;
+        const bool ok = ii >= 0 && ii < n && jj >= 0 && jj < n;
+        const Acc h = (Acc)h2f(H[k * plane + p]);
+        const Acc xv = (Acc)x[ok ? (int64_t)jj * P + ii : p];
+        acc += h * (ok ? xv : (Acc)0);
     }
     return acc;
 }
@@ -84,12 +78,33 @@ __global__ void __launch_bounds__(kThreads) k_outer_residual(const OuterSlot<T> 
     double r = 0.0;
     if (i < s.n && j < s.n) {
         const int64_t p = (int64_t)j * s.P + i;
-        r = s.f[p] - apply3x3<double, double, double>(s.A64, s.plane, s.u, s.n, s.P, i, j);
+        r = s.f[p] - apply3x3<decltype(s.A64), decltype(s.u), double>(s.A64, s.plane, s.u, s.n, s.P, i, j);
         s.r[p] = (T)r;
     }
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
     const double sum = block_sum<kThreads>(r * r, red);
     if (tid == 0) s.partial[blockIdx.y * gridDim.x + blockIdx.x] = sum;
+}
+
+// The stopping rule of the solver (section 6.1) for one problem, given
+// rr = ||f - A u||^2; called by one thread.
+__device__ inline void stopping_rule(SolveState &st, double rr, const SolveParams *prm, int prob)
+{
+    const double rel = st.fnorm > 0.0 ? sqrt(rr) / st.fnorm : 0.0;
+    st.relres = rel;
+    if (prm->history) prm->history[(int64_t)prob * prm->hist_stride + st.iters] = rel;
+    if (rel <= prm->tol) {
+        st.active = 0;
+        st.status = 0;
+    } else if (!isfinite(rel) || rel > 1e3) {
+        st.active = 0;
+        st.status = -4;
+    } else if (st.iters >= prm->maxit) {
+        st.active = 0;
+        st.status = 1;
+    } else {
+        st.iters += 1;
+    }
 }
 
 // One block per slot.  init = 1: the partial sums are ||f||^2 (u = 0); set up
@@ -114,21 +129,7 @@ __global__ void __launch_bounds__(kThreads)
         st.relres = 1.0;
         return;
     }
-    const double rel = st.fnorm > 0.0 ? sqrt(rr) / st.fnorm : 0.0;
-    st.relres = rel;
-    if (prm->history) prm->history[(int64_t)s.prob * prm->hist_stride + st.iters] = rel;
-    if (rel <= prm->tol) {
-        st.active = 0;
-        st.status = 0;
-    } else if (!isfinite(rel) || rel > 1e3) {
-        st.active = 0;
-        st.status = -4;
-    } else if (st.iters >= prm->maxit) {
-        st.active = 0;
-        st.status = 1;
-    } else {
-        st.iters += 1;
-    }
+    stopping_rule(st, rr, prm, s.prob);
 }
 
 template <typename T>
@@ -155,7 +156,7 @@ __global__ void __launch_bounds__(kThreads) k_smooth_first(const CycleSlot<T> *s
     const int64_t p = (int64_t)j * s.P + i;
     T v;
     if (CNN)
-        v = apply5x5<typename SmootherStore<T>::type, T, T>(s.H, s.plane, s.r, s.n, s.P, i, j);
+        v = apply5x5<decltype(s.H), decltype(s.r), T>(s.H, s.plane, s.r, s.n, s.P, i, j);
     else
         v = omega * s.r[p] / s.A[kCentre * s.plane + p];
     s.e[p] = v;
@@ -170,7 +171,7 @@ __global__ void __launch_bounds__(kThreads) k_residual(const CycleSlot<T> *slots
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= s.n || j >= s.n) return;
     const int64_t p = (int64_t)j * s.P + i;
-    s.s[p] = s.r[p] - apply3x3<T, T, T>(s.A, s.plane, s.e, s.n, s.P, i, j);
+    s.s[p] = s.r[p] - apply3x3<decltype(s.A), decltype(s.e), T>(s.A, s.plane, s.e, s.n, s.P, i, j);
 }
 
 // e += M^{-1} s (s = r - A e from k_residual).
@@ -185,7 +186,7 @@ __global__ void __launch_bounds__(kThreads) k_smooth_apply(const CycleSlot<T> *s
     const int64_t p = (int64_t)j * s.P + i;
     T v;
     if (CNN)
-        v = apply5x5<typename SmootherStore<T>::type, T, T>(s.H, s.plane, s.s, s.n, s.P, i, j);
+        v = apply5x5<decltype(s.H), decltype(s.s), T>(s.H, s.plane, s.s, s.n, s.P, i, j);
     else
         v = omega * s.s[p] / s.A[kCentre * s.plane + p];
     s.e[p] += v;
@@ -210,7 +211,7 @@ __global__ void __launch_bounds__(kThreads) k_residual_restrict(const CycleSlot<
         T v = 0;
         if (fx < s.n && fy < s.n) {
             const int64_t p = (int64_t)fy * s.P + fx;
-            v = s.r[p] - apply3x3<T, T, T>(s.A, s.plane, s.e, s.n, s.P, fx, fy);
+            v = s.r[p] - apply3x3<decltype(s.A), decltype(s.e), T>(s.A, s.plane, s.e, s.n, s.P, fx, fy);
         }
         sres[q / kRfX][q % kRfX] = v;
     }
@@ -235,21 +236,19 @@ __global__ void __launch_bounds__(kThreads) k_prolong(const CycleSlot<T> *slots,
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int j = blockIdx.y * blockDim.y + threadIdx.y;
     if (i >= s.n || j >= s.n) return;
-    int Ix[2], Jy[2];
-    T wx[2], wy[2];
-    int nx, ny;
-    if (i & 1) { Ix[0] = (i - 1) >> 1; wx[0] = 1; nx = 1; }
-    else { Ix[0] = (i >> 1) - 1; Ix[1] = i >> 1; wx[0] = wx[1] = (T)0.5; nx = 2; }
-    if (j & 1) { Jy[0] = (j - 1) >> 1; wy[0] = 1; ny = 1; }
-    else { Jy[0] = (j >> 1) - 1; Jy[1] = j >> 1; wy[0] = wy[1] = (T)0.5; ny = 2; }
-    T acc = 0;
-    for (int b = 0; b < ny; ++b) {
-        if (Jy[b] < 0 || Jy[b] >= s.nc) continue;
-        for (int a = 0; a < nx; ++a) {
-            if (Ix[a] < 0 || Ix[a] >= s.nc) continue;
-            acc += wx[a] * wy[b] * s.ec[(int64_t)Jy[b] * s.Pc + Ix[a]];
-        }
-    }
+    // coarse neighbours: one on odd coordinates, two (weights 1/2) on even ones
+    const int ia = (i & 1) ? (i - 1) >> 1 : (i >> 1) - 1, ib = (i & 1) ? ia : ia + 1;
+    const int ja = (j & 1) ? (j - 1) >> 1 : (j >> 1) - 1, jb = (j & 1) ? ja : ja + 1;
+    const T wx = (i & 1) ? (T)1 : (T)0.5, wy = (j & 1) ? (T)1 : (T)0.5;
+    const bool oka = ia >= 0, okb = ib < s.nc, okj = ja >= 0, okk = jb < s.nc;
+    const T c00 = s.ec[(okj && oka) ? (int64_t)ja * s.Pc + ia : 0];
+    const T c01 = s.ec[(okj && okb) ? (int64_t)ja * s.Pc + ib : 0];
+    const T c10 = s.ec[(okk && oka) ? (int64_t)jb * s.Pc + ia : 0];
+    const T c11 = s.ec[(okk && okb) ? (int64_t)jb * s.Pc + ib : 0];
+    const bool two_x = !(i & 1), two_y = !(j & 1);
+    T acc = (okj && oka ? c00 : (T)0) + (two_x && okj && okb ? c01 : (T)0) + (two_y && okk && oka ? c10 : (T)0) +
+            (two_x && two_y && okk && okb ? c11 : (T)0);
+    acc *= wx * wy;
     s.e[(int64_t)j * s.P + i] += acc;
 }
 

@@ -104,13 +104,15 @@ struct mg_ctx_s {
     std::vector<mg::ProbBuf> probs;
     std::vector<mg::SizeClass> classes;  // levels above the coarsest, n descending
     std::vector<mg::SizeClass> outer;    // finest levels, by n
-    void *d_coarse = nullptr;            // CoarseSlot<T>[nprob]
+    void *d_bottom = nullptr;            // BottomSlot<T>[nprob]
+    int bottom_top_n = 0;                // largest top level of the bottom kernel
     mg::SolveState *d_state = nullptr;
     mg::SolveParams *d_params = nullptr;
     int *d_flag = nullptr;
     double *d_history = nullptr;
     size_t history_cap = 0;              // doubles
     bool smoother_ready = false;
+    bool fused = false;                  // V(1,1): fused level kernels
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     hipEvent_t t0 = nullptr, t1 = nullptr;

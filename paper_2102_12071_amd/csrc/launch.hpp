@@ -15,10 +15,16 @@ void launch_copy_field(int n, int nch, const double *src, int Ps, int64_t planes
 void launch_to_f32(int64_t count, const double *src, float *dst, hipStream_t st);
 void launch_validate(int n, int P, int64_t plane, const double *A, int *flag, hipStream_t st);
 
-// ---- coarse.hip: coarsest-level factorisation and solve ----
+// ---- coarse.hip: coarsest-level factorisation (explicit inverse) ----
 void launch_coarse_factor(int m, int P, int64_t plane, const double *A, double *Ainv, int *flag, hipStream_t st);
+
+// ---- fused.hip: one launch per level and direction for V(1,1) ----
 template <typename T>
-void launch_coarse_solve(const CoarseSlot<T> *slots, int nslots, const SolveState *state, hipStream_t st);
+void launch_descend(const CycleSlot<T> *slots, int nslots, int n, bool cnn, double omega, const SolveState *state,
+                    hipStream_t st);
+template <typename T>
+void launch_ascend(const CycleSlot<T> *slots, int nslots, int n, bool cnn, double omega, const SolveState *state,
+                   hipStream_t st);
 
 // ---- cycle.hip: V-cycle kernels (T = float: mixed precision; double: FP64) ----
 // Every launcher covers one size class (all slots share n); blocks of
@@ -51,6 +57,15 @@ template <typename T>
 void launch_prolong(const CycleSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st);
 template <typename T>
 void launch_zero_e(const CycleSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st);
+
+// ---- bottom.hip: all levels with n <= kBottomMax, one workgroup per problem ----
+template <typename T>
+size_t bottom_smem_bytes(int top_n);
+template <typename T>
+void launch_bottom(const BottomSlot<T> *slots, int nslots, int top_n, bool cnn, double omega, int nu1, int nu2,
+                   const SolveState *state, hipStream_t st);
+template <typename T>
+void prepare_bottom();
 
 // ---- cnn.hip: smoother inference ----
 // Direct (VALU) 3x3 convolution layer, "same" zero padding; planes of pitch P.

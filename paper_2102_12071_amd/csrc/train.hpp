@@ -9,15 +9,16 @@ struct TrainProb {
     int index;        // position in the batch
     int n;
     int64_t plane;    // n * n
-    const double *A;  // stencil [9][n][n] FP64 (caller's)
-    const float *V;   // HF vectors [J][n][n] (caller's)
-    float *x0;        // network input [9][plane]
-    float *act;       // post-ReLU activations of layers 1..3, [3][32][plane]
-    float *y;         // last-layer output [25][plane]
-    float *Av;        // [J][plane]
-    float *g;         // v - H A v, [J][plane]
-    float *gnorm;     // [J]
-    float *dA, *dB;   // gradient ping-pong buffers, [32][plane] each
+    const double MG_G *A;  // stencil [9][n][n] FP64 (caller's)
+    const float MG_G *V;   // HF vectors [J][n][n] (caller's)
+    float MG_G *x0;        // network input [9][plane]
+    float MG_G *act;       // post-ReLU activations of layers 1..3, [3][32][plane]
+    float MG_G *y;         // last-layer output [25][plane]
+    float MG_G *Av;        // [J][plane]
+    float MG_G *g;         // v - H A v, [J][plane]
+    float MG_G *gnorm;     // [J]
+    float MG_G *dA;        // gradient ping-pong buffers, [32][plane] each
+    float MG_G *dB;
 };
 
 // Offsets of one layer's weights and bias in the flat parameter vector.

@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(kT) k_tr_input(const TrainProb *probs)
     for (int c = 0; c < 9; ++c) P.x0[c * P.plane + p] = (float)(P.A[c * P.plane + p] / ac);
 }
 
-__device__ inline const float *layer_input(const TrainProb &P, int l)
+__device__ inline const float MG_G *layer_input(const TrainProb &P, int l)
 {
     return l == 0 ? P.x0 : P.act + (int64_t)(l - 1) * 32 * P.plane;
 }
@@ -41,11 +41,11 @@ __global__ void __launch_bounds__(kT) k_tr_conv_fwd(const TrainProb *probs, cons
     const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (p >= P.plane) return;
     const int n = P.n, i = (int)(p % n), j = (int)(p / n);
-    const float *in = layer_input(P, layer);
+    const float MG_G *in = layer_input(P, layer);
     const float *w = params + L.woff + (int64_t)co * L.cin * 9;
     float acc = params[L.boff + co];
     for (int ci = 0; ci < L.cin; ++ci) {
-        const float *x = in + (int64_t)ci * P.plane;
+        const float MG_G *x = in + (int64_t)ci * P.plane;
         const float *wk = w + ci * 9;
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
@@ -69,7 +69,7 @@ __global__ void __launch_bounds__(kT) k_tr_av(const TrainProb *probs, int J)
     const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (p >= P.plane) return;
     const int n = P.n, i = (int)(p % n), j = (int)(p / n);
-    const float *v = P.V + (int64_t)jv * P.plane;
+    const float MG_G *v = P.V + (int64_t)jv * P.plane;
     float acc = 0.0f;
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
@@ -87,9 +87,9 @@ __global__ void __launch_bounds__(kT) k_tr_residual_norm(const TrainProb *probs,
     const TrainProb &P = probs[blockIdx.x / J];
     const int jv = blockIdx.x % J;
     const int n = P.n;
-    const float *Av = P.Av + (int64_t)jv * P.plane;
-    const float *v = P.V + (int64_t)jv * P.plane;
-    float *g = P.g + (int64_t)jv * P.plane;
+    const float MG_G *Av = P.Av + (int64_t)jv * P.plane;
+    const float MG_G *v = P.V + (int64_t)jv * P.plane;
+    float MG_G *g = P.g + (int64_t)jv * P.plane;
     double acc2 = 0.0;
     for (int64_t p = threadIdx.x; p < P.plane; p += kT) {
         const int i = (int)(p % n), j = (int)(p / n);
@@ -128,7 +128,7 @@ __global__ void __launch_bounds__(kT) k_tr_dout(const TrainProb *probs, int J, f
         const float gn = P.gnorm[jv];
         if (gn == 0.0f) continue;
         const float c = -scale * P.g[(int64_t)jv * P.plane + p] / gn * inv_ac;
-        const float *Av = P.Av + (int64_t)jv * P.plane;
+        const float MG_G *Av = P.Av + (int64_t)jv * P.plane;
 #pragma unroll
         for (int k = 0; k < 25; ++k) {
             const int ii = i + k % 5 - 2, jj = j + k / 5 - 2;
@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(kT) k_tr_dout(const TrainProb *probs, int J, f
     for (int k = 0; k < 25; ++k) P.dA[(int64_t)k * P.plane + p] = acc[k];
 }
 
-__device__ inline float *dpre_buf(const TrainProb &P, int layer) { return (layer & 1) ? P.dA : P.dB; }
+__device__ inline float MG_G *dpre_buf(const TrainProb &P, int layer) { return (layer & 1) ? P.dA : P.dB; }
 
 // dX[ci](q) = sum_co sum_tap w[co][ci][tap] dPre[co](q - tap + 1), masked by the
 // previous layer's ReLU (act > 0).  grid.z = problem * cin + ci.
@@ -151,11 +151,11 @@ __global__ void __launch_bounds__(kT) k_tr_conv_bwd_data(const TrainProb *probs,
     const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (q >= P.plane) return;
     const int n = P.n, i = (int)(q % n), j = (int)(q / n);
-    const float *dp = (layer == 3) ? P.dA : dpre_buf(P, layer);
+    const float MG_G *dp = (layer == 3) ? P.dA : dpre_buf(P, layer);
     float acc = 0.0f;
     for (int co = 0; co < L.cout; ++co) {
         const float *w = params + L.woff + ((int64_t)co * L.cin + ci) * 9;
-        const float *d = dp + (int64_t)co * P.plane;
+        const float MG_G *d = dp + (int64_t)co * P.plane;
 #pragma unroll
         for (int t = 0; t < 9; ++t) {
             const int ii = i - (t % 3 - 1), jj = j - (t / 3 - 1);  // output node that read q through tap t
@@ -163,7 +163,7 @@ __global__ void __launch_bounds__(kT) k_tr_conv_bwd_data(const TrainProb *probs,
         }
     }
     const float a = P.act[((int64_t)(layer - 1) * 32 + ci) * P.plane + q];
-    float *out = dpre_buf(P, layer - 1);
+    float MG_G *out = dpre_buf(P, layer - 1);
     out[(int64_t)ci * P.plane + q] = a > 0.0f ? acc : 0.0f;
 }
 
@@ -179,8 +179,8 @@ __global__ void __launch_bounds__(kT) k_tr_conv_bwd_weight(const TrainProb *prob
     __shared__ float ds[32][kMaxRow];         // dPre row j
     const TrainProb &P = probs[blockIdx.z];
     const int n = P.n;
-    const float *X = layer_input(P, layer);
-    const float *dp = (layer == 3) ? P.dA : dpre_buf(P, layer);
+    const float MG_G *X = layer_input(P, layer);
+    const float MG_G *dp = (layer == 3) ? P.dA : dpre_buf(P, layer);
     const int t = threadIdx.x;
     const int groups = kT / L.cin;
     const int ci = t % L.cin, g0 = t / L.cin;

@@ -159,14 +159,16 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
 /* Time of the last mg_solve's device work in milliseconds (HIP events). */
 mg_status mg_last_solve_ms(mg_ctx ctx, double *ms);
 
-/* Kernel timing for roofline reports: launches each kernel of one solver
- * iteration on the finest level of problem 0 (the whole size class of that
- * level), reps times back to back between HIP events on the library's
- * stream, and writes the mean duration per launch in milliseconds to
- * ms[0 .. MG_NUM_TIMED_KERNELS-1] (kernel k is named by mg_kernel_name(k)).
+/* Kernel timing for roofline reports: launches each solver kernel on the
+ * finest level of problem 0 (the whole size class of that level; the bottom-
+ * levels kernel on every problem), reps times back to back between HIP events
+ * on the library's stream, and writes the mean duration per launch in
+ * milliseconds to ms[0 .. MG_NUM_TIMED_KERNELS-1] (kernel k is named by
+ * mg_kernel_name(k)).  V(1,1) solves use outer_residual, check, descend,
+ * ascend and bottom; other sweep counts use the step-by-step kernels.
  * Leaves the context's vectors undefined (the next mg_solve resets them).
  * Synchronises. */
-#define MG_NUM_TIMED_KERNELS 7
+#define MG_NUM_TIMED_KERNELS 11
 mg_status mg_time_kernels(mg_ctx ctx, int32_t reps, double *ms);
 const char *mg_kernel_name(int32_t k);
 

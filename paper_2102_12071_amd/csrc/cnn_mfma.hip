@@ -1,0 +1,203 @@
+// Smoother inference on the matrix cores (paper section 4.2: the network maps
+// the field of operator stencils to per-point smoothing kernels), all four
+// layers of 3x3 convolutions (9 -> 32 -> 32 -> 32 -> 25) in one kernel.
+//
+// Each workgroup produces a kTO x kTO tile of smoother stencils.  It reads
+// the stencil field on the tile plus a halo of four nodes (one per layer),
+// forms the network input x0 = A / a_C, and runs the layers on shrinking
+// regions (tile + 6, + 4, + 2, + 0), keeping the activations in LDS in BF16,
+// channel-last (pixel-major, 32 channels per pixel).  Each layer is an
+// implicit GEMM: M = pixels, N = output channels, K = (tap, input channel),
+// on v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  The first layer's nine
+// input channels are padded to sixteen, so one K step of 32 covers two taps.
+// Activations at nodes outside the grid are set to zero after every layer:
+// this is the per-layer zero padding of "same" convolutions.  The last layer
+// writes H = (omega*delta_0 + y) / a_C in BF16.
+//
+// MFMA operand layout used (16x16x32, wave of 64): lane l supplies
+// A[m = l % 16][k = 8 (l / 16) + e] and B[k = 8 (l / 16) + e][n = l % 16],
+// e = 0..7, and receives C[m = 4 (l / 16) + i][n = l % 16], i = 0..3.
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace mg {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTO = 16;                       // output tile side
+constexpr int kT = 256;                       // 4 waves
+constexpr int kR0 = kTO + 8, kR1 = kTO + 6, kR2 = kTO + 4, kR3 = kTO + 2;
+constexpr int kCS0 = 16, kCS = 32;            // channel strides (bf16) of the input and hidden buffers
+constexpr int kSteps[4] = {5, 9, 9, 9};       // K steps of 32 per layer
+// packed B fragments: [layer][step][n-block][lane][8] bf16
+constexpr int kPackOff[5] = {0, 5 * 2 * 64 * 8, 14 * 2 * 64 * 8, 23 * 2 * 64 * 8, 32 * 2 * 64 * 8};
+constexpr int kPackElems = kPackOff[4];
+constexpr int kBufX = (kR2 * kR2 * kCS > kR0 * kR0 * kCS0) ? kR2 * kR2 * kCS : kR0 * kR0 * kCS0;
+constexpr int kBufY = kR1 * kR1 * kCS;
+static_assert(kTO * kTO * 25 * 2 <= kBufX, "the output staging (FP32) must fit in buffer X");
+
+struct PackedNet {
+    bf16_t w[kPackElems];
+    float bias[4][32];
+};
+
+// One layer: out(region Wo x Wo, origin (gy0, gx0)) = conv(in(region Wo+2)).
+template <int STEPS, bool FIRST, bool LAST>
+__device__ inline void conv_layer(const bf16_t *in, int CSin, int Wo, bf16_t *out_bf, float *out_f, int gy0, int gx0,
+                                  int n, const PackedNet MG_G *pk, int layer)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int Wi = Wo + 2;
+    bf16x8 bw[STEPS][2];
+    const bf16_t MG_G *wl = pk->w + kPackOff[layer];
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) bw[s][nb] = *(const bf16x8 MG_G *)(wl + ((s * 2 + nb) * 64 + lane) * 8);
+    const float b0 = pk->bias[layer][lane % 16], b1 = pk->bias[layer][16 + lane % 16];
+    const int P = Wo * Wo, MB = (P + 15) / 16;
+    const int g = lane >> 4;
+    for (int mb = wave; mb < MB; mb += kT / 64) {
+        int pa = mb * 16 + (lane & 15);
+        pa = pa < P ? pa : P - 1;
+        const int oy = pa / Wo, ox = pa - oy * Wo;
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            int tap, cg;
+            if (FIRST) {
+                tap = 2 * s + (g >> 1);
+                cg = g & 1;
+            } else {
+                tap = s;
+                cg = g;
+            }
+            bf16x8 a;
+            if (FIRST && tap > 8) {
+                a = bf16x8{};
+            } else {
+                const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+                a = *(const bf16x8 *)(in + ((oy + ky) * Wi + ox + kx) * CSin + cg * 8);
+            }
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[s][0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[s][1], acc1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int pix = mb * 16 + 4 * g + i;
+            if (pix >= P) continue;
+            const int py = pix / Wo, px = pix - py * Wo;
+            const int gy = gy0 + py, gx = gx0 + px;
+            const bool in_grid = gy >= 0 && gy < n && gx >= 0 && gx < n;
+            float v0 = acc0[i] + b0, v1 = acc1[i] + b1;
+            if (LAST) {
+                // staging [pixel][25] in FP32
+                const int co0 = lane & 15, co1 = 16 + (lane & 15);
+                out_f[pix * 25 + co0] = v0;
+                if (co1 < 25) out_f[pix * 25 + co1] = v1;
+            } else {
+                v0 = (in_grid && v0 > 0.f) ? v0 : 0.f;  // ReLU and zero padding off the grid
+                v1 = (in_grid && v1 > 0.f) ? v1 : 0.f;
+                out_bf[pix * kCS + (lane & 15)] = f32_to_bf16(v0);
+                out_bf[pix * kCS + 16 + (lane & 15)] = f32_to_bf16(v1);
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(kT) k_cnn_fused(int n, int P, int64_t plane, const float *A32, const PackedNet *pkg,
+                                                  float omega, bf16_t *H)
+{
+    __shared__ __align__(16) bf16_t bufX[kBufX];
+    __shared__ __align__(16) bf16_t bufY[kBufY];
+    const PackedNet MG_G *pk = (const PackedNet MG_G *)pkg;
+    const int X0 = blockIdx.x * kTO, Y0 = blockIdx.y * kTO;
+    const int tid = threadIdx.x;
+    // network input x0 = A / a_C on the tile plus a halo of four (zero off the grid)
+    for (int q = tid; q < kR0 * kR0; q += kT) {
+        const int gy = Y0 - 4 + q / kR0, gx = X0 - 4 + q % kR0;
+        const bool ok = gy >= 0 && gy < n && gx >= 0 && gx < n;
+        const int64_t p = ok ? (int64_t)gy * P + gx : 0;
+        float a[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) a[c] = A32[c * plane + p];
+        const float inv = 1.0f / a[kCentre];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) bufX[q * kCS0 + c] = f32_to_bf16((ok && c < 9) ? a[c < 9 ? c : 0] * inv : 0.0f);
+    }
+    __syncthreads();
+    conv_layer<5, true, false>(bufX, kCS0, kR1, bufY, nullptr, Y0 - 3, X0 - 3, n, pk, 0);
+    __syncthreads();
+    conv_layer<9, false, false>(bufY, kCS, kR2, bufX, nullptr, Y0 - 2, X0 - 2, n, pk, 1);
+    __syncthreads();
+    conv_layer<9, false, false>(bufX, kCS, kR3, bufY, nullptr, Y0 - 1, X0 - 1, n, pk, 2);
+    __syncthreads();
+    float *stage = (float *)bufX;
+    conv_layer<9, false, true>(bufY, kCS, kTO, nullptr, stage, Y0, X0, n, pk, 3);
+    __syncthreads();
+    // H = (omega * delta_0 + y) / a_C, plane by plane
+    for (int q = tid; q < kTO * kTO; q += kT) {
+        const int gy = Y0 + q / kTO, gx = X0 + q % kTO;
+        if (gy >= n || gx >= n) continue;
+        const int64_t p = (int64_t)gy * P + gx;
+        const float inv = 1.0f / A32[kCentre * plane + p];
+#pragma unroll
+        for (int k = 0; k < 25; ++k) H[k * plane + p] = f32_to_bf16((stage[q * 25 + k] + (k == 12 ? omega : 0.f)) * inv);
+    }
+}
+
+// Packs FP32 weights [Cout][Cin][3][3] + bias per layer into the per-lane
+// B fragments and padded biases used by k_cnn_fused.
+__global__ void k_pack(const float *params, PackedNet *pk)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ch[5] = {9, 32, 32, 32, 25};
+    if (idx < kPackElems) {
+        int l = 0;
+        while (idx >= kPackOff[l + 1]) ++l;
+        int64_t woff = 0;
+        for (int q = 0; q < l; ++q) woff += (int64_t)ch[q + 1] * ch[q] * 9 + ch[q + 1];
+        const int cin = ch[l], cout = ch[l + 1];
+        const int r = idx - kPackOff[l];
+        const int e = r & 7, lane = (r >> 3) & 63, nb = (r >> 9) & 1, s = r >> 10;
+        const int co = nb * 16 + (lane & 15), g = lane >> 4;
+        int tap, ci;
+        if (l == 0) {
+            tap = 2 * s + (g >> 1);
+            ci = 8 * (g & 1) + e;
+        } else {
+            tap = s;
+            ci = 8 * g + e;
+        }
+        const bool ok = tap < 9 && ci < cin && co < cout;
+        pk->w[idx] = f32_to_bf16(ok ? params[woff + ((int64_t)co * cin + ci) * 9 + tap] : 0.0f);
+    }
+    if (idx < 128) {
+        const int l = idx / 32, co = idx % 32;
+        int64_t woff = 0;
+        for (int q = 0; q < l; ++q) woff += (int64_t)ch[q + 1] * ch[q] * 9 + ch[q + 1];
+        const int64_t boff = woff + (int64_t)ch[l + 1] * ch[l] * 9;
+        pk->bias[l][co] = co < ch[l + 1] ? params[boff + co] : 0.0f;
+    }
+}
+
+}  // namespace
+
+size_t packed_net_bytes() { return sizeof(PackedNet); }
+
+void launch_pack_weights_mfma(const float *params, void *packed, hipStream_t st)
+{
+    k_pack<<<(kPackElems + 255) / 256, 256, 0, st>>>(params, (PackedNet *)packed);
+}
+
+void launch_cnn_fused_mfma(int n, int P, int64_t plane, const float *A32, const void *packed, double omega, bf16_t *H,
+                           hipStream_t st)
+{
+    const dim3 g((n + kTO - 1) / kTO, (n + kTO - 1) / kTO);
+    k_cnn_fused<<<g, kT, 0, st>>>(n, P, plane, A32, (const PackedNet *)packed, (float)omega, H);
+}
+
+}  // namespace mg

@@ -624,12 +624,46 @@ mg_status mg_restencil(mg_ctx ctx, const mg_problem *probs)
 
 const char *mg_kernel_name(int32_t k)
 {
-    static const char *names[MG_NUM_TIMED_KERNELS] = {"outer_residual", "smooth_first", "residual_restrict",
-                                                      "prolong", "residual", "smooth_apply", "update_u"};
+    static const char *names[MG_NUM_TIMED_KERNELS] = {
+        "outer_residual", "check",    "descend",      "ascend",       "bottom",  "smooth_first",
+        "residual_restrict", "prolong", "residual", "smooth_apply", "update_u"};
     return (k >= 0 && k < MG_NUM_TIMED_KERNELS) ? names[k] : "";
 }
 
-mg_status mg_time_kernels(mg_ctx ctx, int32_t reps, double *ms)
+}  // extern "C"
+
+namespace {
+
+// Launches timed kernel k on the finest level's size class of problem 0.
+template <typename T>
+void launch_timed(mg_ctx_s &c, int k, const SizeClass &cls, const SizeClass &oc, hipStream_t st)
+{
+    auto *s = (const CycleSlot<T> *)cls.d_slots;
+    auto *o = (const OuterSlot<T> *)oc.d_slots;
+    const bool cnn = c.opt.smoother == MG_SMOOTHER_CNN;
+    const double w = c.opt.omega;
+    const int n = cls.n;
+    switch (k) {
+    case 0: launch_outer_residual<T>(o, oc.nslots, n, c.d_state, st); break;
+    case 1: launch_check<T>(o, oc.nslots, c.d_state, c.d_params, 1, st); break;
+    case 2: launch_descend<T>(s, cls.nslots, n, cnn, w, c.d_state, st); break;
+    case 3: launch_ascend<T>(s, cls.nslots, n, cnn, w, c.d_state, st); break;
+    case 4:
+        launch_bottom<T>((const BottomSlot<T> *)c.d_bottom, c.nprob, c.bottom_top_n, cnn, w, c.opt.nu_pre,
+                         c.opt.nu_post, c.d_state, st);
+        break;
+    case 5: launch_smooth_first<T>(s, cls.nslots, n, cnn, w, c.d_state, st); break;
+    case 6: launch_residual_restrict<T>(s, cls.nslots, n, c.d_state, st); break;
+    case 7: launch_prolong<T>(s, cls.nslots, n, c.d_state, st); break;
+    case 8: launch_residual<T>(s, cls.nslots, n, c.d_state, st); break;
+    case 9: launch_smooth_apply<T>(s, cls.nslots, n, cnn, w, c.d_state, st); break;
+    default: launch_update_u<T>(o, oc.nslots, n, c.d_state, st); break;
+    }
+}
+
+}  // namespace
+
+extern "C" mg_status mg_time_kernels(mg_ctx ctx, int32_t reps, double *ms)
 {
     clear_error();
     MG_TRY(check_ctx(ctx));
@@ -643,40 +677,17 @@ mg_status mg_time_kernels(mg_ctx ctx, int32_t reps, double *ms)
         if (k.n == n0) cls = &k;
     for (const SizeClass &k : c.outer)
         if (k.n == n0) oc = &k;
-    if (!cls || !oc) return set_error(MG_ERR_STATE, "problem 0 has no smoothed level");
+    if (!cls || !oc) return set_error(MG_ERR_STATE, "problem 0 has no level above the bottom kernel's");
     MG_TRY(c.join.enter());
     hipStream_t st = c.join.internal;
     launch_activate(c.d_state, c.nprob, st);
-    const bool cnn = c.opt.smoother == MG_SMOOTHER_CNN;
-    const double w = c.opt.omega;
     for (int k = 0; k < MG_NUM_TIMED_KERNELS; ++k) {
         MG_HIP(hipEventRecord(c.t0, st));
         for (int q = 0; q < reps; ++q) {
-            if (c.opt.precision == MG_PREC_FP64) {
-                auto *s = (const CycleSlot<double> *)cls->d_slots;
-                auto *o = (const OuterSlot<double> *)oc->d_slots;
-                switch (k) {
-                case 0: launch_outer_residual<double>(o, oc->nslots, n0, c.d_state, st); break;
-                case 1: launch_smooth_first<double>(s, cls->nslots, n0, cnn, w, c.d_state, st); break;
-                case 2: launch_residual_restrict<double>(s, cls->nslots, n0, c.d_state, st); break;
-                case 3: launch_prolong<double>(s, cls->nslots, n0, c.d_state, st); break;
-                case 4: launch_residual<double>(s, cls->nslots, n0, c.d_state, st); break;
-                case 5: launch_smooth_apply<double>(s, cls->nslots, n0, cnn, w, c.d_state, st); break;
-                default: launch_update_u<double>(o, oc->nslots, n0, c.d_state, st); break;
-                }
-            } else {
-                auto *s = (const CycleSlot<float> *)cls->d_slots;
-                auto *o = (const OuterSlot<float> *)oc->d_slots;
-                switch (k) {
-                case 0: launch_outer_residual<float>(o, oc->nslots, n0, c.d_state, st); break;
-                case 1: launch_smooth_first<float>(s, cls->nslots, n0, cnn, w, c.d_state, st); break;
-                case 2: launch_residual_restrict<float>(s, cls->nslots, n0, c.d_state, st); break;
-                case 3: launch_prolong<float>(s, cls->nslots, n0, c.d_state, st); break;
-                case 4: launch_residual<float>(s, cls->nslots, n0, c.d_state, st); break;
-                case 5: launch_smooth_apply<float>(s, cls->nslots, n0, cnn, w, c.d_state, st); break;
-                default: launch_update_u<float>(o, oc->nslots, n0, c.d_state, st); break;
-                }
-            }
+            if (c.opt.precision == MG_PREC_FP64)
+                launch_timed<double>(c, k, *cls, *oc, st);
+            else
+                launch_timed<float>(c, k, *cls, *oc, st);
         }
         MG_HIP(hipEventRecord(c.t1, st));
         MG_HIP(hipEventSynchronize(c.t1));
@@ -688,6 +699,7 @@ mg_status mg_time_kernels(mg_ctx ctx, int32_t reps, double *ms)
     return c.join.leave();
 }
 
+extern "C" {
 }  // extern "C"
 
 // ---------------------------------------------------------------- inference
@@ -731,28 +743,35 @@ extern "C" mg_status mg_smoother_infer(mg_ctx ctx, mg_net net)
     if (!net) return set_error(MG_ERR_ARG, "net is null");
     mg_ctx_s &c = *ctx;
     const bool fp64 = c.opt.precision == MG_PREC_FP64;
-    // scratch: input (9) + two ping-pong activation buffers (32 each) on the largest level
-    int64_t vmax = 0;
-    for (const ProbBuf &pb : c.probs) vmax = std::max<int64_t>(vmax, pb.lev[0].plane);
-    const size_t need = (size_t)vmax * (9 + 32 + 32) * (fp64 ? sizeof(double) : sizeof(float));
-    if (need > c.cnn_scratch_bytes) {
-        MG_TRY(c.arena.alloc(&c.cnn_scratch, need));
-        c.cnn_scratch_bytes = need;
+    // FP64 (direct path) scratch: input (9) + two ping-pong activation buffers (32 each) on the
+    // largest level; the fused MFMA path keeps its activations in LDS
+    if (fp64) {
+        int64_t vmax = 0;
+        for (const ProbBuf &pb : c.probs) vmax = std::max<int64_t>(vmax, pb.lev[0].plane);
+        const size_t need = (size_t)vmax * (9 + 32 + 32) * sizeof(double);
+        if (need > c.cnn_scratch_bytes) {
+            MG_TRY(c.arena.alloc(&c.cnn_scratch, need));
+            c.cnn_scratch_bytes = need;
+        }
     }
     MG_TRY(c.join.enter());
     hipStream_t st = c.join.internal;
     MG_HIP(hipEventRecord(net->join.ev, net->join.internal));
     MG_HIP(hipStreamWaitEvent(st, net->join.ev, 0));
-    if (fp64) MG_TRY(net_params64(net, st));
+    if (fp64)
+        MG_TRY(net_params64(net, st));
+    else
+        MG_TRY(net_pack_mfma(net, st));
     for (ProbBuf &pb : c.probs) {
         for (int l = 0; l + 1 < pb.nlev; ++l) {
             const LevelBuf &L = pb.lev[l];
             if (fp64)
                 MG_TRY(infer_level_direct<double>(c, L, net->params64, net->ch, (double *)c.cnn_scratch, st));
             else
-                MG_TRY(infer_level_direct<float>(c, L, net->params, net->ch, (float *)c.cnn_scratch, st));
+                launch_cnn_fused_mfma(L.n, L.P, L.plane, L.A32, net->packed, c.opt.omega, (bf16_t *)L.H, st);
         }
     }
+    MG_HIP(hipGetLastError());
     c.smoother_ready = true;
     return c.join.leave();
 }

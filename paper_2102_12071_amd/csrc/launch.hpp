@@ -79,8 +79,11 @@ void launch_cnn_output(int n, int P, int64_t plane, const T *A, const T *y, doub
                        typename SmootherStore<T>::type *H, hipStream_t st);
 void launch_f32_to_f64(int64_t count, const float *src, double *dst, hipStream_t st);
 // Fused four-layer BF16 MFMA inference (9 -> 32 -> 32 -> 32 -> 25) writing
-// H = W / a_C in BF16.  w_packed: weights laid out by pack_weights_mfma.
-void launch_cnn_fused_mfma(int n, int P, int64_t plane, const float *A32, const void *w_packed, double omega,
+// H = W / a_C in BF16.  packed: weights laid out by launch_pack_weights_mfma
+// into a buffer of packed_net_bytes().
+size_t packed_net_bytes();
+void launch_pack_weights_mfma(const float *params, void *packed, hipStream_t st);
+void launch_cnn_fused_mfma(int n, int P, int64_t plane, const float *A32, const void *packed, double omega,
                            bf16_t *H, hipStream_t st);
 // Smoother field conversions for mg_set_smoother / mg_get_smoother.
 // H = W / a_C (a_C from the FP64 stencil), and back.

@@ -38,6 +38,15 @@ mg_status net_params64(mg_net net, hipStream_t st)
     return MG_OK;
 }
 
+mg_status net_pack_mfma(mg_net net, hipStream_t st)
+{
+    if (net->packed_valid) return MG_OK;
+    launch_pack_weights_mfma(net->params, net->packed, st);
+    MG_HIP(hipGetLastError());
+    net->packed_valid = true;
+    return MG_OK;
+}
+
 }  // namespace mg
 
 extern "C" {
@@ -62,6 +71,7 @@ mg_status mg_net_create(const mg_net_desc *d, void *stream, mg_net *out)
     if (s == MG_OK) s = net->arena.alloc((void **)&net->v, net->np * sizeof(float));
     if (s == MG_OK) s = net->arena.alloc((void **)&net->grad, net->np * sizeof(float));
     if (s == MG_OK) s = net->arena.alloc((void **)&net->params64, net->np * sizeof(double));
+    if (s == MG_OK) s = net->arena.alloc(&net->packed, packed_net_bytes());
     if (s < 0) {
         net->arena.release();
         net->join.destroy();

@@ -24,7 +24,7 @@ SMOOTHER_JACOBI, SMOOTHER_CNN = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 
 CNN_CHANNELS = (9, 32, 32, 32, 25)
-NUM_TIMED_KERNELS = 7
+NUM_TIMED_KERNELS = 11
 
 # Every exported symbol of the header, with its ctypes signature.
 _c_dp = C.POINTER(C.c_double)

@@ -70,6 +70,10 @@ def parse():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--only", choices=["both", "cnn", "jacobi"], default="both",
                     help="profiling aid: run one smoother only (the JSON line then lacks the comparison)")
+    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2",
+                    help="c2: the headline problem (default); c4: variable-coefficient 4095^2 with FP64 "
+                         "refinement to 1e-10; c5: 512 uneven problems batched in one context")
+    ap.add_argument("--batch", type=int, default=512, help="c5: number of problems")
     return ap.parse_args()
 
 
@@ -91,6 +95,10 @@ def main():
 
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "c4":
+        return workload_c4(args)
+    if args.workload == "c5":
+        return workload_c5(args)
     n, theta, eps, tol = args.n, args.theta, args.eps, args.tol
     f = torch.tensor(mg_inputs.rhs_uniform(n, 0), dtype=torch.float64, device="cuda")
 
@@ -199,6 +207,111 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, theta, eps, net, cnn_s["iters"], args.cpu_cycles)
     print(json.dumps(out), flush=True)
+
+
+def load_net(args):
+    import numpy as np
+
+    import mg_inputs
+    from paper_2102_12071_amd import mgcnn
+    net = mgcnn.Net()
+    if os.path.exists(args.weights):
+        net.load(args.weights)
+        return net, True
+    net.set(mg_inputs.cnn_init(0).astype(np.float32))
+    return net, False
+
+
+def workload_c4(args):
+    """Variable-coefficient diffusion -div(a grad u) = f on a 4095^2 grid, five-
+    point face-average stencil of a = exp(g), g a Gaussian random field
+    (squared-exponential covariance, length 0.1, sigma 1, seed 7); CNN smoother
+    on every level, V(1,1), FP64 iterative refinement to 1e-10; damped Jacobi
+    beside it."""
+    import torch
+
+    import mg_inputs
+    from paper_2102_12071_amd import mgcnn
+    n = args.n if args.n != 1023 else 4095
+    tol = 1e-10
+    t0 = time.perf_counter()
+    a = torch.tensor(mg_inputs.lognormal_coefficient(n, 0.1, 1.0, 7), dtype=torch.float64, device="cuda")
+    f = torch.tensor(mg_inputs.rhs_uniform(n, 7), dtype=torch.float64, device="cuda")
+    log(f"c4 inputs generated on the host in {time.perf_counter() - t0:.1f} s")
+    net, trained = load_net(args)
+    A = mgcnn.stencil_cellavg5(a)
+    out = {"workload": f"variable-coefficient 5-point, a = exp(GRF(0.1, 1, seed 7)), n={n}, V(1,1) to {tol:g}",
+           "n": n, "unknowns": n * n, "weights": "trained" if trained else "untrained"}
+    for name, sm in (("cnn", mgcnn.SMOOTHER_CNN), ("jacobi", mgcnn.SMOOTHER_JACOBI)):
+        ctx = mgcnn.Context([A], mgcnn.Options(smoother=sm))
+        times = []
+        for k in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            ctx.restencil([mgcnn.stencil_cellavg5(a)])
+            if sm == mgcnn.SMOOTHER_CNN:
+                ctx.infer(net)
+            res = ctx.solve([f], tol, args.maxit)
+            times.append((time.perf_counter() - ts) * 1e3)
+            log(f"c4 {name} step {k}: {int(res.iters[0])} iterations, relres {res.relres[0]:.2e}, "
+                f"{times[-1]:.1f} ms")
+        ms = sum(times[args.warmup:]) / args.steps
+        kt = ctx.time_kernels(args.kernel_reps)
+        key = "cnn" if sm == mgcnn.SMOOTHER_CNN else "jacobi"
+        gbs = {k: BYTES_PER_NODE[key][k] * n * n / (kt[k] * 1e-3) / 1e9 for k in SOLVE_KERNELS}
+        out[name] = {"iters": int(res.iters[0]), "relres": float(res.relres[0]), "status": int(res.status[0]),
+                     "ms_per_step": ms, "solve_device_ms": res.ms, "unknowns_per_s": n * n / (ms * 1e-3),
+                     "kernels_ms": {k: kt[k] for k in SOLVE_KERNELS + ("check", "bottom")},
+                     "kernels_gbs": gbs, "kernels_hbm_frac": {k: v / HBM_PEAK_GBS for k, v in gbs.items()}}
+        ctx.close()
+    print(json.dumps({"metric": METRIC, "value": out["cnn"]["unknowns_per_s"], "unit": "unknowns/s",
+                      "config": out}), flush=True)
+
+
+def workload_c5(args):
+    """An uneven batch: problems with n uniform in {63, ..., 1023}, theta ~
+    U[0, pi), log10 eps ~ U[-4, 0], RHS U(-1, 1), all in one context (one
+    launch per size class and kernel), solved to 1e-8 with the CNN smoother and
+    with damped Jacobi."""
+    import numpy as np
+    import torch
+
+    import mg_inputs
+    from paper_2102_12071_amd import mgcnn
+    ns, theta, eps, seeds = mg_inputs.c5_draws(args.batch, 5)
+    tol = 1e-8
+    fs = [torch.tensor(mg_inputs.rhs_uniform(int(n), int(s)), dtype=torch.float64, device="cuda")
+          for n, s in zip(ns, seeds)]
+    stencils = [mgcnn.stencil_q1_rotated(int(n), float(t), float(e)) for n, t, e in zip(ns, theta, eps)]
+    net, trained = load_net(args)
+    N = int(sum(int(n) * int(n) for n in ns))
+    out = {"workload": f"{args.batch} problems, n in {{63..1023}}, theta ~ U[0,pi), log10 eps ~ U[-4,0], "
+                       f"V(1,1) to {tol:g}", "problems": int(args.batch), "unknowns": N,
+           "weights": "trained" if trained else "untrained"}
+    for name, sm in (("cnn", mgcnn.SMOOTHER_CNN), ("jacobi", mgcnn.SMOOTHER_JACOBI)):
+        t0 = time.perf_counter()
+        ctx = mgcnn.Context(stencils, mgcnn.Options(smoother=sm))
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        times = []
+        for k in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            ctx.restencil(stencils)
+            if sm == mgcnn.SMOOTHER_CNN:
+                ctx.infer(net)
+            res = ctx.solve(fs, tol, args.maxit)
+            times.append((time.perf_counter() - ts) * 1e3)
+            log(f"c5 {name} step {k}: max {int(res.iters.max())} iterations, "
+                f"{int((res.status == 0).sum())} converged, {times[-1]:.1f} ms")
+        ms = sum(times[args.warmup:]) / args.steps
+        out[name] = {"ms_per_step": ms, "unknowns_per_s": N / (ms * 1e-3), "allocation_setup_ms": setup_ms,
+                     "iters_median": float(np.median(res.iters)), "iters_max": int(res.iters.max()),
+                     "converged": int((res.status == 0).sum()), "not_converged": int((res.status == 1).sum()),
+                     "diverged": int((res.status == -4).sum()),
+                     "iters_by_n": {str(m): float(np.median(res.iters[ns == m])) for m in sorted(set(ns.tolist()))}}
+        ctx.close()
+    print(json.dumps({"metric": METRIC, "value": out["cnn"]["unknowns_per_s"], "unit": "unknowns/s",
+                      "config": out}), flush=True)
 
 
 def cpu_baseline(n, theta, eps, net, gpu_iters, cycles):

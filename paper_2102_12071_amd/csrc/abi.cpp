@@ -45,20 +45,30 @@ mg_status require_device()
     return MG_OK;
 }
 
+// Sub-allocates 256-byte aligned, zeroed pieces from chunks of at least
+// kArenaChunk bytes (one hipMalloc and one memset per chunk).
 mg_status Arena::alloc(void **p, size_t bytes)
 {
+    constexpr size_t kArenaChunk = (size_t)64 << 20;
     *p = nullptr;
+    bytes = (bytes + 255) & ~(size_t)255;
     if (bytes == 0) bytes = 256;
-    void *q = nullptr;
-    hipError_t e = hipMalloc(&q, bytes);
-    if (e != hipSuccess) {
-        return set_error(e == hipErrorOutOfMemory ? MG_ERR_OOM : MG_ERR_DEVICE, "hipMalloc(%zu): %s", bytes,
-                         hipGetErrorString(e));
+    if (blocks.empty() || used + bytes > cap) {
+        const size_t want = bytes > kArenaChunk ? bytes : kArenaChunk;
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, want);
+        if (e != hipSuccess) {
+            return set_error(e == hipErrorOutOfMemory ? MG_ERR_OOM : MG_ERR_DEVICE, "hipMalloc(%zu): %s", want,
+                             hipGetErrorString(e));
+        }
+        blocks.push_back(q);
+        e = hipMemset(q, 0, want);
+        if (e != hipSuccess) return set_error(MG_ERR_DEVICE, "hipMemset: %s", hipGetErrorString(e));
+        cap = want;
+        used = 0;
     }
-    blocks.push_back(q);
-    e = hipMemset(q, 0, bytes);
-    if (e != hipSuccess) return set_error(MG_ERR_DEVICE, "hipMemset: %s", hipGetErrorString(e));
-    *p = q;
+    *p = (char *)blocks.back() + used;
+    used += bytes;
     return MG_OK;
 }
 
@@ -66,6 +76,7 @@ void Arena::release()
 {
     for (void *q : blocks) (void)hipFree(q);
     blocks.clear();
+    cap = used = 0;
 }
 
 mg_status StreamJoin::init(hipStream_t user_stream)

@@ -35,6 +35,7 @@ mg_status require_device();
 // Device allocations owned by a context or network, freed together.
 struct Arena {
     std::vector<void *> blocks;
+    size_t cap = 0, used = 0;  // the last chunk
     mg_status alloc(void **p, size_t bytes);
     void release();
 };

@@ -43,3 +43,42 @@ void launch_adam(int64_t np, float *p, float *m, float *v, const float *g, float
                  float c1, float c2, hipStream_t st);
 
 }  // namespace mg
+
+namespace mg {
+
+// BF16 training path (train_mfma.hip): channel-last activations.
+enum { kTbX0 = 0, kTbAct0 = 1, kTbAct1 = 2, kTbAct2 = 3, kTbDA = 4, kTbDB = 5 };
+
+struct TrainProbB {
+    int index;             // position in the batch
+    int n;
+    int64_t plane;         // n * n
+    int tile0;             // first 16 x 16 tile of this problem in the weight-gradient parts
+    const double MG_G *A;  // stencil [9][n][n] FP64 (caller's)
+    const float MG_G *V;   // HF vectors [J][n][n] (caller's)
+    bf16_t MG_G *x0;       // [plane][16]
+    bf16_t MG_G *act;      // [3][plane][32], post-ReLU
+    float MG_G *y;         // last layer output [plane][32]
+    bf16_t MG_G *dA;       // gradient ping-pong, [plane][32] each
+    bf16_t MG_G *dB;
+    float MG_G *Av;        // [J][plane]
+    float MG_G *g;         // [J][plane]
+    float MG_G *gnorm;     // [J]
+};
+
+void launch_trb_pack(const float *params, int64_t woff, int cin, int cout, bool first, bool transposed, bf16_t *out,
+                     hipStream_t st);
+void launch_trb_bias(const float *params, int64_t boff, int cout, float *out32, hipStream_t st);
+void launch_trb_input(const TrainProbB *probs, int nb, int n, hipStream_t st);
+void launch_trb_conv_fwd(const TrainProbB *probs, int nb, int n, int layer, const bf16_t *wpack, const float *bias,
+                         hipStream_t st);
+void launch_trb_conv_bwd_data(const TrainProbB *probs, int nb, int n, int layer, const bf16_t *wpack_t,
+                              hipStream_t st);
+void launch_trb_wgrad(const TrainProbB *probs, int nb, int n, int layer, int cout, float *part, hipStream_t st);
+void launch_trb_reduce(const float *part, int ntiles, int cin, int cout, int64_t woff, int64_t boff, float *grad,
+                       hipStream_t st);
+void launch_trb_av(const TrainProbB *probs, int nb, int n, int J, hipStream_t st);
+void launch_trb_residual_norm(const TrainProbB *probs, int nb, int J, float omega, float *loss_part, hipStream_t st);
+void launch_trb_dout(const TrainProbB *probs, int nb, int n, int J, float scale, hipStream_t st);
+
+}  // namespace mg

@@ -1,0 +1,429 @@
+// BF16 training path of the stencil-to-smoother network on the matrix cores.
+// Activations are stored channel-last in BF16 ([pixel][channel], 16 channels
+// for the network input, 32 for hidden layers and gradients); the last
+// layer's output is kept in FP32.  Every convolution is an implicit GEMM on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation:
+//   forward       out[p][co] = sum_{tap,ci} in[p + tap][ci] W[co][ci][tap]  (M = pixels)
+//   data gradient dX[q][ci]  = sum_{tap,co} dY[q - tap][co] W[co][ci][tap] (the same GEMM with
+//                 the transposed, flipped weights; masked by the ReLU of the forward pass)
+//   weight grad.  dW[tap][co][ci] = sum_p dY[p][co] X[p + tap][ci]         (M = co, N = ci, K = pixels)
+// Workgroups take 16 x 16 tiles of one problem; weight gradients are written
+// per tile and reduced in a fixed order (deterministic).
+//
+// MFMA operand layout (16x16x32, wave of 64): lane l supplies
+// A[m = l % 16][k = 8 (l / 16) + e], B[k = 8 (l / 16) + e][n = l % 16],
+// and receives C[m = 4 (l / 16) + i][n = l % 16].
+#include "common.hpp"
+#include "train.hpp"
+
+namespace mg {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kT = 256;
+constexpr int kTile = 16;
+constexpr int kHalo = kTile + 2;
+
+__device__ inline bool in_grid(int n, int i, int j) { return i >= 0 && i < n && j >= 0 && j < n; }
+
+// Tensor selector of a TrainProbB.
+__device__ inline bf16_t MG_G *bsel(const TrainProbB &P, int which)
+{
+    switch (which) {
+    case kTbX0: return P.x0;
+    case kTbAct0: return P.act;
+    case kTbAct1: return P.act + P.plane * 32;
+    case kTbAct2: return P.act + P.plane * 64;
+    case kTbDA: return P.dA;
+    default: return P.dB;
+    }
+}
+
+// One convolution layer on a 16 x 16 tile.  EPI: 0 forward hidden layer
+// (bias, ReLU, zero off the grid, BF16 out); 1 forward last layer (bias,
+// FP32 out to y); 2 data gradient (mask by the forward activation `mask`).
+template <int CSIN, int STEPS, bool FIRST, int EPI>
+__global__ void __launch_bounds__(kT) k_trb_conv(const TrainProbB *probs, const bf16_t *wpack, const float *bias,
+                                                 int in_sel, int out_sel, int mask_sel)
+{
+    __shared__ __align__(16) bf16_t tin[kHalo * kHalo * CSIN];
+    const TrainProbB &P = probs[blockIdx.z];
+    const int n = P.n;
+    const int X0 = blockIdx.x * kTile, Y0 = blockIdx.y * kTile;
+    if (X0 >= n || Y0 >= n) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4;
+    const bf16_t MG_G *in = bsel(P, in_sel);
+    // input tile with a halo of one, zero off the grid: 16-byte chunks of 8 channels
+    constexpr int CH = CSIN / 8;
+    for (int q = tid; q < kHalo * kHalo * CH; q += kT) {
+        const int pix = q / CH, c8 = q % CH;
+        const int gi = X0 - 1 + pix % kHalo, gj = Y0 - 1 + pix / kHalo;
+        const bool ok = in_grid(n, gi, gj);
+        const int64_t p = ok ? (int64_t)gj * n + gi : 0;
+        u32x4 v = *(const u32x4 MG_G *)(in + p * CSIN + c8 * 8);
+        if (!ok) v = u32x4{0u, 0u, 0u, 0u};
+        *(u32x4 *)(tin + pix * CSIN + c8 * 8) = v;
+    }
+    bf16x8 bw[STEPS][2];
+    const bf16_t MG_G *wp = (const bf16_t MG_G *)wpack;
+#pragma unroll
+    for (int s = 0; s < STEPS; ++s)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) bw[s][nb] = *(const bf16x8 MG_G *)(wp + ((s * 2 + nb) * 64 + lane) * 8);
+    const float b0 = bias ? bias[lane & 15] : 0.f, b1 = bias ? bias[16 + (lane & 15)] : 0.f;
+    __syncthreads();
+    for (int mb = wave; mb < kTile * kTile / 16; mb += kT / 64) {
+        const int pa = mb * 16 + (lane & 15);
+        const int oy = pa / kTile, ox = pa % kTile;
+        f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int s = 0; s < STEPS; ++s) {
+            int tap, cg;
+            if (FIRST) {
+                tap = 2 * s + (g >> 1);
+                cg = g & 1;
+            } else {
+                tap = s;
+                cg = g;
+            }
+            bf16x8 a;
+            if (FIRST && tap > 8) {
+                a = bf16x8{};
+            } else {
+                const int ky = tap / 3, kx = tap - 3 * (tap / 3);
+                a = *(const bf16x8 *)(tin + ((oy + ky) * kHalo + ox + kx) * CSIN + cg * 8);
+            }
+            acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[s][0], acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[s][1], acc1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int pix = mb * 16 + 4 * g + i;
+            const int gi = X0 + pix % kTile, gj = Y0 + pix / kTile;
+            if (gi >= n || gj >= n) continue;
+            const int64_t p = (int64_t)gj * n + gi;
+            const int c0 = lane & 15, c1 = 16 + (lane & 15);
+            float v0 = acc0[i] + b0, v1 = acc1[i] + b1;
+            if (EPI == 0) {
+                bf16_t MG_G *out = bsel(P, out_sel);
+                out[p * 32 + c0] = f32_to_bf16(v0 > 0.f ? v0 : 0.f);
+                out[p * 32 + c1] = f32_to_bf16(v1 > 0.f ? v1 : 0.f);
+            } else if (EPI == 1) {
+                P.y[p * 32 + c0] = v0;
+                P.y[p * 32 + c1] = v1;
+            } else {
+                const bf16_t MG_G *m = bsel(P, mask_sel);
+                bf16_t MG_G *out = bsel(P, out_sel);
+                out[p * 32 + c0] = f32_to_bf16(bf16_to_f32(m[p * 32 + c0]) > 0.f ? v0 : 0.f);
+                out[p * 32 + c1] = f32_to_bf16(bf16_to_f32(m[p * 32 + c1]) > 0.f ? v1 : 0.f);
+            }
+        }
+    }
+}
+
+// Weight and bias gradient of one layer on one tile:
+//   part[tap][co][ci] = sum_{p in tile} dY[p][co] X[p + tap][ci],  part_b[co] = sum_p dY[p][co].
+// dY and X are staged channel-major in LDS so that a lane's eight K values
+// (eight consecutive pixels of one channel) are contiguous.
+template <int CIN>
+__global__ void __launch_bounds__(kT) k_trb_wgrad(const TrainProbB *probs, int dy_sel, int x_sel, int cout,
+                                                  float *part)
+{
+    __shared__ __align__(16) bf16_t dyT[32][kTile * kTile];
+    __shared__ bf16_t xT[CIN][kHalo * kHalo];
+    const TrainProbB &P = probs[blockIdx.z];
+    const int n = P.n;
+    const int X0 = blockIdx.x * kTile, Y0 = blockIdx.y * kTile;
+    const int tiles = (n + kTile - 1) / kTile;
+    float *out = part + ((int64_t)P.tile0 + blockIdx.y * tiles + blockIdx.x) * (9 * 32 * 32 + 32);
+    if (X0 >= n || Y0 >= n) return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4;
+    const bf16_t MG_G *dy = bsel(P, dy_sel);
+    const bf16_t MG_G *x = bsel(P, x_sel);
+    for (int q = tid; q < kTile * kTile * 4; q += kT) {
+        const int pix = q / 4, c8 = q % 4;
+        const int gi = X0 + pix % kTile, gj = Y0 + pix / kTile;
+        const bool ok = in_grid(n, gi, gj);
+        const int64_t p = ok ? (int64_t)gj * n + gi : 0;
+        u32x4 v = *(const u32x4 MG_G *)(dy + p * 32 + c8 * 8);
+        if (!ok) v = u32x4{0u, 0u, 0u, 0u};
+        const bf16_t *e8 = (const bf16_t *)&v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) dyT[c8 * 8 + e][pix] = e8[e];
+    }
+    constexpr int CH = CIN / 8;
+    for (int q = tid; q < kHalo * kHalo * CH; q += kT) {
+        const int pix = q / CH, c8 = q % CH;
+        const int gi = X0 - 1 + pix % kHalo, gj = Y0 - 1 + pix / kHalo;
+        const bool ok = in_grid(n, gi, gj);
+        const int64_t p = ok ? (int64_t)gj * n + gi : 0;
+        u32x4 v = *(const u32x4 MG_G *)(x + p * CIN + c8 * 8);
+        if (!ok) v = u32x4{0u, 0u, 0u, 0u};
+        const bf16_t *e8 = (const bf16_t *)&v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) xT[c8 * 8 + e][pix] = e8[e];
+    }
+    __syncthreads();
+    // bias gradient
+    if (tid < 32) {
+        float sacc = 0.f;
+        for (int p = 0; p < kTile * kTile; ++p) sacc += bf16_to_f32(dyT[tid][p]);
+        out[9 * 32 * 32 + tid] = tid < cout ? sacc : 0.f;
+    }
+    // (tap, co-block, ci-block) jobs spread over the waves
+    constexpr int NB = CIN / 16;
+    for (int job = wave; job < 9 * 2 * NB; job += kT / 64) {
+        const int tap = job / (2 * NB), mb = (job / NB) % 2, nb = job % NB;
+        const int ky = tap / 3, kx = tap % 3;
+        const int co = mb * 16 + (lane & 15), ci = nb * 16 + (lane & 15);
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+        for (int ks = 0; ks < kTile * kTile / 32; ++ks) {
+            const int k0 = ks * 32 + 8 * g;           // eight consecutive pixels of one tile row
+            const int py = k0 / kTile, px = k0 % kTile;
+            const bf16x8 a = *(const bf16x8 *)&dyT[co][k0];
+            bf16x8 b;
+            const int base = (py + ky) * kHalo + px + kx;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) b[e] = __builtin_bit_cast(__bf16, xT[ci][base + e]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int co_i = mb * 16 + 4 * g + i;
+            out[(tap * 32 + co_i) * 32 + nb * 16 + (lane & 15)] = acc[i];
+        }
+    }
+}
+
+// x0 = A / a_C, channel-last BF16 with 16 channels (9 used).
+__global__ void __launch_bounds__(kT) k_trb_input(const TrainProbB *probs)
+{
+    const TrainProbB &P = probs[blockIdx.z];
+    const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (p >= P.plane) return;
+    const double ac = P.A[kCentre * P.plane + p];
+    for (int c = 0; c < 16; ++c) P.x0[p * 16 + c] = f32_to_bf16(c < 9 ? (float)(P.A[c * P.plane + p] / ac) : 0.f);
+}
+
+// Av_j = A v_j.  grid.z = problem * J + j.
+__global__ void __launch_bounds__(kT) k_trb_av(const TrainProbB *probs, int J)
+{
+    const TrainProbB &P = probs[blockIdx.z / J];
+    const int jv = blockIdx.z % J;
+    const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (p >= P.plane) return;
+    const int n = P.n, i = (int)(p % n), j = (int)(p / n);
+    const float MG_G *v = P.V + (int64_t)jv * P.plane;
+    float acc = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        const int ii = i + c % 3 - 1, jj = j + c / 3 - 1;
+        const bool ok = in_grid(n, ii, jj);
+        const float xv = v[ok ? (int64_t)jj * n + ii : p];
+        acc += (float)P.A[c * P.plane + p] * (ok ? xv : 0.f);
+    }
+    P.Av[(int64_t)jv * P.plane + p] = acc;
+}
+
+// g_j = v_j - H A v_j, ||g_j||; H from y (channel-last FP32).  One block per (problem, vector).
+__global__ void __launch_bounds__(kT) k_trb_residual_norm(const TrainProbB *probs, int J, float omega,
+                                                          float *loss_part)
+{
+    __shared__ double red[kT / 64];
+    const TrainProbB &P = probs[blockIdx.x / J];
+    const int jv = blockIdx.x % J;
+    const int n = P.n;
+    const float MG_G *Av = P.Av + (int64_t)jv * P.plane;
+    const float MG_G *v = P.V + (int64_t)jv * P.plane;
+    float MG_G *gq = P.g + (int64_t)jv * P.plane;
+    double acc2 = 0.0;
+    for (int64_t p = threadIdx.x; p < P.plane; p += kT) {
+        const int i = (int)(p % n), j = (int)(p / n);
+        float y = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 25; ++k) {
+            const int ii = i + k % 5 - 2, jj = j + k / 5 - 2;
+            const bool ok = in_grid(n, ii, jj);
+            const float wk = P.y[p * 32 + k] + (k == 12 ? omega : 0.0f);
+            const float xv = Av[ok ? (int64_t)jj * n + ii : p];
+            y += wk * (ok ? xv : 0.f);
+        }
+        y /= (float)P.A[kCentre * P.plane + p];
+        const float gv = v[p] - y;
+        gq[p] = gv;
+        acc2 += (double)gv * gv;
+    }
+    const double s = block_sum<kT>(acc2, red);
+    if (threadIdx.x == 0) {
+        const float gn = (float)sqrt(s);
+        P.gnorm[jv] = gn;
+        loss_part[P.index * J + jv] = gn;
+    }
+}
+
+// dL/dy_p[k] = -(1/(B J)) sum_j (g_j(p)/||g_j||) Av_j(p + k)/a_C(p) -> dA (channel-last BF16, 32 channels).
+__global__ void __launch_bounds__(kT) k_trb_dout(const TrainProbB *probs, int J, float scale)
+{
+    const TrainProbB &P = probs[blockIdx.z];
+    const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (p >= P.plane) return;
+    const int n = P.n, i = (int)(p % n), j = (int)(p / n);
+    const float inv_ac = 1.0f / (float)P.A[kCentre * P.plane + p];
+    float acc[25];
+#pragma unroll
+    for (int k = 0; k < 25; ++k) acc[k] = 0.0f;
+    for (int jv = 0; jv < J; ++jv) {
+        const float gn = P.gnorm[jv];
+        const float c = gn > 0.f ? -scale * P.g[(int64_t)jv * P.plane + p] / gn * inv_ac : 0.f;
+        const float MG_G *Av = P.Av + (int64_t)jv * P.plane;
+#pragma unroll
+        for (int k = 0; k < 25; ++k) {
+            const int ii = i + k % 5 - 2, jj = j + k / 5 - 2;
+            const bool ok = in_grid(n, ii, jj);
+            const float xv = Av[ok ? (int64_t)jj * n + ii : p];
+            acc[k] += c * (ok ? xv : 0.f);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 32; ++k) P.dA[p * 32 + k] = f32_to_bf16(k < 25 ? acc[k < 25 ? k : 0] : 0.f);
+}
+
+// grad[flat] = sum over tiles of the per-tile parts, in tile order.
+__global__ void __launch_bounds__(kT) k_trb_reduce(const float *part, int ntiles, int cin, int cout, int64_t woff,
+                                                   int64_t boff, float *grad)
+{
+    const int q = blockIdx.x * kT + threadIdx.x;
+    const int nw = cout * cin * 9;
+    if (q >= nw + cout) return;
+    int64_t src, dst;
+    if (q < nw) {
+        const int co = q / (cin * 9), ci = (q / 9) % cin, tap = q % 9;
+        src = (tap * 32 + co) * 32 + ci;
+        dst = woff + q;
+    } else {
+        src = 9 * 32 * 32 + (q - nw);
+        dst = boff + (q - nw);
+    }
+    float s = 0.f;
+    for (int t = 0; t < ntiles; ++t) s += part[(int64_t)t * (9 * 32 * 32 + 32) + src];
+    grad[dst] = s;
+}
+
+// Per-lane B fragments: forward weights of layer l (mode 0) or the transposed,
+// flipped weights for the data gradient of layer l (mode 1: B[k = co][n = ci] =
+// W[co][ci][8 - tap]).  Layout [step][n-block][lane][8].
+__global__ void k_trb_pack(const float *params, int64_t woff, int cin, int cout, int first, int mode, bf16_t *out,
+                           int steps)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= steps * 2 * 64 * 8) return;
+    const int e = idx & 7, lane = (idx >> 3) & 63, nb = (idx >> 9) & 1, s = idx >> 10;
+    const int g = lane >> 4, col = nb * 16 + (lane & 15);
+    float v = 0.f;
+    if (mode == 0) {
+        int tap, ci;
+        if (first) {
+            tap = 2 * s + (g >> 1);
+            ci = 8 * (g & 1) + e;
+        } else {
+            tap = s;
+            ci = 8 * g + e;
+        }
+        const int co = col;
+        if (tap < 9 && ci < cin && co < cout) v = params[woff + ((int64_t)co * cin + ci) * 9 + tap];
+    } else {
+        const int tap = s, co = 8 * g + e, ci = col;
+        if (co < cout && ci < cin) v = params[woff + ((int64_t)co * cin + ci) * 9 + (8 - tap)];
+    }
+    out[idx] = f32_to_bf16(v);
+}
+
+__global__ void k_trb_bias(const float *params, int64_t boff, int cout, float *out32)
+{
+    const int co = threadIdx.x;
+    if (co < 32) out32[co] = co < cout ? params[boff + co] : 0.f;
+}
+
+inline unsigned blocks_for(int64_t count) { return (unsigned)((count + kT - 1) / kT); }
+
+}  // namespace
+
+void launch_trb_bias(const float *params, int64_t boff, int cout, float *out32, hipStream_t st)
+{
+    k_trb_bias<<<1, 32, 0, st>>>(params, boff, cout, out32);
+}
+
+void launch_trb_pack(const float *params, int64_t woff, int cin, int cout, bool first, bool transposed, bf16_t *out,
+                     hipStream_t st)
+{
+    const int steps = (first && !transposed) ? 5 : 9;
+    k_trb_pack<<<blocks_for(steps * 2 * 64 * 8), kT, 0, st>>>(params, woff, cin, cout, first ? 1 : 0,
+                                                              transposed ? 1 : 0, out, steps);
+}
+
+void launch_trb_input(const TrainProbB *probs, int nb, int n, hipStream_t st)
+{
+    k_trb_input<<<dim3(blocks_for((int64_t)n * n), 1, nb), kT, 0, st>>>(probs);
+}
+
+void launch_trb_conv_fwd(const TrainProbB *probs, int nb, int n, int layer, const bf16_t *wpack, const float *bias,
+                         hipStream_t st)
+{
+    const int t = (n + kTile - 1) / kTile;
+    const dim3 g(t, t, nb);
+    if (layer == 0)
+        k_trb_conv<16, 5, true, 0><<<g, kT, 0, st>>>(probs, wpack, bias, kTbX0, kTbAct0, 0);
+    else if (layer < 3)
+        k_trb_conv<32, 9, false, 0><<<g, kT, 0, st>>>(probs, wpack, bias, kTbAct0 + layer - 1, kTbAct0 + layer, 0);
+    else
+        k_trb_conv<32, 9, false, 1><<<g, kT, 0, st>>>(probs, wpack, bias, kTbAct2, 0, 0);
+}
+
+void launch_trb_conv_bwd_data(const TrainProbB *probs, int nb, int n, int layer, const bf16_t *wpack_t,
+                              hipStream_t st)
+{
+    // the gradient of layer `layer`'s output is in dA for layers 3 and 1, dB for layer 2
+    const int t = (n + kTile - 1) / kTile;
+    const dim3 g(t, t, nb);
+    const int in_sel = (layer & 1) ? kTbDA : kTbDB, out_sel = (layer & 1) ? kTbDB : kTbDA;
+    k_trb_conv<32, 9, false, 2><<<g, kT, 0, st>>>(probs, wpack_t, nullptr, in_sel, out_sel, kTbAct0 + layer - 1);
+}
+
+void launch_trb_wgrad(const TrainProbB *probs, int nb, int n, int layer, int cout, float *part, hipStream_t st)
+{
+    const int t = (n + kTile - 1) / kTile;
+    const dim3 g(t, t, nb);
+    const int dy_sel = (layer & 1) ? kTbDA : kTbDB;
+    if (layer == 0)
+        k_trb_wgrad<16><<<g, kT, 0, st>>>(probs, dy_sel, kTbX0, cout, part);
+    else
+        k_trb_wgrad<32><<<g, kT, 0, st>>>(probs, dy_sel, kTbAct0 + layer - 1, cout, part);
+}
+
+void launch_trb_reduce(const float *part, int ntiles, int cin, int cout, int64_t woff, int64_t boff, float *grad,
+                       hipStream_t st)
+{
+    k_trb_reduce<<<blocks_for(cout * cin * 9 + cout), kT, 0, st>>>(part, ntiles, cin, cout, woff, boff, grad);
+}
+
+void launch_trb_av(const TrainProbB *probs, int nb, int n, int J, hipStream_t st)
+{
+    k_trb_av<<<dim3(blocks_for((int64_t)n * n), 1, nb * J), kT, 0, st>>>(probs, J);
+}
+
+void launch_trb_residual_norm(const TrainProbB *probs, int nb, int J, float omega, float *loss_part, hipStream_t st)
+{
+    k_trb_residual_norm<<<nb * J, kT, 0, st>>>(probs, J, omega, loss_part);
+}
+
+void launch_trb_dout(const TrainProbB *probs, int nb, int n, int J, float scale, hipStream_t st)
+{
+    k_trb_dout<<<dim3(blocks_for((int64_t)n * n), 1, nb), kT, 0, st>>>(probs, J, scale);
+}
+
+}  // namespace mg

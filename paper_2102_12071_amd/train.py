@@ -97,7 +97,7 @@ def main():
     ap.add_argument("--nvec", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--precision", type=int, default=1, help="1: BF16 on MFMA (default); 0: FP32")
     ap.add_argument("--var-frac", type=float, default=0.5)
     ap.add_argument("--eval-every", type=int, default=500)
     ap.add_argument("--out", default=DEFAULT_OUT)

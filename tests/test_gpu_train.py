@@ -95,3 +95,42 @@ def test_training_reduces_the_loss(mg):
     # the untrained network is damped Jacobi: its loss is the oracle's Jacobi loss
     L0, _ = ora.hf_loss(stencils, vecs, mg_inputs.cnn_init(0), grad=False)
     assert abs(losses[0] - L0) <= 1e-5 * L0
+
+
+def _cosine(a, b):
+    return float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)))
+
+
+def test_bf16_mfma_loss_and_gradient_close_to_oracle(mg):
+    # BF16 activations and weights, FP32 accumulation: compare with the FP64 oracle by angle and norm
+    stencils, vecs = _batch(4)
+    params = mg_inputs.cnn_random(7)
+    L_ref, g_ref = ora.hf_loss(stencils, vecs, params)
+    net = mg.Net()
+    net.set(params.astype(np.float32))
+    st, vs = _dev(stencils, vecs)
+    L, g = net.train_step(st, vs, mg.TrainOptions(precision=1, apply_update=0), want_grad=True)
+    g = g.astype(np.float64)
+    assert abs(L - L_ref) <= 1e-2 * L_ref
+    assert _cosine(g, g_ref) >= 0.999
+    assert np.linalg.norm(g - g_ref) <= 2e-2 * np.linalg.norm(g_ref)
+    # every layer's block of the gradient, not only the largest one
+    off = 0
+    for l in range(4):
+        cin, cout = mg_inputs.CNN_CHANNELS[l], mg_inputs.CNN_CHANNELS[l + 1]
+        k = cout * cin * 9 + cout
+        assert _cosine(g[off:off + k], g_ref[off:off + k]) >= 0.995, l
+        off += k
+
+
+def test_bf16_training_step_is_deterministic_and_reduces_the_loss(mg):
+    stencils, vecs = _batch(5)
+    st, vs = _dev(stencils, vecs)
+    p0 = mg_inputs.cnn_init(0).astype(np.float32)
+    nets = [mg.Net(), mg.Net()]
+    for net in nets:
+        net.set(p0)
+    losses = [[net.train_step(st, vs, mg.TrainOptions(precision=1, lr=2e-3))[0] for _ in range(40)] for net in nets]
+    assert losses[0] == losses[1]
+    assert np.array_equal(nets[0].get(), nets[1].get())
+    assert losses[0][-1] < 0.9 * losses[0][0]

@@ -68,12 +68,16 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=30, help="V-cycles in the oracle's timed sample")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--tune-reps", type=int, default=10, help="launches per tile shape in the autotuner")
     ap.add_argument("--only", choices=["both", "cnn", "jacobi"], default="both",
                     help="profiling aid: run one smoother only (the JSON line then lacks the comparison)")
     ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2",
                     help="c2: the headline problem (default); c4: variable-coefficient 4095^2 with FP64 "
                          "refinement to 1e-10; c5: 512 uneven problems batched in one context")
     ap.add_argument("--batch", type=int, default=512, help="c5: number of problems")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="profiling aid: only run a plain device copy of MIB MiB five times (the known-size "
+                         "kernel that scales the HBM byte counters) and exit")
     return ap.parse_args()
 
 
@@ -95,6 +99,15 @@ def main():
 
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "launches": 5}), flush=True)
+        return
     if args.workload == "c4":
         return workload_c4(args)
     if args.workload == "c5":
@@ -112,6 +125,8 @@ def main():
     A = mgcnn.stencil_q1_rotated(n, theta, eps)
     ctx_cnn = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_CNN, precision=mgcnn.PREC_MIXED))
     ctx_jac = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_JACOBI, precision=mgcnn.PREC_MIXED))
+    for ctx in (ctx_cnn, ctx_jac):  # set-up, outside the timed steps
+        ctx.autotune(args.tune_reps)
 
     def step(ctx, cnn: bool):
         """One pass of the hot path; returns (iters, relres, phase times in ms)."""
@@ -176,6 +191,8 @@ def main():
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                 "bytes_per_launch": nbytes, "avg_launch_ms": kt[dom],
                 "kernels_ms": kt,
+                "tiles": {k: ctx_cnn.tile(k, n)["shape"] for k in mgcnn.TILE_KERNELS},
+                "tile_ms": {k: ctx_cnn.tile(k, n)["ms"] for k in mgcnn.TILE_KERNELS},
                 "kernels_gbs": {k: BYTES_PER_NODE["cnn"][k] * N / (v * 1e-3) / 1e9 for k, v in kt.items()
                                 if k in BYTES_PER_NODE["cnn"]}}
     # the kernel timing leaves the context's vectors undefined; the next solve resets them
@@ -243,7 +260,10 @@ def workload_c4(args):
     out = {"workload": f"variable-coefficient 5-point, a = exp(GRF(0.1, 1, seed 7)), n={n}, V(1,1) to {tol:g}",
            "n": n, "unknowns": n * n, "weights": "trained" if trained else "untrained"}
     for name, sm in (("cnn", mgcnn.SMOOTHER_CNN), ("jacobi", mgcnn.SMOOTHER_JACOBI)):
+        if args.only not in ("both", name):
+            continue
         ctx = mgcnn.Context([A], mgcnn.Options(smoother=sm))
+        ctx.autotune(args.tune_reps)
         times = []
         for k in range(args.warmup + args.steps):
             torch.cuda.synchronize()
@@ -262,10 +282,12 @@ def workload_c4(args):
         out[name] = {"iters": int(res.iters[0]), "relres": float(res.relres[0]), "status": int(res.status[0]),
                      "ms_per_step": ms, "solve_device_ms": res.ms, "unknowns_per_s": n * n / (ms * 1e-3),
                      "kernels_ms": {k: kt[k] for k in SOLVE_KERNELS + ("check", "bottom")},
+                     "tiles": {k: ctx.tile(k, n)["shape"] for k in mgcnn.TILE_KERNELS},
+                     "tile_ms": {k: ctx.tile(k, n)["ms"] for k in mgcnn.TILE_KERNELS},
                      "kernels_gbs": gbs, "kernels_hbm_frac": {k: v / HBM_PEAK_GBS for k, v in gbs.items()}}
         ctx.close()
-    print(json.dumps({"metric": METRIC, "value": out["cnn"]["unknowns_per_s"], "unit": "unknowns/s",
-                      "config": out}), flush=True)
+    print(json.dumps({"metric": METRIC, "value": out.get("cnn", out.get("jacobi"))["unknowns_per_s"],
+                      "unit": "unknowns/s", "config": out}), flush=True)
 
 
 def workload_c5(args):
@@ -292,6 +314,7 @@ def workload_c5(args):
         t0 = time.perf_counter()
         ctx = mgcnn.Context(stencils, mgcnn.Options(smoother=sm))
         setup_ms = (time.perf_counter() - t0) * 1e3
+        ctx.autotune(args.tune_reps)
         times = []
         for k in range(args.warmup + args.steps):
             torch.cuda.synchronize()

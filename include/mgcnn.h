@@ -172,6 +172,30 @@ mg_status mg_last_solve_ms(mg_ctx ctx, double *ms);
 mg_status mg_time_kernels(mg_ctx ctx, int32_t reps, double *ms);
 const char *mg_kernel_name(int32_t k);
 
+/* Workgroup shapes of the fused V(1,1) level kernels (kernel 0: descent,
+ * 1: ascent), chosen per level size for the batched size classes.  Every
+ * shape computes each node with the same arithmetic in the same order, so
+ * the choice changes speed only, never results.
+ *
+ * mg_autotune times each of the MG_NUM_TILES shapes of both kernels on every
+ * level size above the bottom kernel's (reps launches after one warm-up, on
+ * the context's own buffers and batch) and keeps the fastest.  cache: NULL,
+ * or the path of a text file of "key = shape" lines: choices found there are
+ * taken without timing, new ones are appended (the file is rewritten);
+ * MG_ERR_ARG if it cannot be written.  Contexts whose sweeps are not V(1,1)
+ * have nothing to tune (MG_OK).  Leaves the context's vectors undefined (the
+ * next mg_solve resets them).  Synchronises. */
+#define MG_NUM_TILES 5
+mg_status mg_autotune(mg_ctx ctx, int32_t reps, const char *cache);
+/* The shape in use for kernel on level size n, and (ms non-NULL) the time per
+ * launch of each shape at the last mg_autotune (MG_NUM_TILES entries, 0 when
+ * not timed).  MG_ERR_ARG if no level of size n runs the fused kernels. */
+mg_status mg_get_tile(mg_ctx ctx, int32_t kernel, int32_t n, int32_t *tile, double *ms);
+/* Forces a shape for kernel on level size n (n = 0: every size). */
+mg_status mg_set_tile(mg_ctx ctx, int32_t kernel, int32_t n, int32_t tile);
+/* Static description of a shape ("32x8 coarse nodes, 512 threads"). */
+const char *mg_tile_name(int32_t kernel, int32_t tile);
+
 /* ------------------------------------------------------------------------ */
 /* Smoother network (section 4.2, convolutional parameterisation).           */
 /* ------------------------------------------------------------------------ */

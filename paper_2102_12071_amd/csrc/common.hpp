@@ -28,6 +28,27 @@ constexpr int kMaxCoarseUnknowns = 49;  // coarsest grid up to 7 x 7
 // such planes, plane stride n*P.
 __host__ __device__ inline int64_t plane_of(int n, int P) { return (int64_t)n * P; }
 
+// ------------------------------------------------------- workgroup order
+// The dispatcher hands workgroups to the 8 XCDs round-robin in linear block
+// order (x fastest, then y, then z), and each XCD has its own L2.  Tiled
+// kernels renumber their blocks so that every XCD runs one contiguous run of
+// tiles: neighbouring tiles, which read the same halo cache lines, then share
+// an L2.  The renumbering is a bijection of [0, nblocks) for any grid.
+constexpr int kNumXcd = 8;
+struct TileId {
+    int x, y, z;
+};
+__device__ inline TileId xcd_tile()
+{
+    const int gx = gridDim.x, gy = gridDim.y;
+    const int nb = gx * gy * gridDim.z;
+    const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+    const int xcd = b % kNumXcd, local = b / kNumXcd;
+    const int q = nb / kNumXcd, r = nb % kNumXcd;
+    const int t = xcd * q + min(xcd, r) + local;
+    return TileId{t % gx, (t / gx) % gy, t / (gx * gy)};
+}
+
 // ------------------------------------------------------------------- bf16
 // Storage as raw 16-bit words; conversion is round-to-nearest-even (the
 // hardware v_cvt_pk_bf16_f32 on gfx950).

@@ -11,9 +11,12 @@
 // out on the device, so one captured graph serves every iteration.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
+#include <string>
 
 #include "internal.hpp"
 #include "launch.hpp"
@@ -68,7 +71,10 @@ mg_status build_slots(mg_ctx_s &c)
             s.e = (T *)L.e;
             s.s = (T *)L.s;
             s.rc = (T *)Lc.r;
-            s.ec = (T *)Lc.e;
+            // the fused ascent of a level writes its post-smoothed correction to s (its
+            // neighbours still read the pre-smoothed e in their halos); the bottom-levels
+            // kernel leaves its top level's correction in e
+            s.ec = (c.fused && l + 1 < top) ? (T *)Lc.s : (T *)Lc.e;
             s.nc = Lc.n;
             s.Pc = Lc.P;
             s.u = (c.fused && l == 0) ? pb.u : nullptr;
@@ -136,10 +142,11 @@ void enqueue_vcycle(mg_ctx_s &c, hipStream_t st)
     const double w = c.opt.omega;
     if (c.fused) {
         for (const SizeClass &k : c.classes)  // descending sizes
-            launch_descend<T>((const CycleSlot<T> *)k.d_slots, k.nslots, k.n, cnn, w, c.d_state, st);
+            launch_descend<T>((const CycleSlot<T> *)k.d_slots, k.nslots, k.n, cnn, w, c.d_state, st, k.tile[0]);
         launch_bottom<T>((const BottomSlot<T> *)c.d_bottom, c.nprob, c.bottom_top_n, cnn, w, 1, 1, c.d_state, st);
         for (auto it = c.classes.rbegin(); it != c.classes.rend(); ++it)  // ascending sizes
-            launch_ascend<T>((const CycleSlot<T> *)it->d_slots, it->nslots, it->n, cnn, w, c.d_state, st);
+            launch_ascend<T>((const CycleSlot<T> *)it->d_slots, it->nslots, it->n, cnn, w, c.d_state, st,
+                             it->tile[1]);
         return;
     }
     for (const SizeClass &k : c.classes) {  // descending sizes
@@ -646,8 +653,8 @@ void launch_timed(mg_ctx_s &c, int k, const SizeClass &cls, const SizeClass &oc,
     switch (k) {
     case 0: launch_outer_residual<T>(o, oc.nslots, n, c.d_state, st); break;
     case 1: launch_check<T>(o, oc.nslots, c.d_state, c.d_params, 1, st); break;
-    case 2: launch_descend<T>(s, cls.nslots, n, cnn, w, c.d_state, st); break;
-    case 3: launch_ascend<T>(s, cls.nslots, n, cnn, w, c.d_state, st); break;
+    case 2: launch_descend<T>(s, cls.nslots, n, cnn, w, c.d_state, st, cls.tile[0]); break;
+    case 3: launch_ascend<T>(s, cls.nslots, n, cnn, w, c.d_state, st, cls.tile[1]); break;
     case 4:
         launch_bottom<T>((const BottomSlot<T> *)c.d_bottom, c.nprob, c.bottom_top_n, cnn, w, c.opt.nu_pre,
                          c.opt.nu_post, c.d_state, st);
@@ -699,8 +706,156 @@ extern "C" mg_status mg_time_kernels(mg_ctx ctx, int32_t reps, double *ms)
     return c.join.leave();
 }
 
-extern "C" {
-}  // extern "C"
+// ---------------------------------------------------------------- autotuning
+namespace mg {
+namespace {
+
+static_assert(MG_NUM_TILES == kNumTiles, "tile count of the ABI and of the kernels");
+
+void drop_graph(mg_ctx_s &c)
+{
+    if (c.graph_exec) (void)hipGraphExecDestroy(c.graph_exec);
+    if (c.graph) (void)hipGraphDestroy(c.graph);
+    c.graph_exec = nullptr;
+    c.graph = nullptr;
+}
+
+std::string tune_key(const mg_ctx_s &c, int kernel, const SizeClass &k)
+{
+    char b[160];
+    std::snprintf(b, sizeof b, "%s n=%d slots=%d precision=%d smoother=%d", kernel ? "ascend" : "descend", k.n,
+                  k.nslots, c.opt.precision, c.opt.smoother);
+    return b;
+}
+
+template <typename T>
+void launch_tile(mg_ctx_s &c, int kernel, const SizeClass &k, int tile, hipStream_t st)
+{
+    auto *s = (const CycleSlot<T> *)k.d_slots;
+    const bool cnn = c.opt.smoother == MG_SMOOTHER_CNN;
+    if (kernel == 0)
+        launch_descend<T>(s, k.nslots, k.n, cnn, c.opt.omega, c.d_state, st, tile);
+    else
+        launch_ascend<T>(s, k.nslots, k.n, cnn, c.opt.omega, c.d_state, st, tile);
+}
+
+// Cache file: one "key = tile" line per (kernel, level size, batch, precision, smoother).
+void read_tune_cache(const char *path, std::map<std::string, int> &known)
+{
+    FILE *fh = std::fopen(path, "r");
+    if (!fh) return;
+    char line[256];
+    while (std::fgets(line, sizeof line, fh)) {
+        char *eq = std::strrchr(line, '=');
+        if (!eq || eq == line || eq[-1] != ' ') continue;
+        const int t = std::atoi(eq + 1);
+        if (t < 0 || t >= kNumTiles) continue;
+        known[std::string(line, eq - 1)] = t;
+    }
+    std::fclose(fh);
+}
+
+mg_status write_tune_cache(const char *path, const std::map<std::string, int> &known)
+{
+    FILE *fh = std::fopen(path, "w");
+    if (!fh) return set_error(MG_ERR_ARG, "cannot write the tuning cache %s", path);
+    for (const auto &kv : known) std::fprintf(fh, "%s = %d\n", kv.first.c_str(), kv.second);
+    std::fclose(fh);
+    return MG_OK;
+}
+
+}  // namespace
+}  // namespace mg
+
+extern "C" mg_status mg_autotune(mg_ctx ctx, int32_t reps, const char *cache)
+{
+    clear_error();
+    MG_TRY(check_ctx(ctx));
+    if (reps < 1) return set_error(MG_ERR_ARG, "reps must be >= 1");
+    mg_ctx_s &c = *ctx;
+    if (!c.fused || c.classes.empty()) return MG_OK;  // no fused level kernels to shape
+    std::map<std::string, int> known;
+    if (cache) read_tune_cache(cache, known);
+    bool timed = false;
+    MG_TRY(c.join.enter());
+    hipStream_t st = c.join.internal;
+    launch_activate(c.d_state, c.nprob, st);
+    for (SizeClass &k : c.classes) {
+        for (int kernel = 0; kernel < 2; ++kernel) {
+            const std::string key = tune_key(c, kernel, k);
+            const auto it = known.find(key);
+            if (it != known.end()) {
+                k.tile[kernel] = it->second;
+                continue;
+            }
+            double best = 0.0;
+            for (int t = 0; t < kNumTiles; ++t) {
+                auto launch = [&]() {
+                    if (c.opt.precision == MG_PREC_FP64)
+                        launch_tile<double>(c, kernel, k, t, st);
+                    else
+                        launch_tile<float>(c, kernel, k, t, st);
+                };
+                launch();  // warm-up
+                MG_HIP(hipEventRecord(c.t0, st));
+                for (int q = 0; q < reps; ++q) launch();
+                MG_HIP(hipEventRecord(c.t1, st));
+                MG_HIP(hipEventSynchronize(c.t1));
+                float ms = 0.0f;
+                MG_HIP(hipEventElapsedTime(&ms, c.t0, c.t1));
+                k.tile_ms[kernel][t] = (double)ms / reps;
+                if (t == 0 || k.tile_ms[kernel][t] < best) {
+                    best = k.tile_ms[kernel][t];
+                    k.tile[kernel] = t;
+                }
+            }
+            known[key] = k.tile[kernel];
+            timed = true;
+        }
+    }
+    MG_HIP(hipGetLastError());
+    drop_graph(c);
+    MG_TRY(c.join.leave());
+    if (cache && timed) MG_TRY(write_tune_cache(cache, known));
+    return MG_OK;
+}
+
+extern "C" mg_status mg_get_tile(mg_ctx ctx, int32_t kernel, int32_t n, int32_t *tile, double *ms)
+{
+    clear_error();
+    MG_TRY(check_ctx(ctx));
+    if (kernel != 0 && kernel != 1) return set_error(MG_ERR_ARG, "kernel must be 0 (descent) or 1 (ascent)");
+    for (const SizeClass &k : ctx->classes) {
+        if (k.n != n) continue;
+        if (tile) *tile = k.tile[kernel];
+        if (ms)
+            for (int t = 0; t < kNumTiles; ++t) ms[t] = k.tile_ms[kernel][t];
+        return MG_OK;
+    }
+    return set_error(MG_ERR_ARG, "no level of size %d runs the fused kernels in this context", n);
+}
+
+extern "C" mg_status mg_set_tile(mg_ctx ctx, int32_t kernel, int32_t n, int32_t tile)
+{
+    clear_error();
+    MG_TRY(check_ctx(ctx));
+    if (kernel != 0 && kernel != 1) return set_error(MG_ERR_ARG, "kernel must be 0 (descent) or 1 (ascent)");
+    if (tile < 0 || tile >= kNumTiles) return set_error(MG_ERR_ARG, "tile must be in [0, %d)", kNumTiles);
+    bool found = n == 0;
+    for (SizeClass &k : ctx->classes)
+        if (n == 0 || k.n == n) {
+            k.tile[kernel] = tile;
+            found = true;
+        }
+    if (!found) return set_error(MG_ERR_ARG, "no level of size %d runs the fused kernels in this context", n);
+    drop_graph(*ctx);
+    return MG_OK;
+}
+
+extern "C" const char *mg_tile_name(int32_t kernel, int32_t tile)
+{
+    return (kernel == 0 || kernel == 1) && tile >= 0 && tile < kNumTiles ? tile_name(kernel, tile) : "unknown";
+}
 
 // ---------------------------------------------------------------- inference
 namespace mg {

@@ -71,10 +71,11 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads) k_outer_residual(const OuterSlot<T> *slots, const SolveState *state)
 {
     __shared__ double red[kThreads / 64];
-    const OuterSlot<T> s = slots[blockIdx.z];
+    const TileId tile = xcd_tile();
+    const OuterSlot<T> s = slots[tile.z];
     if (!state[s.prob].active) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    const int i = tile.x * blockDim.x + threadIdx.x;
+    const int j = tile.y * blockDim.y + threadIdx.y;
     double r = 0.0;
     if (i < s.n && j < s.n) {
         const int64_t p = (int64_t)j * s.P + i;
@@ -83,7 +84,7 @@ __global__ void __launch_bounds__(kThreads) k_outer_residual(const OuterSlot<T> 
     }
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
     const double sum = block_sum<kThreads>(r * r, red);
-    if (tid == 0) s.partial[blockIdx.y * gridDim.x + blockIdx.x] = sum;
+    if (tid == 0) s.partial[tile.y * gridDim.x + tile.x] = sum;
 }
 
 // The stopping rule of the solver (section 6.1) for one problem, given

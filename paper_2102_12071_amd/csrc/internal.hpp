@@ -73,6 +73,8 @@ struct ProbBuf {
 struct SizeClass {
     int n = 0, nslots = 0;
     void *d_slots = nullptr;  // CycleSlot<T>[nslots] or OuterSlot<T>[nslots]
+    int tile[2] = {0, 0};     // workgroup shape of the fused descent and ascent
+    double tile_ms[2][8] = {};  // time per launch of each shape at the last autotuning (0: not timed)
 };
 
 }  // namespace mg

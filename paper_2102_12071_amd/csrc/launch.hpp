@@ -19,12 +19,16 @@ void launch_validate(int n, int P, int64_t plane, const double *A, int *flag, hi
 void launch_coarse_factor(int m, int P, int64_t plane, const double *A, double *Ainv, int *flag, hipStream_t st);
 
 // ---- fused.hip: one launch per level and direction for V(1,1) ----
+// tile: one of kNumTiles workgroup shapes (0 = default); results do not depend on it.
+constexpr int kNumTiles = 5;
 template <typename T>
 void launch_descend(const CycleSlot<T> *slots, int nslots, int n, bool cnn, double omega, const SolveState *state,
-                    hipStream_t st);
+                    hipStream_t st, int tile = 0);
 template <typename T>
 void launch_ascend(const CycleSlot<T> *slots, int nslots, int n, bool cnn, double omega, const SolveState *state,
-                   hipStream_t st);
+                   hipStream_t st, int tile = 0);
+// "32x8 coarse nodes, 512 threads" and the like (kernel 0: descent, 1: ascent).
+const char *tile_name(int kernel, int tile);
 
 // ---- cycle.hip: V-cycle kernels (T = float: mixed precision; double: FP64) ----
 // Every launcher covers one size class (all slots share n); blocks of

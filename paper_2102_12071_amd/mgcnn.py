@@ -25,6 +25,8 @@ PREC_FP64, PREC_MIXED = 0, 1
 
 CNN_CHANNELS = (9, 32, 32, 32, 25)
 NUM_TIMED_KERNELS = 11
+NUM_TILES = 5
+TILE_KERNELS = ("descend", "ascend")
 
 # Every exported symbol of the header, with its ctypes signature.
 _c_dp = C.POINTER(C.c_double)
@@ -85,6 +87,10 @@ SIGNATURES = {
     "mg_restencil": (C.c_int, [C.c_void_p, C.POINTER(Problem)]),
     "mg_time_kernels": (C.c_int, [C.c_void_p, C.c_int32, _c_dp]),
     "mg_kernel_name": (C.c_char_p, [C.c_int32]),
+    "mg_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_char_p]),
+    "mg_get_tile": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _c_ip, _c_dp]),
+    "mg_set_tile": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]),
+    "mg_tile_name": (C.c_char_p, [C.c_int32, C.c_int32]),
     "mg_net_create": (C.c_int, [C.POINTER(NetDesc), C.c_void_p, C.POINTER(C.c_void_p)]),
     "mg_net_destroy": (C.c_int, [C.c_void_p]),
     "mg_net_num_params": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64)]),
@@ -229,6 +235,24 @@ class Context:
         ms = np.zeros(NUM_TIMED_KERNELS, dtype=np.float64)
         _check(lib.mg_time_kernels(self._h, int(reps), ms.ctypes.data_as(_c_dp)))
         return {lib.mg_kernel_name(k).decode(): float(ms[k]) for k in range(NUM_TIMED_KERNELS)}
+
+    def autotune(self, reps: int = 10, cache: Optional[str] = None) -> None:
+        """Times every workgroup shape of the fused level kernels per level size and keeps the fastest."""
+        _check(load_library().mg_autotune(self._h, int(reps), cache.encode() if cache else None))
+
+    def tile(self, kernel: str, n: int) -> dict:
+        """Shape in use for 'descend' or 'ascend' on level size n, with the per-shape times of the last tuning."""
+        lib = load_library()
+        k = TILE_KERNELS.index(kernel)
+        t = C.c_int32(0)
+        ms = np.zeros(NUM_TILES, dtype=np.float64)
+        _check(lib.mg_get_tile(self._h, k, int(n), C.byref(t), ms.ctypes.data_as(_c_dp)))
+        return {"tile": int(t.value), "shape": lib.mg_tile_name(k, t.value).decode(),
+                "ms": {lib.mg_tile_name(k, q).decode(): float(ms[q]) for q in range(NUM_TILES)}}
+
+    def set_tile(self, kernel: str, n: int, tile: int) -> None:
+        """Forces a shape for 'descend' or 'ascend' on level size n (0: all sizes)."""
+        _check(load_library().mg_set_tile(self._h, TILE_KERNELS.index(kernel), int(n), int(tile)))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -86,6 +86,29 @@ def test_vcycle_jacobi_fp64(mg, nu, n, coarse):
     assert _rel(u.cpu().numpy(), ref) <= 1e-12
 
 
+@pytest.mark.parametrize("n", [2047])
+def test_vcycle_fused_many_tiles_fp64(mg, n):
+    # Levels with more tiles than the GPU holds at once (1024 ascent tiles at
+    # n = 1023): a tile that starts after its neighbour finished must still see
+    # the neighbour's pre-smoothing correction in its halo.  A wrong halo value
+    # changes the result at the size of a smoothing step (1e-2 and more); the
+    # bound is instead set from the oracle's own sensitivity to rounding: the
+    # cycle's change when the stencil carries relative noise of 1e-16 (the
+    # hierarchy's conditioning grows like n^2: about 1e-14 at n = 63, 1e-11 here).
+    A = ora.stencil_q1_rotated(n, 0.4, 0.02)
+    f = mg_inputs.rhs_uniform(n, 5)
+    u0 = mg_inputs.random_field((n, n), 6)
+    ctx = mg.Context([_dev(A)], mg.Options(precision=mg.PREC_FP64))
+    u = _dev(u0)
+    ctx.vcycle([_dev(f)], [u])
+    r0 = f - ora.matvec(A, u0)
+    ref = u0 + ora.Hierarchy(A).vcycle(r0, 1, 1)
+    noisy = A * (1.0 + 1e-16 * np.random.default_rng(1).standard_normal(A.shape))
+    sensitivity = _rel(u0 + ora.Hierarchy(noisy).vcycle(r0, 1, 1), ref)
+    assert 1e-13 < sensitivity < 1e-10
+    assert _rel(u.cpu().numpy(), ref) <= 20 * sensitivity
+
+
 @pytest.mark.parametrize("n", [31, 127])
 def test_vcycle_given_smoother_fp64(mg, n):
     # an explicit 5x5 smoother field on every level (the learned smoother's kernel)

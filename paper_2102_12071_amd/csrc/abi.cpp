@@ -62,8 +62,9 @@ mg_status Arena::alloc(void **p, size_t bytes)
                              hipGetErrorString(e));
         }
         blocks.push_back(q);
-        e = hipMemset(q, 0, want);
-        if (e != hipSuccess) return set_error(MG_ERR_DEVICE, "hipMemset: %s", hipGetErrorString(e));
+        e = hipMemsetAsync(q, 0, want, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return set_error(MG_ERR_DEVICE, "clearing a new chunk: %s", hipGetErrorString(e));
         cap = want;
         used = 0;
     }

@@ -279,6 +279,7 @@ mg_status read_flag(mg_ctx_s &c, hipStream_t st)
 mg_status setup_impl(mg_ctx_s &c, const mg_problem *probs, hipStream_t user)
 {
     MG_TRY(c.join.init(user));
+    c.arena.stream = c.join.internal;
     MG_HIP(hipEventCreate(&c.t0));
     MG_HIP(hipEventCreate(&c.t1));
     MG_TRY(c.join.enter());

@@ -41,7 +41,15 @@ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 // arithmetic in the same order, so the choice changes speed only; the
 // autotuner picks one per level size.
 #define MG_DESCEND_TILES(X) X(0, 32, 8, 512) X(1, 32, 4, 256) X(2, 16, 8, 256) X(3, 32, 16, 1024) X(4, 64, 8, 1024)
-#define MG_ASCEND_TILES(X) X(0, 64, 16, 512) X(1, 64, 8, 256) X(2, 128, 8, 512) X(3, 64, 32, 1024) X(4, 128, 16, 1024)
+#define MG_ASCEND_TILES(X)                                                                                     \
+    X(0, 64, 16, 512) X(1, 64, 8, 256) X(2, 128, 8, 512) X(3, 64, 32, 1024) X(4, 128, 16, 1024)            \
+    X(5, 256, 8, 1024) X(6, 32, 16, 256)
+// The descent split in two launches: the pre-smoothing sweep on owned fine
+// tiles of FX x FY nodes (NT1 threads), then residual and restriction on
+// coarse tiles of CX x CY nodes (NT2 threads) reading e back.  It moves 8 more
+// bytes per node (e written and read) but reads every smoother entry once, on
+// aligned rows, instead of recomputing e on a one-node ring around each tile.
+#define MG_SPLIT_TILES(X) X(5, 64, 16, 512, 32, 8, 512) X(6, 128, 8, 512, 64, 8, 1024)
 
 template <typename T> struct Pair { typedef T type __attribute__((ext_vector_type(2))); };
 
@@ -226,6 +234,193 @@ __global__ void __launch_bounds__(kT) k_descend(const CycleSlot<T> *slots, const
     }
     __syncthreads();
     // ---- r_c = R s
+    const T *sts = (const T *)st;
+    constexpr int SW = 2 * SXP;
+    if (tid < kCX * kCY) {
+        const int tx = tid % kCX, ty = tid / kCX;
+        const int I = I0 + tx, J = J0 + ty;
+        if (I < nc && J < nc) {
+            const int c = (2 * ty + 1) * SW + 2 * tx + 1;
+            const T v = (T)0.0625 * (sts[c - SW - 1] + sts[c - SW + 1] + sts[c + SW - 1] + sts[c + SW + 1]) +
+                        (T)0.125 * (sts[c - SW] + sts[c + SW] + sts[c - 1] + sts[c + 1]) + (T)0.25 * sts[c];
+            s.rc[(int64_t)J * s.Pc + I] = v;
+        }
+    }
+}
+
+// First pre-smoothing sweep from e = 0 on an owned tile of kFX x kFY fine
+// nodes: e = M^{-1} r, written to memory (the split descent's first launch).
+template <typename T, bool CNN, int kFX, int kFY, int kT>
+__global__ void __launch_bounds__(kT) k_presmooth(const CycleSlot<T> *slots, const SolveState *state, T omega)
+{
+    static_assert(kFX % 2 == 0, "tiles start at even columns");
+    typedef typename Pair<T>::type T2;
+    typedef HPair<T> HP;
+    typedef typename HP::type H2;
+    constexpr bool PH = PrefetchH<T>::value;
+    constexpr int OXP = kFX / 2, NO = OXP * kFY, IO = ceil_div(NO, kT);
+    constexpr int RHP = CNN ? 1 : 0, RHY = CNN ? 2 : 0;  // r reaches two nodes (one pair) out for the CNN
+    constexpr int RXP = OXP + 2 * RHP, RY = kFY + 2 * RHY, NR = RXP * RY, IR = ceil_div(NR, kT);
+    constexpr int NH = CNN ? 25 : 1;
+    __shared__ T2 rt[NR];
+    const TileId tile = xcd_tile();
+    const CycleSlot<T> s = slots[tile.z];
+    if (!state[s.prob].active) return;
+    const int n = s.n;
+    const int X0 = tile.x * kFX, Y0 = tile.y * kFY;
+    const int rx0 = X0 - 2 * RHP, ry0 = Y0 - RHY;
+    const int tid = threadIdx.x;
+    auto pair_ok = [n](int i, int j) { return i >= 0 && i < n && j >= 0 && j < n; };
+
+    T2 rv[IR];
+#pragma unroll
+    for (int k = 0; k < IR; ++k) {
+        const int q = tid + k * kT;
+        const int i = rx0 + 2 * (q % RXP), j = ry0 + q / RXP;
+        const bool ok = q < NR && pair_ok(i, j);
+        const T2 v = ld2(s.r, ok ? (int64_t)j * s.P + i : 0);
+        rv[k].x = ok ? v.x : (T)0;
+        rv[k].y = ok && i + 1 < n ? v.y : (T)0;
+    }
+    H2 hv[IO][PH ? NH : 1];
+    T2 acv[IO];
+#pragma unroll
+    for (int k = 0; k < IO; ++k) {
+        const int q = tid + k * kT;
+        const int i = X0 + 2 * (q % OXP), j = Y0 + q / OXP;
+        const int64_t p = q < NO && pair_ok(i, j) ? (int64_t)j * s.P + i : 0;
+        if (CNN) {
+            if (PH) {
+#pragma unroll
+                for (int t = 0; t < NH; ++t) hv[k][t] = HP::load(s.H, t * s.plane + p);  // unused off the grid
+            }
+        } else {
+            acv[k] = ld2(s.A, kCentre * s.plane + p);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < IR; ++k) {
+        const int q = tid + k * kT;
+        if (q < NR) rt[q] = rv[k];
+    }
+    __syncthreads();
+    const T *rts = (const T *)rt;
+#pragma unroll
+    for (int k = 0; k < IO; ++k) {
+        const int q = tid + k * kT;
+        if (q >= NO) break;
+        const int px = q % OXP, y = q / OXP;
+        const int i = X0 + 2 * px, j = Y0 + y;
+        if (!pair_ok(i, j)) continue;
+        const int64_t p = (int64_t)j * s.P + i;
+        T lo = 0, hi = 0;
+        if (CNN) {
+#pragma unroll
+            for (int dy = -2; dy <= 2; ++dy) {
+                // r at columns i-2 .. i+3 of row j+dy (r's region starts at column X0-2)
+                const T *row = rts + (y + RHY + dy) * (2 * RXP) + 2 * px;
+                const T2 a = *(const T2 *)row, b = *(const T2 *)(row + 2), c = *(const T2 *)(row + 4);
+                const T w[6] = {a.x, a.y, b.x, b.y, c.x, c.y};
+#pragma unroll
+                for (int dx = -2; dx <= 2; ++dx) {
+                    const int tap = 5 * (dy + 2) + dx + 2;
+                    const H2 h = PH ? hv[k][PH ? tap : 0] : HP::load(s.H, tap * s.plane + p);
+                    lo += (T)HP::lo(h) * w[dx + 2];
+                    hi += (T)HP::hi(h) * w[dx + 3];
+                }
+            }
+        } else {
+            const T2 r = rt[y * RXP + px];
+            lo = omega * r.x / acv[k].x;
+            hi = i + 1 < n ? omega * r.y / acv[k].y : (T)0;
+        }
+        T2 v;
+        v.x = lo;
+        v.y = i + 1 < n ? hi : (T)0;
+        st2(s.e, p, v);
+    }
+}
+
+// s = r - A e and r_c = R s for a tile of kCX x kCY coarse nodes, with e read
+// from memory (the split descent's second launch).
+template <typename T, int kCX, int kCY, int kT>
+__global__ void __launch_bounds__(kT) k_resrestrict(const CycleSlot<T> *slots, const SolveState *state)
+{
+    static_assert(kCX * kCY <= kT, "one thread per coarse node of the tile");
+    typedef typename Pair<T>::type T2;
+    // residual region x in [sx0, sx0 + 2 kCX + 2), y in [sy0, sy0 + 2 kCY];
+    // e on it plus one node around, in pairs from sx0 - 2
+    constexpr int SXP = kCX + 1, SY = 2 * kCY + 1;
+    constexpr int EXP = kCX + 2, EY = SY + 2, EWP = EXP + 1;
+    constexpr int NE = EXP * EY, NS = SXP * SY;
+    constexpr int IE = ceil_div(NE, kT), IS = ceil_div(NS, kT);
+    __shared__ T2 et[EY * EWP];
+    __shared__ T2 st[SY * SXP];
+    const TileId tile = xcd_tile();
+    const CycleSlot<T> s = slots[tile.z];
+    if (!state[s.prob].active) return;
+    const int n = s.n, nc = s.nc;
+    const int I0 = tile.x * kCX, J0 = tile.y * kCY;
+    const int sx0 = 2 * I0, sy0 = 2 * J0;
+    const int ex0 = sx0 - 2, ey0 = sy0 - 1;
+    const int tid = threadIdx.x;
+    auto pair_ok = [n](int i, int j) { return i >= 0 && i < n && j >= 0 && j < n; };
+
+    T2 ev[IE];
+#pragma unroll
+    for (int k = 0; k < IE; ++k) {
+        const int q = tid + k * kT;
+        const int i = ex0 + 2 * (q % EXP), j = ey0 + q / EXP;
+        const bool ok = q < NE && pair_ok(i, j);
+        const T2 v = ld2(s.e, ok ? (int64_t)j * s.P + i : 0);
+        ev[k].x = ok ? v.x : (T)0;
+        ev[k].y = ok && i + 1 < n ? v.y : (T)0;
+    }
+    T2 rv[IS], av[IS][9];
+#pragma unroll
+    for (int k = 0; k < IS; ++k) {
+        const int q = tid + k * kT;
+        const int i = sx0 + 2 * (q % SXP), j = sy0 + q / SXP;
+        const int64_t p = q < NS && pair_ok(i, j) ? (int64_t)j * s.P + i : 0;
+        rv[k] = ld2(s.r, p);  // unused off the grid
+#pragma unroll
+        for (int c = 0; c < 9; ++c) av[k][c] = ld2(s.A, c * s.plane + p);
+    }
+#pragma unroll
+    for (int k = 0; k < IE; ++k) {
+        const int q = tid + k * kT;
+        if (q >= NE) break;
+        const int px = q % EXP, y = q / EXP;
+        et[y * EWP + px] = ev[k];
+        if (px == EXP - 1) et[y * EWP + EXP] = T2{0, 0};
+    }
+    __syncthreads();
+    const T *ets = (const T *)et;
+#pragma unroll
+    for (int k = 0; k < IS; ++k) {
+        const int q = tid + k * kT;
+        if (q >= NS) break;
+        const int px = q % SXP, y = q / SXP;
+        const int i = sx0 + 2 * px, j = sy0 + y;
+        T lo = 0, hi = 0;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            const T *row = ets + (y + 1 + dy) * (2 * EWP) + 2 * px;
+            const T2 a = *(const T2 *)row, b = *(const T2 *)(row + 2), c = *(const T2 *)(row + 4);
+            const T w[6] = {a.x, a.y, b.x, b.y, c.x, c.y};
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int cc = 3 * (dy + 1) + dx + 1;
+                lo += av[k][cc].x * w[dx + 2];
+                hi += av[k][cc].y * w[dx + 3];
+            }
+        }
+        T2 v;
+        v.x = pair_ok(i, j) ? rv[k].x - lo : (T)0;
+        v.y = pair_ok(i, j) && i + 1 < n ? rv[k].y - hi : (T)0;
+        st[q] = v;
+    }
+    __syncthreads();
     const T *sts = (const T *)st;
     constexpr int SW = 2 * SXP;
     if (tid < kCX * kCY) {
@@ -449,6 +644,19 @@ void launch_descend(const CycleSlot<T> *slots, int nslots, int n, bool cnn, doub
     }
         MG_DESCEND_TILES(MG_CASE)
 #undef MG_CASE
+#define MG_CASE(V, FX, FY, NT1, CX, CY, NT2)                                                               \
+    case V: {                                                                                              \
+        const dim3 g1((n + FX - 1) / FX, (n + FY - 1) / FY, nslots);                                       \
+        const dim3 g2((nc + CX - 1) / CX, (nc + CY - 1) / CY, nslots);                                     \
+        if (cnn)                                                                                           \
+            k_presmooth<T, true, FX, FY, NT1><<<g1, NT1, 0, st>>>(slots, state, (T)omega);                 \
+        else                                                                                               \
+            k_presmooth<T, false, FX, FY, NT1><<<g1, NT1, 0, st>>>(slots, state, (T)omega);                \
+        k_resrestrict<T, CX, CY, NT2><<<g2, NT2, 0, st>>>(slots, state);                                   \
+        break;                                                                                             \
+    }
+        MG_SPLIT_TILES(MG_CASE)
+#undef MG_CASE
     }
 }
 
@@ -474,10 +682,13 @@ void launch_ascend(const CycleSlot<T> *slots, int nslots, int n, bool cnn, doubl
 const char *tile_name(int kernel, int tile)
 {
 #define MG_NAME_D(V, X, Y, NT) #X "x" #Y " coarse nodes, " #NT " threads",
+#define MG_NAME_S(V, FX, FY, NT1, CX, CY, NT2) \
+    "split: " #FX "x" #FY " fine nodes, " #NT1 " threads; " #CX "x" #CY " coarse nodes, " #NT2 " threads",
 #define MG_NAME_A(V, X, Y, NT) #X "x" #Y " fine nodes, " #NT " threads",
-    static const char *const descend[] = {MG_DESCEND_TILES(MG_NAME_D)};
+    static const char *const descend[] = {MG_DESCEND_TILES(MG_NAME_D) MG_SPLIT_TILES(MG_NAME_S)};
     static const char *const ascend[] = {MG_ASCEND_TILES(MG_NAME_A)};
 #undef MG_NAME_D
+#undef MG_NAME_S
 #undef MG_NAME_A
     static_assert(sizeof(descend) / sizeof(descend[0]) == kNumTiles, "descent shapes");
     static_assert(sizeof(ascend) / sizeof(ascend[0]) == kNumTiles, "ascent shapes");

@@ -32,10 +32,14 @@ void clear_error();
 // Checks that a gfx950 device is current (once per process).
 mg_status require_device();
 
-// Device allocations owned by a context or network, freed together.
+// Device allocations owned by a context or network, freed together.  New
+// chunks are zeroed on the owner's stream (the library's non-blocking stream,
+// which the null stream does not order against) and the call waits for it,
+// so no later copy or kernel can race the clearing.
 struct Arena {
     std::vector<void *> blocks;
     size_t cap = 0, used = 0;  // the last chunk
+    hipStream_t stream = nullptr;
     mg_status alloc(void **p, size_t bytes);
     void release();
 };

@@ -66,6 +66,7 @@ mg_status mg_net_create(const mg_net_desc *d, void *stream, mg_net *out)
     mg_net net = new mg_net_s();
     net->np = count_params(4, want);
     mg_status s = net->join.init((hipStream_t)stream);
+    net->arena.stream = net->scratch.stream = net->join.internal;
     if (s == MG_OK) s = net->arena.alloc((void **)&net->params, net->np * sizeof(float));
     if (s == MG_OK) s = net->arena.alloc((void **)&net->m, net->np * sizeof(float));
     if (s == MG_OK) s = net->arena.alloc((void **)&net->v, net->np * sizeof(float));

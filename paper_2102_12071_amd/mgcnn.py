@@ -25,7 +25,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 
 CNN_CHANNELS = (9, 32, 32, 32, 25)
 NUM_TIMED_KERNELS = 11
-NUM_TILES = 5
+NUM_TILES = 7
 TILE_KERNELS = ("descend", "ascend")
 
 # Every exported symbol of the header, with its ctypes signature.

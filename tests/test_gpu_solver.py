@@ -206,6 +206,30 @@ def test_setup_rejects_invalid_stencils(mg):
     assert ei.value.status == mg.MG_ERR_STATE
 
 
+def test_fresh_contexts_are_bit_identical(mg):
+    # Set-up writes the hierarchy into freshly cleared device memory; the
+    # clearing must be ordered before the set-up kernels, or parts of the
+    # stencils and coarsest inverse are wiped at random.
+    n = 127
+    A = _dev(ora.stencil_q1_rotated(n, 0.4, 0.02))
+    f = _dev(mg_inputs.rhs_uniform(n, 4))
+    first = None
+    for _ in range(4):
+        ctx = mg.Context([A], mg.Options(precision=mg.PREC_MIXED))
+        levels = [ctx.stencil(0, l).cpu() for l in range(ctx.num_levels(0))]
+        u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        ctx.vcycle([f], [u])
+        ctx.vcycle([f], [u])
+        got = (levels, u.cpu())
+        ctx.close()
+        if first is None:
+            first = got
+            continue
+        for a, b in zip(got[0], first[0]):
+            assert torch.equal(a, b)
+        assert torch.equal(got[1], first[1])
+
+
 def test_graph_and_eager_give_identical_results(mg):
     n = 127
     A = ora.stencil_q1_rotated(n, 0.4, 0.02)

@@ -49,6 +49,51 @@ BYTES_PER_NODE = {
 }
 SOLVE_KERNELS = ("outer_residual", "descend", "ascend")  # per-node kernels of the V(1,1) solve
 
+# Measured HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by
+# what the counter reads for a plain copy of known size) of every tile shape of the
+# finest-level kernels, with the hash of the kernel sources they were taken with.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_hbm_traffic.txt")
+KERNEL_SOURCES = ("paper_2102_12071_amd/csrc/fused.hip", "paper_2102_12071_amd/csrc/cycle.hip",
+                  "paper_2102_12071_amd/csrc/common.hpp")
+
+
+def measured_traffic(kernel: str, tile: str):
+    """HBM bytes per launch of the CNN-smoother kernel at this tile shape, from the
+    committed counter summary; None when it is missing or the sources changed since."""
+    import hashlib
+    import re
+    try:
+        line = next(l for l in open(TRAFFIC_FILE) if l.startswith("data: "))
+        data = json.loads(line[len("data: "):])
+    except (OSError, StopIteration, ValueError):
+        return None
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != data.get("source_sha256"):
+        return None
+    if kernel == "outer_residual":
+        names = ["k_outer_residual<float>"]
+    elif tile.startswith("split:"):
+        m = re.match(r"split: (\d+)x(\d+) fine nodes, (\d+) threads; (\d+)x(\d+) coarse nodes, (\d+) threads", tile)
+        if not m:
+            return None
+        a = m.groups()
+        names = [f"k_presmooth<float, true, {a[0]}, {a[1]}, {a[2]}>", f"k_resrestrict<float, {a[3]}, {a[4]}, {a[5]}>"]
+    else:
+        m = re.match(r"(\d+)x(\d+) (?:coarse|fine) nodes, (\d+) threads", tile)
+        if not m:
+            return None
+        names = [f"k_{kernel}<float, true, {m.group(1)}, {m.group(2)}, {m.group(3)}>"]
+    k = data["kernels"]
+    if not all(n in k for n in names):
+        return None
+    return {"bytes": sum(k[n]["fetch"] + k[n]["write"] for n in names),
+            "fetch": sum(k[n]["fetch"] for n in names), "write": sum(k[n]["write"] for n in names),
+            "kernels": names, "source": os.path.relpath(TRAFFIC_FILE, ROOT),
+            "fetch_factor": data["fetch_factor"], "write_factor": data["write_factor"]}
+
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -187,11 +232,14 @@ def main():
     dom = max(SOLVE_KERNELS, key=kt.get)
     nbytes = BYTES_PER_NODE["cnn"][dom] * N
     achieved = nbytes / (kt[dom] * 1e-3) / 1e9
+    tiles = {k: ctx_cnn.tile(k, n)["shape"] for k in mgcnn.TILE_KERNELS}
+    traffic = measured_traffic(dom, tiles.get(dom, ""))
     roofline = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic["bytes"] if traffic else None,
+                "traffic_detail": traffic,
                 "bytes_per_launch": nbytes, "avg_launch_ms": kt[dom],
                 "kernels_ms": kt,
-                "tiles": {k: ctx_cnn.tile(k, n)["shape"] for k in mgcnn.TILE_KERNELS},
+                "tiles": tiles,
                 "tile_ms": {k: ctx_cnn.tile(k, n)["ms"] for k in mgcnn.TILE_KERNELS},
                 "kernels_gbs": {k: BYTES_PER_NODE["cnn"][k] * N / (v * 1e-3) / 1e9 for k, v in kt.items()
                                 if k in BYTES_PER_NODE["cnn"]}}

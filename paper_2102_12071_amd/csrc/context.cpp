@@ -45,6 +45,23 @@ mg_status upload(Arena &arena, const std::vector<S> &v, void **dptr)
     return MG_OK;
 }
 
+// A size class's slot table: uploaded, kept on the host for compaction, and
+// room for the compacted copy.
+template <typename S>
+mg_status upload_class(Arena &arena, const std::vector<S> &v, const std::vector<int> &probs, SizeClass &sc)
+{
+    sc.nslots = (int)v.size();
+    sc.probs = probs;
+    sc.slot_bytes = sizeof(S);
+    sc.host_slots.assign((const char *)v.data(), (const char *)(v.data() + v.size()));
+    MG_TRY(upload(arena, v, &sc.d_slots));
+    MG_TRY(arena.alloc(&sc.d_live, sizeof(S) * v.size()));
+    sc.d_run = sc.d_slots;
+    sc.nrun = sc.nslots;
+    sc.live = sc.nslots > 0;
+    return MG_OK;
+}
+
 // Builds the slot tables of every size class for compute type T.
 template <typename T>
 mg_status build_slots(mg_ctx_s &c)
@@ -52,6 +69,7 @@ mg_status build_slots(mg_ctx_s &c)
     typedef typename SmootherStore<T>::type HT;
     std::map<int, std::vector<CycleSlot<T>>, std::greater<int>> cls;
     std::map<int, std::vector<OuterSlot<T>>, std::greater<int>> out;
+    std::map<int, std::vector<int>> cls_probs, out_probs;
     std::vector<BottomSlot<T>> bottom;
     c.bottom_top_n = 0;
     for (int p = 0; p < c.nprob; ++p) {
@@ -79,6 +97,7 @@ mg_status build_slots(mg_ctx_s &c)
             s.Pc = Lc.P;
             s.u = (c.fused && l == 0) ? pb.u : nullptr;
             cls[L.n].push_back(s);
+            cls_probs[L.n].push_back(p);
         }
         const LevelBuf &L0 = pb.lev[0], &Lm = pb.lev[pb.nlev - 1];
         OuterSlot<T> o{};
@@ -93,6 +112,7 @@ mg_status build_slots(mg_ctx_s &c)
         o.e = (const T *)L0.e;
         o.partial = pb.partial;
         out[L0.n].push_back(o);
+        out_probs[L0.n].push_back(p);
         (void)Lm;
         BottomSlot<T> b{};
         b.prob = p;
@@ -115,18 +135,19 @@ mg_status build_slots(mg_ctx_s &c)
     for (auto &kv : cls) {
         SizeClass sc;
         sc.n = kv.first;
-        sc.nslots = (int)kv.second.size();
-        MG_TRY(upload(c.arena, kv.second, &sc.d_slots));
+        MG_TRY(upload_class(c.arena, kv.second, cls_probs[kv.first], sc));
         c.classes.push_back(sc);
     }
     for (auto &kv : out) {
         SizeClass sc;
         sc.n = kv.first;
-        sc.nslots = (int)kv.second.size();
-        MG_TRY(upload(c.arena, kv.second, &sc.d_slots));
+        MG_TRY(upload_class(c.arena, kv.second, out_probs[kv.first], sc));
         c.outer.push_back(sc);
     }
-    MG_TRY(upload(c.arena, bottom, &c.d_bottom));
+    std::vector<int> all(c.nprob);
+    for (int p = 0; p < c.nprob; ++p) all[p] = p;
+    c.bottom.n = c.bottom_top_n;
+    MG_TRY(upload_class(c.arena, bottom, all, c.bottom));
     prepare_bottom<T>();
     return MG_OK;
 }
@@ -142,35 +163,42 @@ void enqueue_vcycle(mg_ctx_s &c, hipStream_t st)
     const double w = c.opt.omega;
     if (c.fused) {
         for (const SizeClass &k : c.classes)  // descending sizes
-            launch_descend<T>((const CycleSlot<T> *)k.d_slots, k.nslots, k.n, cnn, w, c.d_state, st, k.tile[0]);
-        launch_bottom<T>((const BottomSlot<T> *)c.d_bottom, c.nprob, c.bottom_top_n, cnn, w, 1, 1, c.d_state, st);
+            if (k.live)
+                launch_descend<T>((const CycleSlot<T> *)k.d_run, k.nrun, k.n, cnn, w, c.d_state, st, k.tile[0]);
+        if (c.bottom.live)
+            launch_bottom<T>((const BottomSlot<T> *)c.bottom.d_run, c.bottom.nrun, c.bottom_top_n, cnn, w, 1, 1,
+                             c.d_state, st);
         for (auto it = c.classes.rbegin(); it != c.classes.rend(); ++it)  // ascending sizes
-            launch_ascend<T>((const CycleSlot<T> *)it->d_slots, it->nslots, it->n, cnn, w, c.d_state, st,
-                             it->tile[1]);
+            if (it->live)
+                launch_ascend<T>((const CycleSlot<T> *)it->d_run, it->nrun, it->n, cnn, w, c.d_state, st,
+                                 it->tile[1]);
         return;
     }
     for (const SizeClass &k : c.classes) {  // descending sizes
-        auto *s = (const CycleSlot<T> *)k.d_slots;
+        if (!k.live) continue;
+        auto *s = (const CycleSlot<T> *)k.d_run;
         if (c.opt.nu_pre == 0) {
-            launch_zero_e<T>(s, k.nslots, k.n, c.d_state, st);
+            launch_zero_e<T>(s, k.nrun, k.n, c.d_state, st);
         } else {
-            launch_smooth_first<T>(s, k.nslots, k.n, cnn, w, c.d_state, st);
+            launch_smooth_first<T>(s, k.nrun, k.n, cnn, w, c.d_state, st);
             for (int it = 1; it < c.opt.nu_pre; ++it) {
-                launch_residual<T>(s, k.nslots, k.n, c.d_state, st);
-                launch_smooth_apply<T>(s, k.nslots, k.n, cnn, w, c.d_state, st);
+                launch_residual<T>(s, k.nrun, k.n, c.d_state, st);
+                launch_smooth_apply<T>(s, k.nrun, k.n, cnn, w, c.d_state, st);
             }
         }
-        launch_residual_restrict<T>(s, k.nslots, k.n, c.d_state, st);
+        launch_residual_restrict<T>(s, k.nrun, k.n, c.d_state, st);
     }
-    launch_bottom<T>((const BottomSlot<T> *)c.d_bottom, c.nprob, c.bottom_top_n, cnn, w, c.opt.nu_pre, c.opt.nu_post,
-                     c.d_state, st);
+    if (c.bottom.live)
+        launch_bottom<T>((const BottomSlot<T> *)c.bottom.d_run, c.bottom.nrun, c.bottom_top_n, cnn, w, c.opt.nu_pre,
+                         c.opt.nu_post, c.d_state, st);
     for (auto it = c.classes.rbegin(); it != c.classes.rend(); ++it) {  // ascending sizes
         const SizeClass &k = *it;
-        auto *s = (const CycleSlot<T> *)k.d_slots;
-        launch_prolong<T>(s, k.nslots, k.n, c.d_state, st);
+        if (!k.live) continue;
+        auto *s = (const CycleSlot<T> *)k.d_run;
+        launch_prolong<T>(s, k.nrun, k.n, c.d_state, st);
         for (int q = 0; q < c.opt.nu_post; ++q) {
-            launch_residual<T>(s, k.nslots, k.n, c.d_state, st);
-            launch_smooth_apply<T>(s, k.nslots, k.n, cnn, w, c.d_state, st);
+            launch_residual<T>(s, k.nrun, k.n, c.d_state, st);
+            launch_smooth_apply<T>(s, k.nrun, k.n, cnn, w, c.d_state, st);
         }
     }
 }
@@ -179,14 +207,14 @@ template <typename T>
 void enqueue_outer_residual(mg_ctx_s &c, hipStream_t st)
 {
     for (const SizeClass &k : c.outer)
-        launch_outer_residual<T>((const OuterSlot<T> *)k.d_slots, k.nslots, k.n, c.d_state, st);
+        if (k.live) launch_outer_residual<T>((const OuterSlot<T> *)k.d_run, k.nrun, k.n, c.d_state, st);
 }
 
 template <typename T>
 void enqueue_check(mg_ctx_s &c, int init, hipStream_t st)
 {
     for (const SizeClass &k : c.outer)
-        launch_check<T>((const OuterSlot<T> *)k.d_slots, k.nslots, c.d_state, c.d_params, init, st);
+        if (k.live) launch_check<T>((const OuterSlot<T> *)k.d_run, k.nrun, c.d_state, c.d_params, init, st);
 }
 
 // u += e where the V-cycle did not do it.
@@ -194,7 +222,8 @@ template <typename T>
 void enqueue_update(mg_ctx_s &c, hipStream_t st)
 {
     if (c.fused) return;
-    for (const SizeClass &k : c.outer) launch_update_u<T>((const OuterSlot<T> *)k.d_slots, k.nslots, k.n, c.d_state, st);
+    for (const SizeClass &k : c.outer)
+        if (k.live) launch_update_u<T>((const OuterSlot<T> *)k.d_run, k.nrun, k.n, c.d_state, st);
 }
 
 // One solver iteration: residual and stopping rule, V-cycle, update.
@@ -379,6 +408,51 @@ void copy_out(mg_ctx_s &c, double *const *u, hipStream_t st)
     }
 }
 
+void drop_graph(mg_ctx_s &c)
+{
+    if (c.graph_exec) (void)hipGraphExecDestroy(c.graph_exec);
+    if (c.graph) (void)hipGraphDestroy(c.graph);
+    c.graph_exec = nullptr;
+    c.graph = nullptr;
+}
+
+// Keeps the launches to the problems that still iterate: each size class
+// launches a compacted copy of its slot table holding only the active
+// problems' slots (a class with none is left out), and the captured iteration
+// is rebuilt whenever that changes.  Blocks of finished problems would return
+// at once, but an uneven batch's last few slow problems would still pay for
+// dispatching every finished problem's tiles of every level size.  Called with
+// the stream idle (the slot copies are synchronous).
+mg_status update_live(mg_ctx_s &c, const std::vector<char> &active)
+{
+    bool changed = false;
+    auto compact = [&](SizeClass &k) -> mg_status {
+        int cnt = 0;
+        for (int p : k.probs) cnt += active[p] != 0;
+        if (cnt == k.nrun && (cnt == k.nslots) == (k.d_run == k.d_slots)) return MG_OK;
+        changed = true;
+        k.live = cnt > 0;
+        if (cnt == k.nslots) {
+            k.d_run = k.d_slots;
+            k.nrun = k.nslots;
+            return MG_OK;
+        }
+        std::vector<char> buf((size_t)cnt * k.slot_bytes);
+        int q = 0;
+        for (int s = 0; s < k.nslots; ++s)
+            if (active[k.probs[s]]) std::memcpy(&buf[(size_t)q++ * k.slot_bytes], &k.host_slots[(size_t)s * k.slot_bytes], k.slot_bytes);
+        if (cnt > 0) MG_HIP(hipMemcpy(k.d_live, buf.data(), buf.size(), hipMemcpyHostToDevice));
+        k.d_run = k.d_live;
+        k.nrun = cnt;
+        return MG_OK;
+    };
+    for (SizeClass &k : c.classes) MG_TRY(compact(k));
+    for (SizeClass &k : c.outer) MG_TRY(compact(k));
+    MG_TRY(compact(c.bottom));
+    if (changed) drop_graph(c);
+    return MG_OK;
+}
+
 mg_status ensure_graph(mg_ctx_s &c)
 {
     if (c.graph_exec || !c.opt.use_graph) return MG_OK;
@@ -505,6 +579,7 @@ mg_status mg_vcycle(mg_ctx ctx, const double *const *f, double *const *u)
     MG_TRY(ctx->join.enter());
     hipStream_t st = ctx->join.internal;
     copy_in(*ctx, f, u, false, st);
+    MG_TRY(update_live(*ctx, std::vector<char>(ctx->nprob, 1)));  // every problem takes part
     launch_activate(ctx->d_state, ctx->nprob, st);
     if (ctx->opt.precision == MG_PREC_FP64) {
         enqueue_outer_residual<double>(*ctx, st);
@@ -541,7 +616,7 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
             c.history_cap = need;
         }
     }
-    MG_TRY(ensure_graph(c));
+    MG_TRY(update_live(c, std::vector<char>(c.nprob, 1)));
     MG_TRY(c.join.enter());
     hipStream_t st = c.join.internal;
     MG_HIP(hipEventRecord(c.t0, st));
@@ -563,9 +638,11 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
         enqueue_check<float>(c, 1, st);
     }
     std::vector<SolveState> hs(c.nprob);
+    std::vector<char> act(c.nprob);
     const int every = c.opt.check_every;
     int64_t replays = 0;
     for (;;) {
+        MG_TRY(ensure_graph(c));  // (re)captured with the live classes; the stream is idle here
         for (int q = 0; q < every; ++q) {
             if (c.graph_exec)
                 MG_HIP(hipGraphLaunch(c.graph_exec, st));
@@ -576,8 +653,12 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
         MG_HIP(hipMemcpyAsync(hs.data(), c.d_state, sizeof(SolveState) * c.nprob, hipMemcpyDeviceToHost, st));
         MG_HIP(hipStreamSynchronize(st));
         bool any = false;
-        for (int p = 0; p < c.nprob; ++p) any |= hs[p].active != 0;
+        for (int p = 0; p < c.nprob; ++p) {
+            act[p] = hs[p].active != 0;
+            any |= act[p] != 0;
+        }
         if (!any || replays > (int64_t)maxit + 2) break;
+        MG_TRY(update_live(c, act));
     }
     copy_out(c, u, st);
     MG_HIP(hipEventRecord(c.t1, st));
@@ -657,7 +738,7 @@ void launch_timed(mg_ctx_s &c, int k, const SizeClass &cls, const SizeClass &oc,
     case 2: launch_descend<T>(s, cls.nslots, n, cnn, w, c.d_state, st, cls.tile[0]); break;
     case 3: launch_ascend<T>(s, cls.nslots, n, cnn, w, c.d_state, st, cls.tile[1]); break;
     case 4:
-        launch_bottom<T>((const BottomSlot<T> *)c.d_bottom, c.nprob, c.bottom_top_n, cnn, w, c.opt.nu_pre,
+        launch_bottom<T>((const BottomSlot<T> *)c.bottom.d_slots, c.nprob, c.bottom_top_n, cnn, w, c.opt.nu_pre,
                          c.opt.nu_post, c.d_state, st);
         break;
     case 5: launch_smooth_first<T>(s, cls.nslots, n, cnn, w, c.d_state, st); break;
@@ -712,14 +793,6 @@ namespace mg {
 namespace {
 
 static_assert(MG_NUM_TILES == kNumTiles, "tile count of the ABI and of the kernels");
-
-void drop_graph(mg_ctx_s &c)
-{
-    if (c.graph_exec) (void)hipGraphExecDestroy(c.graph_exec);
-    if (c.graph) (void)hipGraphDestroy(c.graph);
-    c.graph_exec = nullptr;
-    c.graph = nullptr;
-}
 
 std::string tune_key(const mg_ctx_s &c, int kernel, const SizeClass &k)
 {

@@ -77,6 +77,15 @@ struct ProbBuf {
 struct SizeClass {
     int n = 0, nslots = 0;
     void *d_slots = nullptr;  // CycleSlot<T>[nslots] or OuterSlot<T>[nslots]
+    std::vector<int> probs;   // the problem of each slot
+    bool live = true;         // some problem of the class still iterates (launches skip dead classes)
+    // the slots the solver launches: all of them, or (once problems stop) a
+    // compacted copy holding the iterating problems only
+    std::vector<char> host_slots;  // the slot table as uploaded
+    size_t slot_bytes = 0;
+    void *d_live = nullptr;        // room for the compacted copy
+    void *d_run = nullptr;
+    int nrun = 0;
     int tile[2] = {0, 0};     // workgroup shape of the fused descent and ascent
     double tile_ms[2][8] = {};  // time per launch of each shape at the last autotuning (0: not timed)
 };
@@ -111,7 +120,7 @@ struct mg_ctx_s {
     std::vector<mg::ProbBuf> probs;
     std::vector<mg::SizeClass> classes;  // levels above the coarsest, n descending
     std::vector<mg::SizeClass> outer;    // finest levels, by n
-    void *d_bottom = nullptr;            // BottomSlot<T>[nprob]
+    mg::SizeClass bottom;                // BottomSlot<T>[nprob] (d_slots), one per problem
     int bottom_top_n = 0;                // largest top level of the bottom kernel
     mg::SolveState *d_state = nullptr;
     mg::SolveParams *d_params = nullptr;

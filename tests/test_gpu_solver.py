@@ -174,6 +174,30 @@ def test_uneven_batch_matches_individual_solves(mg):
         assert _rel(res.u[q].cpu().numpy(), u_ref) <= 1e-10
 
 
+@pytest.mark.parametrize("use_graph", [1, 0])
+def test_batch_drops_finished_size_classes_without_changing_results(mg, use_graph):
+    # an easy large problem finishes long before a hard small one: its size
+    # classes leave the launches, and nothing else may change
+    specs = [(255, 0.3, 1.0), (63, 0.05, 1e-3), (127, 1.2, 0.2)]
+    As = [_dev(ora.stencil_q1_rotated(n, t, e)) for n, t, e in specs]
+    fs = [_dev(mg_inputs.rhs_uniform(n, 20 + q)) for q, (n, _, _) in enumerate(specs)]
+    opt = mg.Options(precision=mg.PREC_FP64, use_graph=use_graph, check_every=4)
+    ctx = mg.Context(As, opt)
+    res = ctx.solve(fs, 1e-9, 4000)
+    assert res.iters[0] < res.iters[2] < res.iters[1]
+    for q in range(len(specs)):
+        one = mg.Context([As[q]], opt).solve([fs[q]], 1e-9, 4000)
+        assert one.iters[0] == res.iters[q]
+        assert torch.equal(one.u[0], res.u[q])
+    # a single cycle afterwards runs every size class again
+    us = [torch.zeros_like(f) for f in fs]
+    ctx.vcycle(fs, us)
+    fresh = [torch.zeros_like(f) for f in fs]
+    mg.Context(As, opt).vcycle(fs, fresh)
+    for a, b in zip(us, fresh):
+        assert torch.equal(a, b)
+
+
 def test_maxit_and_not_converged_status(mg):
     n = 63
     A = ora.stencil_q1_rotated(n, 1.0, 1e-3)

@@ -28,6 +28,9 @@ if ROOT not in sys.path:
 METRIC = "time-to-1e-8 residual & unknowns/s: CNN-smoother MG vs Jacobi MG, 1 GPU"
 WEIGHTS = os.path.join(ROOT, "paper_2102_12071_amd", "weights", "cnn_hf.bin")
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16
+# Useful FLOP of the 9 -> 32 -> 32 -> 32 -> 25 network of 3x3 convolutions per grid node
+CNN_FLOP_PER_NODE = 2 * 9 * (9 * 32 + 32 * 32 + 32 * 32 + 32 * 25)
 
 # Algorithmic bytes per finest-level node of each timed kernel (mixed
 # precision: FP64 stencil 72 B and FP64 u/f in the outer residual, FP32
@@ -114,6 +117,8 @@ def parse():
     ap.add_argument("--cpu-cycles", type=int, default=30, help="V-cycles in the oracle's timed sample")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--tune-reps", type=int, default=10, help="launches per tile shape in the autotuner")
+    ap.add_argument("--restart", type=int, default=30,
+                    help="restart length of the FGMRES comparison reported beside the headline (0: skip it)")
     ap.add_argument("--only", choices=["both", "cnn", "jacobi"], default="both",
                     help="profiling aid: run one smoother only (the JSON line then lacks the comparison)")
     ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2",
@@ -269,9 +274,55 @@ def main():
         "roofline": roofline,
     }
 
+    out["inference"] = inference_block(ctx_cnn, net, n)
+    if args.restart > 0:
+        out["fgmres"] = fgmres_block(args, ctx_cnn, ctx_jac, f, n)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, theta, eps, net, cnn_s["iters"], args.cpu_cycles)
     print(json.dumps(out), flush=True)
+
+
+def inference_block(ctx, net, n, reps=10):
+    """mg_smoother_infer (the network on every level but the coarsest, BF16 MFMA)
+    timed on its own: useful FLOP per second against the dense BF16 peak."""
+    import torch
+    nodes, m = 0, n
+    while m > 7:
+        nodes += m * m
+        m = (m - 1) // 2
+    ctx.infer(net)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.infer(net)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    flop = CNN_FLOP_PER_NODE * nodes
+    tflops = flop / (ms * 1e-3) / 1e12
+    return {"bound": "mfma", "ms_per_call": ms, "nodes": nodes, "flop": flop, "achieved": tflops,
+            "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / BF16_MFMA_PEAK_TFLOPS,
+            "note": "useful FLOP (halo recomputation not counted); wall time of the call, all levels"}
+
+
+def fgmres_block(args, ctx_cnn, ctx_jac, f, n):
+    """The same problem solved by flexible GMRES(restart) preconditioned by one
+    V(1,1) cycle per iteration (the paper's incorporation with FGMRES), to the
+    same tolerance: beside the headline, not part of it."""
+    import torch
+    out = {"restart": args.restart, "tol": args.tol}
+    for name, ctx in (("cnn", ctx_cnn), ("jacobi", ctx_jac)):
+        ctx.solve_fgmres([f], args.tol, 10, restart=args.restart)  # warm-up (workspace, code paths)
+        times = []
+        for _ in range(max(args.steps, 1)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = ctx.solve_fgmres([f], args.tol, args.maxit, restart=args.restart)
+            times.append((time.perf_counter() - t0) * 1e3)
+        ms = sum(times) / len(times)
+        out[name] = {"iters": int(res.iters[0]), "relres": float(res.relres[0]), "status": int(res.status[0]),
+                     "solve_ms": ms, "solve_device_ms": float(res.ms), "unknowns_per_s_solve": n * n / (ms * 1e-3)}
+        log(f"fgmres {name}: {int(res.iters[0])} iterations, relres {res.relres[0]:.2e}, {ms:.1f} ms")
+    return out
 
 
 def load_net(args):

@@ -156,6 +156,22 @@ mg_status mg_vcycle(mg_ctx ctx, const double *const *f, double *const *u);
 mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double rtol, int32_t maxit,
                    int32_t *iters, double *relres, int32_t *status, double *history);
 
+/* Flexible GMRES (section 6, incorporation with FGMRES): restarted FGMRES(m)
+ * on A u = f for every problem of the context (one after another), right-
+ * preconditioned by one cycle of mg_vcycle per iteration (the context's
+ * smoother, sweeps and precision; the flexible variant keeps each
+ * preconditioned direction, so a mixed-precision cycle is a valid
+ * preconditioner).  u_0 = 0; stops when the true FP64 relative residual
+ * ||f - A u|| / ||f|| <= rtol, or after maxit iterations (cycles).
+ * restart: m in [1, 256]; the context keeps 2m + 4 FP64 vectors of its
+ * largest finest grid (allocated on the first call, grown for a larger m).
+ * Host outputs as in mg_solve (each may be NULL): iters = preconditioner
+ * applications, relres = final true relative residual, status, history
+ * [nprob][maxit+1] = the GMRES residual estimate / ||f|| after each
+ * iteration (entry 0 = 1).  Synchronises. */
+mg_status mg_solve_fgmres(mg_ctx ctx, const double *const *f, double *const *u, double rtol, int32_t maxit,
+                          int32_t restart, int32_t *iters, double *relres, int32_t *status, double *history);
+
 /* Time of the last mg_solve's device work in milliseconds (HIP events). */
 mg_status mg_last_solve_ms(mg_ctx ctx, double *ms);
 

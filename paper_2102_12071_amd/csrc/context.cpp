@@ -58,6 +58,8 @@ mg_status upload_class(Arena &arena, const std::vector<S> &v, const std::vector<
     MG_TRY(arena.alloc(&sc.d_live, sizeof(S) * v.size()));
     sc.d_run = sc.d_slots;
     sc.nrun = sc.nslots;
+    sc.run_slots.resize(sc.nslots);
+    for (int s = 0; s < sc.nslots; ++s) sc.run_slots[s] = s;
     sc.live = sc.nslots > 0;
     return MG_OK;
 }
@@ -427,23 +429,24 @@ mg_status update_live(mg_ctx_s &c, const std::vector<char> &active)
 {
     bool changed = false;
     auto compact = [&](SizeClass &k) -> mg_status {
-        int cnt = 0;
-        for (int p : k.probs) cnt += active[p] != 0;
-        if (cnt == k.nrun && (cnt == k.nslots) == (k.d_run == k.d_slots)) return MG_OK;
+        std::vector<int> idx;
+        for (int s = 0; s < k.nslots; ++s)
+            if (active[k.probs[s]]) idx.push_back(s);
+        if (idx == k.run_slots) return MG_OK;
         changed = true;
+        const int cnt = (int)idx.size();
         k.live = cnt > 0;
+        k.run_slots = idx;
+        k.nrun = cnt;
         if (cnt == k.nslots) {
             k.d_run = k.d_slots;
-            k.nrun = k.nslots;
             return MG_OK;
         }
         std::vector<char> buf((size_t)cnt * k.slot_bytes);
-        int q = 0;
-        for (int s = 0; s < k.nslots; ++s)
-            if (active[k.probs[s]]) std::memcpy(&buf[(size_t)q++ * k.slot_bytes], &k.host_slots[(size_t)s * k.slot_bytes], k.slot_bytes);
+        for (int q = 0; q < cnt; ++q)
+            std::memcpy(&buf[(size_t)q * k.slot_bytes], &k.host_slots[(size_t)idx[q] * k.slot_bytes], k.slot_bytes);
         if (cnt > 0) MG_HIP(hipMemcpy(k.d_live, buf.data(), buf.size(), hipMemcpyHostToDevice));
         k.d_run = k.d_live;
-        k.nrun = cnt;
         return MG_OK;
     };
     for (SizeClass &k : c.classes) MG_TRY(compact(k));
@@ -468,6 +471,23 @@ mg_status ensure_graph(mg_ctx_s &c)
 }
 
 }  // namespace
+
+// Services of the context for the Krylov driver (krylov.cpp).
+namespace mg {
+mg_status ctx_check(mg_ctx c) { return check_ctx(c); }
+mg_status ctx_check_vectors(mg_ctx c, const double *const *f, double *const *u) { return check_vectors(c, f, u); }
+mg_status ctx_set_live(mg_ctx_s &c, const std::vector<char> &active) { return update_live(c, active); }
+void ctx_enqueue_cycle(mg_ctx_s &c, hipStream_t st)
+{
+    if (c.opt.precision == MG_PREC_FP64) {
+        enqueue_vcycle<double>(c, st);
+        enqueue_update<double>(c, st);
+    } else {
+        enqueue_vcycle<float>(c, st);
+        enqueue_update<float>(c, st);
+    }
+}
+}  // namespace mg
 
 extern "C" {
 

@@ -86,6 +86,7 @@ struct SizeClass {
     void *d_live = nullptr;        // room for the compacted copy
     void *d_run = nullptr;
     int nrun = 0;
+    std::vector<int> run_slots;    // which slots d_run holds, in order
     int tile[2] = {0, 0};     // workgroup shape of the fused descent and ascent
     double tile_ms[2][8] = {};  // time per launch of each shape at the last autotuning (0: not timed)
 };
@@ -112,6 +113,16 @@ struct mg_net_s {
     std::vector<char> host_desc;  // source of the last asynchronous descriptor upload
 };
 
+namespace mg {
+// Services of the solver context used by the Krylov driver (context.cpp).
+mg_status ctx_check(mg_ctx c);
+mg_status ctx_check_vectors(mg_ctx c, const double *const *f, double *const *u);
+// Launches only the slots of the given problems from now on (see update_live).
+mg_status ctx_set_live(mg_ctx_s &c, const std::vector<char> &active);
+// Enqueues e = V(r) of the live problems: level-0 r in, u += e on the finest level.
+void ctx_enqueue_cycle(mg_ctx_s &c, hipStream_t st);
+}  // namespace mg
+
 struct mg_ctx_s {
     mg::StreamJoin join;
     mg::Arena arena;
@@ -136,4 +147,9 @@ struct mg_ctx_s {
     // CNN inference scratch (direct path)
     void *cnn_scratch = nullptr;
     size_t cnn_scratch_bytes = 0;
+    // flexible-GMRES workspace: 2 * restart + 3 FP64 vectors of the largest
+    // finest grid, partial sums and small coefficient arrays
+    double *kr_vec = nullptr;
+    double *kr_small = nullptr;
+    int kr_restart = 0;
 };

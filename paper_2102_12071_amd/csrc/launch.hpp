@@ -30,6 +30,23 @@ void launch_ascend(const CycleSlot<T> *slots, int nslots, int n, bool cnn, doubl
 // "32x8 coarse nodes, 512 threads" and the like (kernel 0: descent, 1: ascent).
 const char *tile_name(int kernel, int tile);
 
+// ---- krylov.hip: FP64 vectors of the flexible-GMRES solver (finest grid, pitch P) ----
+constexpr int kKrylovBlocks = 256;  // partial sums per dot product
+// y = b + sign * A x (b may be null)
+void launch_kr_apply(int n, int P, int64_t plane, const double *A, const double *x, const double *b, double sign,
+                     double *y, hipStream_t st);
+// out[v] = <w, V_v> for v < nv (V_v = V + v * vstride), or sqrt of it when root; partial: nv * kKrylovBlocks
+void launch_kr_dots(int n, int P, const double *w, const double *V, int64_t vstride, int nv, double *partial,
+                    double *out, int root, hipStream_t st);
+// w -= sum_v coef[v] V_v (coef on the device)
+void launch_kr_update(int n, int P, double *w, const double *V, int64_t vstride, int nv, const double *coef,
+                      hipStream_t st);
+// y = x / *d
+void launch_kr_scale(int n, int P, const double *x, const double *d, double *y, hipStream_t st);
+// u += sum_k coef[k] Z_k
+void launch_kr_combine(int n, int P, double *u, const double *Z, int64_t vstride, int nz, const double *coef,
+                       hipStream_t st);
+
 // ---- cycle.hip: V-cycle kernels (T = float: mixed precision; double: FP64) ----
 // Every launcher covers one size class (all slots share n); blocks of
 // problems that are no longer active return at once.

@@ -83,6 +83,8 @@ SIGNATURES = {
     "mg_vcycle": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "mg_solve": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_double, C.c_int32, _c_ip,
                            _c_dp, _c_ip, _c_dp]),
+    "mg_solve_fgmres": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_double, C.c_int32,
+                                  C.c_int32, _c_ip, _c_dp, _c_ip, _c_dp]),
     "mg_last_solve_ms": (C.c_int, [C.c_void_p, _c_dp]),
     "mg_restencil": (C.c_int, [C.c_void_p, C.POINTER(Problem)]),
     "mg_time_kernels": (C.c_int, [C.c_void_p, C.c_int32, _c_dp]),
@@ -331,6 +333,29 @@ class Context:
                                      iters.ctypes.data_as(_c_ip), relres.ctypes.data_as(_c_dp),
                                      status.ctypes.data_as(_c_ip),
                                      hist.ctypes.data_as(_c_dp) if history else None)
+        _check(st, allow=(MG_OK, MG_NOT_CONVERGED, MG_ERR_DIVERGED))
+        ms = C.c_double()
+        _check(load_library().mg_last_solve_ms(self._h, C.byref(ms)))
+        return SolveResult(u=list(u), iters=iters, relres=relres, status=status, history=hist, ms=ms.value)
+
+    def solve_fgmres(self, f: Sequence[torch.Tensor], rtol: float, maxit: int, restart: int = 30,
+                     history: bool = False, u: Optional[Sequence[torch.Tensor]] = None) -> SolveResult:
+        """Flexible GMRES(restart) preconditioned by one V-cycle per iteration (u_0 = 0)."""
+        f = self._vecs(f, "f")
+        if u is None:
+            u = [torch.empty((n, n), dtype=torch.float64, device="cuda") for n in self.ns]
+        else:
+            u = self._vecs(u, "u")
+        fp = (C.c_void_p * self.nprob)(*[x.data_ptr() for x in f])
+        up = (C.c_void_p * self.nprob)(*[x.data_ptr() for x in u])
+        iters = np.zeros(self.nprob, dtype=np.int32)
+        relres = np.zeros(self.nprob, dtype=np.float64)
+        status = np.zeros(self.nprob, dtype=np.int32)
+        hist = np.zeros((self.nprob, maxit + 1), dtype=np.float64) if history else None
+        st = load_library().mg_solve_fgmres(self._h, fp, up, float(rtol), int(maxit), int(restart),
+                                            iters.ctypes.data_as(_c_ip), relres.ctypes.data_as(_c_dp),
+                                            status.ctypes.data_as(_c_ip),
+                                            hist.ctypes.data_as(_c_dp) if history else None)
         _check(st, allow=(MG_OK, MG_NOT_CONVERGED, MG_ERR_DIVERGED))
         ms = C.c_double()
         _check(load_library().mg_last_solve_ms(self._h, C.byref(ms)))

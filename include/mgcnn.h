@@ -98,6 +98,12 @@ typedef struct {
                                FP64 outer residual, norms and coarsest solve (default)        */
     int32_t use_graph;      /* 1: capture one solver iteration as a HIP graph and replay it    */
     int32_t check_every;    /* iterations between host convergence checks in mg_solve (0 = 16) */
+    int32_t fallback;       /* 1: in mg_solve with MG_SMOOTHER_CNN, a problem whose residual has not
+                               improved on its best by 0.1 % for 16 cycles, or has grown to 100 times
+                               its best, is switched to damped Jacobi: its smoother fields are
+                               overwritten with omega / a_C (u restarts from 0 after a divergence,
+                               continues otherwise).  mg_last_fallbacks tells which; a later CNN
+                               solve needs mg_smoother_infer again.  0 (default): off. */
 } mg_options;
 
 /* Fills the defaults listed above. */
@@ -171,6 +177,10 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
  * iteration (entry 0 = 1).  Synchronises. */
 mg_status mg_solve_fgmres(mg_ctx ctx, const double *const *f, double *const *u, double rtol, int32_t maxit,
                           int32_t restart, int32_t *iters, double *relres, int32_t *status, double *history);
+
+/* Per problem: 1 if the last mg_solve switched it from the learned smoother
+ * to damped Jacobi (mg_options.fallback), else 0.  flags: host [nprob]. */
+mg_status mg_last_fallbacks(mg_ctx ctx, int32_t *flags);
 
 /* Time of the last mg_solve's device work in milliseconds (HIP events). */
 mg_status mg_last_solve_ms(mg_ctx ctx, double *ms);

@@ -154,6 +154,7 @@ void mg_options_default(mg_options *opt)
     opt->precision = MG_PREC_MIXED;
     opt->use_graph = 1;
     opt->check_every = 16;
+    opt->fallback = 0;
 }
 
 void mg_train_opts_default(mg_train_opts *o)

@@ -85,6 +85,21 @@ __global__ void k_set_smoother(int n, int P, int64_t plane, const double *W, int
     for (int k = 0; k < kSmoother; ++k) store_h(H + k * plane + p, (T)(W[k * planew + (int64_t)j * Pw + i] / ac));
 }
 
+// Damped Jacobi as a 5x5 smoother field: W = omega * delta_0, so H = W / a_C
+// holds omega / a_C at the centre tap and zero elsewhere (the fallback of a
+// problem whose learned smoother stalls or diverges).
+template <typename T>
+__global__ void k_jacobi_smoother(int n, int P, int64_t plane, const double *A64, double omega,
+                                  typename SmootherStore<T>::type *H)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= n || j >= n) return;
+    const int64_t p = (int64_t)j * P + i;
+    const double ac = A64[kCentre * plane + p];
+    for (int k = 0; k < kSmoother; ++k) store_h(H + k * plane + p, (T)(k == kSmoother / 2 ? omega / ac : 0.0));
+}
+
 template <typename T>
 __global__ void k_get_smoother(int n, int P, int64_t plane, const typename SmootherStore<T>::type *H,
                                const double *A64, double *W, int Pw, int64_t planew)
@@ -139,6 +154,14 @@ void launch_set_smoother(int n, int P, int64_t plane, const double *W, int Pw, i
 }
 
 template <typename T>
+void launch_jacobi_smoother(int n, int P, int64_t plane, const double *A64, double omega,
+                            typename SmootherStore<T>::type *H, hipStream_t st)
+{
+    dim3 blk(64, 4);
+    k_jacobi_smoother<T><<<grid2(n, blk), blk, 0, st>>>(n, P, plane, A64, omega, H);
+}
+
+template <typename T>
 void launch_get_smoother(int n, int P, int64_t plane, const typename SmootherStore<T>::type *H,
                          const double *A64, double *W, int Pw, int64_t planew, hipStream_t st)
 {
@@ -160,7 +183,9 @@ void launch_f32_to_f64(int64_t count, const float *src, double *dst, hipStream_t
     template void launch_set_smoother<T>(int, int, int64_t, const double *, int, int64_t, const double *,         \
                                          typename SmootherStore<T>::type *, hipStream_t);                         \
     template void launch_get_smoother<T>(int, int, int64_t, const typename SmootherStore<T>::type *,              \
-                                         const double *, double *, int, int64_t, hipStream_t);
+                                         const double *, double *, int, int64_t, hipStream_t);                     \
+    template void launch_jacobi_smoother<T>(int, int, int64_t, const double *, double,                            \
+                                            typename SmootherStore<T>::type *, hipStream_t);
 MG_INSTANTIATE(float)
 MG_INSTANTIATE(double)
 #undef MG_INSTANTIATE

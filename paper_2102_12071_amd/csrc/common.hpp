@@ -159,11 +159,21 @@ struct BottomSlot {
 struct SolveState {
     int active;      // 1 while the problem still iterates
     int iters;       // V-cycles applied
-    int status;      // 0 running/converged, 1 not converged, -4 diverged
+    int status;      // 0 running/converged, 1 not converged, -4 diverged, 2 paused for the fallback
     int nparts;      // number of partial sums of the outer residual
     double fnorm;    // ||f||_2
     double relres;   // last relative residual
+    double best;     // smallest relative residual so far
+    int stall;       // cycles since best last improved by kStallGain
+    int fallback;    // 0 none; 1 requested (stalled), 3 requested (diverged); 2 switched to damped Jacobi
 };
+
+// Fallback of the learned smoother to damped Jacobi: a problem whose residual
+// has not improved on its best by 0.1 % for kStallCycles cycles, or has grown
+// to kDivergeFactor times its best, is paused and switched.
+constexpr int kStallCycles = 16;
+constexpr double kStallGain = 1e-3;
+constexpr double kDivergeFactor = 1e2;
 
 // Stopping-rule parameters of one mg_solve call (read by the check kernel so
 // that a captured iteration graph does not depend on them).
@@ -172,6 +182,7 @@ struct SolveParams {
     int maxit;
     int hist_stride;
     double *history;  // [nprob][hist_stride] or null
+    int fallback;     // 1: a stalled or diverging learned smoother requests the switch to damped Jacobi
 };
 
 }  // namespace mg

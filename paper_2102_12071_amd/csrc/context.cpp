@@ -261,6 +261,7 @@ mg_status validate_options(const mg_options &o)
     if (o.precision != MG_PREC_FP64 && o.precision != MG_PREC_MIXED)
         return set_error(MG_ERR_ARG, "precision must be MG_PREC_FP64 or MG_PREC_MIXED");
     if (o.check_every < 0) return set_error(MG_ERR_ARG, "check_every must be >= 0");
+    if (o.fallback != 0 && o.fallback != 1) return set_error(MG_ERR_ARG, "fallback must be 0 or 1");
     return MG_OK;
 }
 
@@ -647,6 +648,8 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
     prm.maxit = maxit;
     prm.hist_stride = stride;
     prm.history = history ? c.d_history : nullptr;
+    prm.fallback = c.opt.fallback && c.opt.smoother == MG_SMOOTHER_CNN;
+    c.fell_back.assign(c.nprob, 0);
     MG_HIP(hipMemcpyAsync(c.d_params, &prm, sizeof prm, hipMemcpyHostToDevice, st));
     // ||f||: the residual of u = 0
     launch_activate(c.d_state, c.nprob, st);
@@ -672,6 +675,33 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
         replays += every;
         MG_HIP(hipMemcpyAsync(hs.data(), c.d_state, sizeof(SolveState) * c.nprob, hipMemcpyDeviceToHost, st));
         MG_HIP(hipStreamSynchronize(st));
+        // problems paused by the fallback rule: damped Jacobi from now on
+        bool resumed = false;
+        for (int p = 0; p < c.nprob; ++p) {
+            SolveState &s = hs[p];
+            if (s.status != 2 || (s.fallback != 1 && s.fallback != 3)) continue;
+            const ProbBuf &pb = c.probs[p];
+            for (int l = 0; l + 1 < pb.nlev; ++l) {
+                const LevelBuf &L = pb.lev[l];
+                if (c.opt.precision == MG_PREC_FP64)
+                    launch_jacobi_smoother<double>(L.n, L.P, L.plane, L.A64, c.opt.omega, (double *)L.H, st);
+                else
+                    launch_jacobi_smoother<float>(L.n, L.P, L.plane, L.A64, c.opt.omega, (bf16_t *)L.H, st);
+            }
+            const bool restart = s.fallback == 3;  // after a divergence u is no starting point
+            if (restart) launch_zero_f64(pb.u, pb.lev[0].plane, st);
+            s.best = restart ? 1.0 : s.relres;
+            s.stall = 0;
+            s.fallback = 2;
+            s.status = 0;
+            s.active = 1;
+            c.fell_back[p] = 1;
+            resumed = true;
+        }
+        if (resumed) {
+            MG_HIP(hipMemcpyAsync(c.d_state, hs.data(), sizeof(SolveState) * c.nprob, hipMemcpyHostToDevice, st));
+            MG_HIP(hipStreamSynchronize(st));
+        }
         bool any = false;
         for (int p = 0; p < c.nprob; ++p) {
             act[p] = hs[p].active != 0;
@@ -690,8 +720,10 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
     MG_HIP(hipMemcpy(hs.data(), c.d_state, sizeof(SolveState) * c.nprob, hipMemcpyDeviceToHost));
     if (history) MG_HIP(hipMemcpy(history, c.d_history, sizeof(double) * c.nprob * stride, hipMemcpyDeviceToHost));
     mg_status agg = MG_OK;
+    for (int p = 0; p < c.nprob; ++p)
+        if (c.fell_back[p]) c.smoother_ready = false;  // the learned smoother was overwritten
     for (int p = 0; p < c.nprob; ++p) {
-        int stt = hs[p].active ? MG_NOT_CONVERGED : hs[p].status;
+        int stt = hs[p].active || hs[p].status == 2 ? MG_NOT_CONVERGED : hs[p].status;
         if (iters) iters[p] = hs[p].iters;
         if (relres) relres[p] = hs[p].relres;
         if (status) status[p] = stt;
@@ -700,6 +732,15 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
     }
     MG_TRY(c.join.leave());
     return agg;
+}
+
+mg_status mg_last_fallbacks(mg_ctx ctx, int32_t *flags)
+{
+    clear_error();
+    MG_TRY(check_ctx(ctx));
+    if (!flags) return set_error(MG_ERR_ARG, "flags is null");
+    for (int p = 0; p < ctx->nprob; ++p) flags[p] = p < (int)ctx->fell_back.size() ? ctx->fell_back[p] : 0;
+    return MG_OK;
 }
 
 mg_status mg_last_solve_ms(mg_ctx ctx, double *ms)

@@ -94,9 +94,22 @@ __device__ inline void stopping_rule(SolveState &st, double rr, const SolveParam
     const double rel = st.fnorm > 0.0 ? sqrt(rr) / st.fnorm : 0.0;
     st.relres = rel;
     if (prm->history) prm->history[(int64_t)prob * prm->hist_stride + st.iters] = rel;
+    if (rel < st.best * (1.0 - kStallGain)) {
+        st.best = rel;
+        st.stall = 0;
+    } else {
+        st.stall += 1;
+    }
+    const bool diverging = !isfinite(rel) || rel > kDivergeFactor * st.best;
     if (rel <= prm->tol) {
         st.active = 0;
         st.status = 0;
+    } else if (prm->fallback && st.fallback == 0 && (diverging || st.stall >= kStallCycles) &&
+               st.iters < prm->maxit) {
+        // pause (no cycle is applied); the host switches the problem to damped Jacobi and resumes it
+        st.active = 0;
+        st.status = 2;
+        st.fallback = diverging ? 3 : 1;
     } else if (!isfinite(rel) || rel > 1e3) {
         st.active = 0;
         st.status = -4;
@@ -128,6 +141,9 @@ __global__ void __launch_bounds__(kThreads)
         st.status = 0;
         st.active = 1;
         st.relres = 1.0;
+        st.best = 1.0;
+        st.stall = 0;
+        st.fallback = 0;
         return;
     }
     stopping_rule(st, rr, prm, s.prob);

@@ -149,6 +149,7 @@ struct mg_ctx_s {
     size_t cnn_scratch_bytes = 0;
     // flexible-GMRES workspace: 2 * restart + 3 FP64 vectors of the largest
     // finest grid, partial sums and small coefficient arrays
+    std::vector<int> fell_back;          // per problem: the last mg_solve switched it to damped Jacobi
     double *kr_vec = nullptr;
     double *kr_small = nullptr;
     int kr_restart = 0;

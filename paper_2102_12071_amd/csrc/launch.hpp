@@ -111,6 +111,10 @@ void launch_cnn_fused_mfma(int n, int P, int64_t plane, const float *A32, const 
 template <typename T>
 void launch_set_smoother(int n, int P, int64_t plane, const double *W, int Pw, int64_t planew, const double *A64,
                          typename SmootherStore<T>::type *H, hipStream_t st);
+// Damped Jacobi written as the smoother field (H = omega / a_C at the centre tap).
+template <typename T>
+void launch_jacobi_smoother(int n, int P, int64_t plane, const double *A64, double omega,
+                            typename SmootherStore<T>::type *H, hipStream_t st);
 template <typename T>
 void launch_get_smoother(int n, int P, int64_t plane, const typename SmootherStore<T>::type *H,
                          const double *A64, double *W, int Pw, int64_t planew, hipStream_t st);

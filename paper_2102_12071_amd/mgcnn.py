@@ -51,7 +51,7 @@ class Problem(C.Structure):
 class COptions(C.Structure):
     _fields_ = [("smoother", C.c_int32), ("nu_pre", C.c_int32), ("nu_post", C.c_int32), ("omega", C.c_double),
                 ("coarsest_n", C.c_int32), ("precision", C.c_int32), ("use_graph", C.c_int32),
-                ("check_every", C.c_int32)]
+                ("check_every", C.c_int32), ("fallback", C.c_int32)]
 
 
 class NetDesc(C.Structure):
@@ -86,6 +86,7 @@ SIGNATURES = {
     "mg_solve_fgmres": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_double, C.c_int32,
                                   C.c_int32, _c_ip, _c_dp, _c_ip, _c_dp]),
     "mg_last_solve_ms": (C.c_int, [C.c_void_p, _c_dp]),
+    "mg_last_fallbacks": (C.c_int, [C.c_void_p, _c_ip]),
     "mg_restencil": (C.c_int, [C.c_void_p, C.POINTER(Problem)]),
     "mg_time_kernels": (C.c_int, [C.c_void_p, C.c_int32, _c_dp]),
     "mg_kernel_name": (C.c_char_p, [C.c_int32]),
@@ -188,10 +189,11 @@ class Options:
     precision: int = PREC_MIXED
     use_graph: int = 1
     check_every: int = 16
+    fallback: int = 0
 
     def to_c(self) -> COptions:
         return COptions(self.smoother, self.nu_pre, self.nu_post, self.omega, self.coarsest_n, self.precision,
-                        self.use_graph, self.check_every)
+                        self.use_graph, self.check_every, self.fallback)
 
 
 @dataclass
@@ -337,6 +339,12 @@ class Context:
         ms = C.c_double()
         _check(load_library().mg_last_solve_ms(self._h, C.byref(ms)))
         return SolveResult(u=list(u), iters=iters, relres=relres, status=status, history=hist, ms=ms.value)
+
+    def fallbacks(self) -> np.ndarray:
+        """Per problem: 1 if the last solve switched it to damped Jacobi."""
+        out = np.zeros(self.nprob, dtype=np.int32)
+        _check(load_library().mg_last_fallbacks(self._h, out.ctypes.data_as(_c_ip)))
+        return out
 
     def solve_fgmres(self, f: Sequence[torch.Tensor], rtol: float, maxit: int, restart: int = 30,
                      history: bool = False, u: Optional[Sequence[torch.Tensor]] = None) -> SolveResult:

@@ -42,7 +42,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_binding_structs_match_header_sizes():
     from paper_2102_12071_amd import mgcnn
-    assert C.sizeof(mgcnn.COptions) == 40
+    assert C.sizeof(mgcnn.COptions) == 48
     assert C.sizeof(mgcnn.Problem) == 16
     assert C.sizeof(mgcnn.TrainOpts) == 32
 

@@ -50,6 +50,7 @@ def _load():
         "ora_smooth_jacobi": (None, [C.c_int, _dp, C.c_double, _dp, _dp]),
         "ora_smooth_stencil5": (None, [C.c_int, _dp, _dp, _dp, _dp]),
         "ora_apply_smoother5": (None, [C.c_int, _dp, _dp, _dp, _dp]),
+        "ora_cnn_vjp": (None, [C.c_int, _dp, C.c_int, _ip, _dp, _dp, _dp]),
         "ora_mg_create": (C.c_void_p, [C.c_int, _dp, C.c_int]),
         "ora_mg_destroy": (None, [C.c_void_p]),
         "ora_mg_num_levels": (C.c_int, [C.c_void_p]),
@@ -260,6 +261,15 @@ def cnn_forward(A, params, channels=CNN_CHANNELS, omega: float = OMEGA) -> np.nd
     W = np.empty((channels[-1], n, n))
     _load().ora_cnn_forward(n, _p(A), len(channels) - 1, _ip_of(ch), _p(prm), float(omega), _p(W))
     return W
+
+
+def cnn_vjp(A, params, dW, channels=CNN_CHANNELS) -> np.ndarray:
+    """Gradient with respect to the parameters of <dW, W(params)> for one problem."""
+    A, prm, dW = _f64(A), _f64(params), _f64(dW)
+    ch = _ints(channels)
+    g = np.zeros(prm.size)
+    _load().ora_cnn_vjp(A.shape[1], _p(A), len(channels) - 1, _ip_of(ch), _p(prm), _p(dW), _p(g))
+    return g
 
 
 def hf_loss(stencils, vectors, params, channels=CNN_CHANNELS, omega: float = OMEGA, grad: bool = True):

@@ -153,6 +153,19 @@ static void cnn_backward(int n, int nlayers, const int *ch, const double *params
     free(dpre);
 }
 
+void ora_cnn_vjp(int n, const double *A, int nlayers, const int *ch, const double *params, const double *dW,
+                 double *grad)
+{
+    const int64_t nn = (int64_t)n * n;
+    double *x0 = (double *)malloc_or_die(sizeof(double) * 9 * nn);
+    double *pre[16];
+    for (int l = 0; l < nlayers; ++l) pre[l] = (double *)malloc_or_die(sizeof(double) * ch[l + 1] * nn);
+    cnn_forward_store(n, A, nlayers, ch, params, x0, pre);
+    cnn_backward(n, nlayers, ch, params, x0, pre, dW, grad);
+    for (int l = 0; l < nlayers; ++l) free(pre[l]);
+    free(x0);
+}
+
 double ora_hf_loss(int B, const int *ns, const double *const *A, const double *const *V, int J,
                    int nlayers, const int *ch, const double *params, double omega, double *grad)
 {

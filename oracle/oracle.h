@@ -138,6 +138,12 @@ void ora_cnn_forward(int n, const double *A, int nlayers, const int *ch,
  * H_b the per-point smoother produced by the CNN from A_b.
  * ns[b] grid sizes, A[b] stencil fields, V[b] = J vectors [J][n_b*n_b].
  * grad (may be NULL) receives dL/dparams. Returns L. */
+/* Vector-Jacobian product of the network: grad += (dW/dparams)^T dW for one
+ * problem (A: [9][n][n]; dW: [25][n][n], the gradient of a loss with respect
+ * to the network's output W; the omega delta_0 term has no parameters). */
+void ora_cnn_vjp(int n, const double *A, int nlayers, const int *ch, const double *params, const double *dW,
+                 double *grad);
+
 double ora_hf_loss(int B, const int *ns, const double *const *A,
                    const double *const *V, int J, int nlayers, const int *ch,
                    const double *params, double omega, double *grad);

@@ -137,6 +137,12 @@ mg_status mg_get_stencil(mg_ctx ctx, int32_t prob, int32_t level, double *out);
  * every operation is FP64.  Required before solving with MG_SMOOTHER_CNN. */
 mg_status mg_smoother_infer(mg_ctx ctx, mg_net net);
 
+/* Runs the network on the smoothing levels of size n only (every problem),
+ * leaving the other levels' smoothers as they are: per-level networks, each
+ * trained for one level size (the adaptive training of section 3.3 yields one
+ * network per level).  MG_ERR_ARG if no level above the coarsest has size n. */
+mg_status mg_smoother_infer_size(mg_ctx ctx, mg_net net, int32_t n);
+
 /* Installs an explicit smoother field W for one level (device [25][n_l][n_l]
  * FP64; stored as the context's precision).  Replaces what inference gave. */
 mg_status mg_set_smoother(mg_ctx ctx, int32_t prob, int32_t level, const double *W);
@@ -275,6 +281,52 @@ void mg_train_opts_default(mg_train_opts *o);
  * receives dL/dparams.  Synchronises when either is requested. */
 mg_status mg_train_step(mg_net net, const mg_train_batch *b, const mg_train_opts *o, float *loss,
                         float *grad);
+
+/* ------------------------------------------------------------------------ */
+/* Adaptive training (section 3.3, Algorithm 2).                              */
+/* ------------------------------------------------------------------------ */
+
+/* The field of the transposed smoother: for the smoother H = W / a_C of
+ * stencil A, WT with (WT / a_C) = H^T, i.e.
+ *   WT_p[k] = a_C(p) W_{p+off(k)}[24-k] / a_C(p+off(k))  (0 where p+off(k) is
+ * off the grid).  A: device [9][n][n], W, WT: device [25][n][n] FP64, W != WT. */
+mg_status mg_smoother_transpose(int32_t n, const double *A, const double *W, double *WT, void *stream);
+
+typedef struct {
+    int32_t nprob;                /* B: the number of problems of the contexts             */
+    const int32_t *k;             /* host [B]: cycles k_b of the loss, 1..64               */
+    const double *const *f;       /* host [B] device pointers, [n][n] FP64 right-hand sides */
+    const double *const *u0;      /* host [B] device pointers, [n][n] FP64 initial guesses  */
+    const double *const *u_star;  /* host [B] device pointers, [n][n] FP64 exact solutions  */
+    double *const *dW;            /* NULL, or host [B] device pointers, [25][n][n] FP64,
+                                     receiving dL/dW_b (FP64) */
+} mg_alpha_batch;
+
+/* One step of the adaptive training of the network on the finest level of
+ * the contexts (Algorithm 2): the loss
+ *   L = (1/B) sum_b || Phi(u0_b, f_b, k_b) - u*_b ||_2,
+ * Phi being k_b cycles of pre-smoothing with the network's smoother H (FP64
+ * inference from the current parameters), coarse correction P Psi_c R with
+ * one cycle Psi_c of the fixed coarser hierarchy, and post-smoothing with H;
+ * the gradient dL/dparams by the adjoint of those cycles (FP64 down to dL/dW,
+ * then the network backward in FP32); and an Adam update if o->apply_update.
+ * top: FP64 context whose problems all have the same n > coarsest_n; its
+ *   finest-level smoother is overwritten by the network's.
+ * coarse: FP64 context of the level-1 stencils of top's problems (same order,
+ *   mg_get_stencil(top, b, 1)), same coarsest_n, nu_pre == nu_post, with the
+ *   fixed smoothers installed (mg_smoother_infer_size / mg_set_smoother, or
+ *   damped Jacobi).  Its cycle is Psi_c.
+ * coarse_t: like coarse with every smoother transposed (mg_smoother_transpose),
+ *   so that its cycle is Psi_c^T; may be coarse itself when coarse's smoothers
+ *   are symmetric (damped Jacobi).
+ * o: precision must be 0; o->omega is not used (the network output's Jacobi
+ *   term takes top's mg_options.omega).
+ * Outputs (host, each may be NULL): loss, losses[B] (the unscaled norms),
+ * grad[num_params] (dL/dparams).  Runs on top's stream; leaves the coarse
+ * contexts' vectors undefined.  MG_ERR_DIVERGED (parameters unchanged) if a
+ * norm is not finite.  Synchronises. */
+mg_status mg_alpha_step(mg_ctx top, mg_ctx coarse, mg_ctx coarse_t, mg_net net, const mg_alpha_batch *b,
+                        const mg_train_opts *o, double *loss, double *losses, float *grad);
 
 /* ------------------------------------------------------------------------ */
 const char *mg_status_str(mg_status s);

@@ -1026,12 +1026,13 @@ mg_status net_pack_mfma(mg_net net, hipStream_t st);  // net.cpp
 
 }  // namespace mg
 
-extern "C" mg_status mg_smoother_infer(mg_ctx ctx, mg_net net)
+namespace mg {
+
+// Runs the network on the smoothing levels of size n (every size when n == 0)
+// of every problem, on stream st after the network's pending work; count
+// receives the number of levels computed.
+mg_status ctx_infer(mg_ctx_s &c, mg_net net, int n, hipStream_t st, int *count)
 {
-    clear_error();
-    MG_TRY(check_ctx(ctx));
-    if (!net) return set_error(MG_ERR_ARG, "net is null");
-    mg_ctx_s &c = *ctx;
     const bool fp64 = c.opt.precision == MG_PREC_FP64;
     // FP64 (direct path) scratch: input (9) + two ping-pong activation buffers (32 each) on the
     // largest level; the fused MFMA path keeps its activations in LDS
@@ -1044,24 +1045,53 @@ extern "C" mg_status mg_smoother_infer(mg_ctx ctx, mg_net net)
             c.cnn_scratch_bytes = need;
         }
     }
-    MG_TRY(c.join.enter());
-    hipStream_t st = c.join.internal;
     MG_HIP(hipEventRecord(net->join.ev, net->join.internal));
     MG_HIP(hipStreamWaitEvent(st, net->join.ev, 0));
     if (fp64)
         MG_TRY(net_params64(net, st));
     else
         MG_TRY(net_pack_mfma(net, st));
+    int done = 0;
     for (ProbBuf &pb : c.probs) {
         for (int l = 0; l + 1 < pb.nlev; ++l) {
             const LevelBuf &L = pb.lev[l];
+            if (n != 0 && L.n != n) continue;
             if (fp64)
                 MG_TRY(infer_level_direct<double>(c, L, net->params64, net->ch, (double *)c.cnn_scratch, st));
             else
                 launch_cnn_fused_mfma(L.n, L.P, L.plane, L.A32, net->packed, c.opt.omega, (bf16_t *)L.H, st);
+            ++done;
         }
     }
     MG_HIP(hipGetLastError());
-    c.smoother_ready = true;
-    return c.join.leave();
+    if (count) *count = done;
+    return MG_OK;
+}
+
+}  // namespace mg
+
+extern "C" mg_status mg_smoother_infer(mg_ctx ctx, mg_net net)
+{
+    clear_error();
+    MG_TRY(check_ctx(ctx));
+    if (!net) return set_error(MG_ERR_ARG, "net is null");
+    MG_TRY(ctx->join.enter());
+    MG_TRY(ctx_infer(*ctx, net, 0, ctx->join.internal, nullptr));
+    ctx->smoother_ready = true;
+    return ctx->join.leave();
+}
+
+extern "C" mg_status mg_smoother_infer_size(mg_ctx ctx, mg_net net, int32_t n)
+{
+    clear_error();
+    MG_TRY(check_ctx(ctx));
+    if (!net) return set_error(MG_ERR_ARG, "net is null");
+    bool found = false;
+    for (const ProbBuf &pb : ctx->probs)
+        for (int l = 0; l + 1 < pb.nlev; ++l) found = found || pb.lev[l].n == n;
+    if (!found) return set_error(MG_ERR_ARG, "no smoothing level of size %d in this context", n);
+    MG_TRY(ctx->join.enter());
+    MG_TRY(ctx_infer(*ctx, net, n, ctx->join.internal, nullptr));
+    ctx->smoother_ready = true;
+    return ctx->join.leave();
 }

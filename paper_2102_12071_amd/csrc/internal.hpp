@@ -121,6 +121,16 @@ mg_status ctx_check_vectors(mg_ctx c, const double *const *f, double *const *u);
 mg_status ctx_set_live(mg_ctx_s &c, const std::vector<char> &active);
 // Enqueues e = V(r) of the live problems: level-0 r in, u += e on the finest level.
 void ctx_enqueue_cycle(mg_ctx_s &c, hipStream_t st);
+// Network inference on the smoothing levels of size n (0: all) of every problem, on st.
+mg_status ctx_infer(mg_ctx_s &c, mg_net net, int n, hipStream_t st, int *count);
+
+// Training services of the network (train.cpp).  net_backward_ext: FP32
+// forward and backward with the output gradient dL/dy given per problem
+// (dout[b]: device [25][n_b*n_b]), writing dL/dparams to net.grad.
+mg_status net_backward_ext(mg_net_s &net, int B, const int *n, const double *const *stencil,
+                           const float *const *dout, hipStream_t st);
+void net_adam(mg_net_s &net, const mg_train_opts &o, hipStream_t st);
+mg_status check_train_opts(const mg_train_opts &o);
 }  // namespace mg
 
 struct mg_ctx_s {
@@ -153,4 +163,9 @@ struct mg_ctx_s {
     double *kr_vec = nullptr;
     double *kr_small = nullptr;
     int kr_restart = 0;
+    // adaptive-training (Algorithm 2) workspace, grown on demand; al_host
+    // stages the small tables uploaded with each step
+    void *al_ws = nullptr;
+    size_t al_bytes = 0;
+    std::vector<char> al_host;
 };

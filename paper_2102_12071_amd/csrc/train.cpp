@@ -77,9 +77,11 @@ mg_status upload_desc(mg_net_s &net, const std::vector<D> &desc, D *d_desc, hipS
     return MG_OK;
 }
 
-// FP32 path: planar activations, direct convolutions.
+// FP32 path: planar activations, direct convolutions.  ext: the output
+// gradient dL/dy is given (b->vectors[q]: [25][n*n] per problem, nvec = 0)
+// instead of coming from the high-frequency loss.
 mg_status step_fp32(mg_net_s &net, const mg_train_batch *b, const mg_train_opts &o, float *loss_part, float *d_loss,
-                    hipStream_t st)
+                    hipStream_t st, bool ext = false)
 {
     const int B = b->nprob, J = b->nvec;
     Layout lay;
@@ -121,11 +123,15 @@ mg_status step_fp32(mg_net_s &net, const mg_train_batch *b, const mg_train_opts 
     TrainProb *d_desc = (TrainProb *)(base + off_desc);
     float *wpart = (float *)(base + off_wpart);
     MG_TRY(upload_desc(net, desc, d_desc, st));
-    const float scale = 1.0f / ((float)B * (float)J);
+    const float scale = J > 0 ? 1.0f / ((float)B * (float)J) : 0.0f;
     for (const Cls &c : classes) launch_tr_input(d_desc + c.first, c.count, c.n, st);
     for (int l = 0; l < 4; ++l)
         for (const Cls &c : classes) launch_tr_conv_fwd(d_desc + c.first, c.count, c.n, net.params, layers[l], l, st);
     for (const Cls &c : classes) {
+        if (ext) {
+            launch_tr_dout_ext(d_desc + c.first, c.count, c.n, st);
+            continue;
+        }
         launch_tr_av(d_desc + c.first, c.count, c.n, J, st);
         launch_tr_residual_norm(d_desc + c.first, c.count, J, (float)o.omega, loss_part, st);
         launch_tr_dout(d_desc + c.first, c.count, c.n, J, scale, st);
@@ -253,6 +259,38 @@ mg_status step_bf16(mg_net_s &net, const mg_train_batch *b, const mg_train_opts 
 
 }  // namespace
 
+namespace mg {
+
+mg_status net_backward_ext(mg_net_s &net, int B, const int *n, const double *const *stencil,
+                           const float *const *dout, hipStream_t st)
+{
+    const mg_train_batch b{B, n, stencil, dout, 0};
+    MG_TRY(ensure_scratch(net, fp32_scratch(net, &b)));
+    mg_train_opts o;
+    mg_train_opts_default(&o);
+    return step_fp32(net, &b, o, nullptr, nullptr, st, true);
+}
+
+void net_adam(mg_net_s &net, const mg_train_opts &o, hipStream_t st)
+{
+    net.step += 1;
+    const double t = (double)net.step;
+    const float c1 = (float)(1.0 - std::pow((double)o.beta1, t));
+    const float c2 = (float)(1.0 - std::pow((double)o.beta2, t));
+    launch_adam(net.np, net.params, net.m, net.v, net.grad, o.lr, o.beta1, o.beta2, o.adam_eps, c1, c2, st);
+    net.packed_valid = false;
+}
+
+mg_status check_train_opts(const mg_train_opts &o)
+{
+    if (o.precision != 0 && o.precision != 1) return set_error(MG_ERR_ARG, "training precision must be 0 or 1");
+    if (!(o.lr >= 0.0f) || !(o.beta1 >= 0.0f && o.beta1 < 1.0f) || !(o.beta2 >= 0.0f && o.beta2 < 1.0f))
+        return set_error(MG_ERR_ARG, "bad Adam parameters");
+    return MG_OK;
+}
+
+}  // namespace mg
+
 extern "C" mg_status mg_train_step(mg_net net, const mg_train_batch *b, const mg_train_opts *o_in, float *loss,
                                    float *grad)
 {
@@ -265,9 +303,7 @@ extern "C" mg_status mg_train_step(mg_net net, const mg_train_batch *b, const mg
         o = *o_in;
     else
         mg_train_opts_default(&o);
-    if (o.precision != 0 && o.precision != 1) return set_error(MG_ERR_ARG, "training precision must be 0 or 1");
-    if (!(o.lr >= 0.0f) || !(o.beta1 >= 0.0f && o.beta1 < 1.0f) || !(o.beta2 >= 0.0f && o.beta2 < 1.0f))
-        return set_error(MG_ERR_ARG, "bad Adam parameters");
+    MG_TRY(check_train_opts(o));
     const int B = b->nprob, J = b->nvec;
     for (int q = 0; q < B; ++q) {
         const int n = b->n[q];
@@ -294,14 +330,7 @@ extern "C" mg_status mg_train_step(mg_net net, const mg_train_batch *b, const mg
         MG_TRY(step_fp32(*net, b, o, loss_part, d_loss, st));
     const float scale = 1.0f / ((float)B * (float)J);
     launch_tr_loss(loss_part, B * J, scale, d_loss, st);
-    if (o.apply_update) {
-        net->step += 1;
-        const double t = (double)net->step;
-        const float c1 = (float)(1.0 - std::pow((double)o.beta1, t));
-        const float c2 = (float)(1.0 - std::pow((double)o.beta2, t));
-        launch_adam(net->np, net->params, net->m, net->v, net->grad, o.lr, o.beta1, o.beta2, o.adam_eps, c1, c2, st);
-        net->packed_valid = false;
-    }
+    if (o.apply_update) net_adam(*net, o, st);
     MG_HIP(hipGetLastError());
     if (loss || grad) {
         if (loss) MG_HIP(hipMemcpyAsync(loss, d_loss, sizeof(float), hipMemcpyDeviceToHost, st));

@@ -33,6 +33,8 @@ void launch_tr_conv_fwd(const TrainProb *probs, int nb, int n, const float *para
 void launch_tr_av(const TrainProb *probs, int nb, int n, int J, hipStream_t st);
 void launch_tr_residual_norm(const TrainProb *probs, int nb, int J, float omega, float *loss_part, hipStream_t st);
 void launch_tr_dout(const TrainProb *probs, int nb, int n, int J, float scale, hipStream_t st);
+// dL/dy copied from P.V ([25][plane] per problem), for a loss computed elsewhere
+void launch_tr_dout_ext(const TrainProb *probs, int nb, int n, hipStream_t st);
 void launch_tr_conv_bwd_data(const TrainProb *probs, int nb, int n, const float *params, TrainLayer L, int layer,
                              hipStream_t st);
 void launch_tr_conv_bwd_weight(const TrainProb *probs, int nb, TrainLayer L, int layer, float *wpart, int64_t np,

@@ -139,6 +139,16 @@ __global__ void __launch_bounds__(kT) k_tr_dout(const TrainProb *probs, int J, f
     for (int k = 0; k < 25; ++k) P.dA[(int64_t)k * P.plane + p] = acc[k];
 }
 
+// Output gradient given from outside (another loss): dL/dy = the 25 planes at P.V.
+__global__ void __launch_bounds__(kT) k_tr_dout_ext(const TrainProb *probs)
+{
+    const TrainProb &P = probs[blockIdx.z];
+    const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (p >= P.plane) return;
+#pragma unroll
+    for (int k = 0; k < 25; ++k) P.dA[(int64_t)k * P.plane + p] = P.V[(int64_t)k * P.plane + p];
+}
+
 __device__ inline float MG_G *dpre_buf(const TrainProb &P, int layer) { return (layer & 1) ? P.dA : P.dB; }
 
 // dX[ci](q) = sum_co sum_tap w[co][ci][tap] dPre[co](q - tap + 1), masked by the
@@ -296,6 +306,11 @@ void launch_tr_residual_norm(const TrainProb *probs, int nb, int J, float omega,
 void launch_tr_dout(const TrainProb *probs, int nb, int n, int J, float scale, hipStream_t st)
 {
     k_tr_dout<<<dim3(blocks_for((int64_t)n * n), 1, nb), kT, 0, st>>>(probs, J, scale);
+}
+
+void launch_tr_dout_ext(const TrainProb *probs, int nb, int n, hipStream_t st)
+{
+    k_tr_dout_ext<<<dim3(blocks_for((int64_t)n * n), 1, nb), kT, 0, st>>>(probs);
 }
 
 void launch_tr_conv_bwd_data(const TrainProb *probs, int nb, int n, const float *params, TrainLayer L, int layer,

@@ -68,6 +68,11 @@ class TrainOpts(C.Structure):
                 ("omega", C.c_double), ("precision", C.c_int32), ("apply_update", C.c_int32)]
 
 
+class AlphaBatch(C.Structure):
+    _fields_ = [("nprob", C.c_int32), ("k", _c_ip), ("f", C.POINTER(C.c_void_p)), ("u0", C.POINTER(C.c_void_p)),
+                ("u_star", C.POINTER(C.c_void_p)), ("dW", C.POINTER(C.c_void_p))]
+
+
 SIGNATURES = {
     "mg_stencil_q1_rotated": (C.c_int, [C.c_int32, C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
     "mg_stencil_cellavg5": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -78,6 +83,10 @@ SIGNATURES = {
     "mg_num_levels": (C.c_int, [C.c_void_p, C.c_int32, _c_ip]),
     "mg_get_stencil": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "mg_smoother_infer": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "mg_smoother_infer_size": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "mg_smoother_transpose": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mg_alpha_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(AlphaBatch),
+                                C.POINTER(TrainOpts), _c_dp, _c_dp, _c_fp]),
     "mg_set_smoother": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "mg_get_smoother": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "mg_vcycle": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
@@ -302,8 +311,12 @@ class Context:
         _check(load_library().mg_set_smoother(self._h, prob, level, _ptr(W)))
         torch.cuda.current_stream().synchronize()
 
-    def infer(self, net: "Net") -> None:
-        _check(load_library().mg_smoother_infer(self._h, net._h))
+    def infer(self, net: "Net", size: Optional[int] = None) -> None:
+        """Network inference on every smoothing level, or (size given) on the levels of that size only."""
+        if size is None:
+            _check(load_library().mg_smoother_infer(self._h, net._h))
+        else:
+            _check(load_library().mg_smoother_infer_size(self._h, net._h, int(size)))
 
     def _vecs(self, xs, name):
         if len(xs) != self.nprob:
@@ -456,3 +469,48 @@ class Net:
                                             C.byref(loss) if want_loss else None,
                                             grad.ctypes.data_as(_c_fp) if want_grad else None))
         return (loss.value if want_loss else None), grad
+
+
+# ----------------------------------------------------------- adaptive training
+def smoother_transpose(A: torch.Tensor, W: torch.Tensor) -> torch.Tensor:
+    """The field WT whose smoother WT / a_C is the transpose of W / a_C."""
+    A = _dev_f64(A)
+    n = A.shape[1]
+    W = _dev_f64(W, (25, n, n))
+    out = torch.empty_like(W)
+    _check(load_library().mg_smoother_transpose(n, _ptr(A), _ptr(W), _ptr(out), _stream()))
+    return out
+
+
+@dataclass
+class AlphaResult:
+    loss: float
+    losses: np.ndarray
+    grad: Optional[np.ndarray] = None
+    dW: Optional[List[torch.Tensor]] = None
+
+
+def alpha_step(top: Context, coarse: Context, coarse_t: Context, net: Net, k: Sequence[int],
+               f: Sequence[torch.Tensor], u0: Sequence[torch.Tensor], u_star: Sequence[torch.Tensor],
+               opts: Optional[TrainOptions] = None, want_grad: bool = False, want_dW: bool = False) -> AlphaResult:
+    """One Algorithm 2 step (mg_alpha_step): loss, optional gradients, Adam update per opts."""
+    opts = opts or TrainOptions(precision=0)
+    B = top.nprob
+    n = top.ns[0]
+    if not (len(k) == len(f) == len(u0) == len(u_star) == B):
+        raise ValueError(f"need {B} entries of k, f, u0 and u_star")
+    f = [_dev_f64(x, (n, n)) for x in f]
+    u0 = [_dev_f64(x, (n, n)) for x in u0]
+    us = [_dev_f64(x, (n, n)) for x in u_star]
+    dW = [torch.empty((25, n, n), dtype=torch.float64, device="cuda") for _ in range(B)] if want_dW else None
+    arr = lambda xs: (C.c_void_p * B)(*[x.data_ptr() for x in xs])
+    kk = (C.c_int32 * B)(*[int(x) for x in k])
+    batch = AlphaBatch(B, kk, arr(f), arr(u0), arr(us), arr(dW) if want_dW else None)
+    o = opts.to_c()
+    loss = C.c_double()
+    losses = np.zeros(B, dtype=np.float64)
+    grad = np.zeros(net.num_params, dtype=np.float32) if want_grad else None
+    _check(load_library().mg_alpha_step(top._h, coarse._h, coarse_t._h, net._h, C.byref(batch), C.byref(o),
+                                        C.byref(loss), losses.ctypes.data_as(_c_dp),
+                                        grad.ctypes.data_as(_c_fp) if want_grad else None))
+    return AlphaResult(loss=loss.value, losses=losses, grad=grad, dW=dW)

@@ -117,6 +117,8 @@ def parse():
     ap.add_argument("--cpu-cycles", type=int, default=30, help="V-cycles in the oracle's timed sample")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--tune-reps", type=int, default=10, help="launches per tile shape in the autotuner")
+    ap.add_argument("--sweeps", type=int, nargs="*", default=[2, 3],
+                    help="damped-Jacobi V(nu,nu) cycles timed beside the CNN's V(1,1) (none: skip)")
     ap.add_argument("--restart", type=int, default=30,
                     help="restart length of the FGMRES comparison reported beside the headline (0: skip it)")
     ap.add_argument("--only", choices=["both", "cnn", "jacobi"], default="both",
@@ -277,6 +279,8 @@ def main():
     out["inference"] = inference_block(ctx_cnn, net, n)
     if args.restart > 0:
         out["fgmres"] = fgmres_block(args, ctx_cnn, ctx_jac, f, n)
+    if args.sweeps:
+        out["jacobi_sweeps"] = sweeps_block(args, A, f, n, cnn_s)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(n, theta, eps, net, cnn_s["iters"], args.cpu_cycles)
     print(json.dumps(out), flush=True)
@@ -302,6 +306,32 @@ def inference_block(ctx, net, n, reps=10):
     return {"bound": "mfma", "ms_per_call": ms, "nodes": nodes, "flop": flop, "achieved": tflops,
             "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": tflops / BF16_MFMA_PEAK_TFLOPS,
             "note": "useful FLOP (halo recomputation not counted); wall time of the call, all levels"}
+
+
+def sweeps_block(args, A, f, n, cnn_s):
+    """Damped Jacobi with more sweeps per cycle, V(nu, nu), against the CNN's
+    V(1,1): a smoother that costs more per application should be compared at
+    equal cost (the paper matches its convolution layers with as many Jacobi
+    steps); here the comparison is simply time to the same tolerance."""
+    import torch
+
+    from paper_2102_12071_amd import mgcnn
+    out = {"cnn_v11_solve_ms": cnn_s["solve_ms"], "cnn_v11_iters": cnn_s["iters"]}
+    for nu in args.sweeps:
+        ctx = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_JACOBI, nu_pre=nu, nu_post=nu))
+        ctx.solve([f], args.tol, args.maxit)  # warm-up
+        times = []
+        for _ in range(max(args.steps, 1)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = ctx.solve([f], args.tol, args.maxit)
+            times.append((time.perf_counter() - t0) * 1e3)
+        ms = sum(times) / len(times)
+        out[f"v{nu}{nu}"] = {"iters": int(res.iters[0]), "status": int(res.status[0]), "solve_ms": ms,
+                             "ms_per_iteration": float(res.ms) / max(int(res.iters[0]), 1)}
+        log(f"jacobi V({nu},{nu}): {int(res.iters[0])} iterations, {ms:.1f} ms")
+        ctx.close()
+    return out
 
 
 def fgmres_block(args, ctx_cnn, ctx_jac, f, n):

@@ -8,6 +8,7 @@ device is not a gfx950, every call raises.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from dataclasses import dataclass, field
 from typing import List, Optional, Sequence
@@ -317,6 +318,20 @@ class Context:
             _check(load_library().mg_smoother_infer(self._h, net._h))
         else:
             _check(load_library().mg_smoother_infer_size(self._h, net._h, int(size)))
+
+    def infer_levels(self, nets: dict) -> None:
+        """Per-level networks keyed by level size (adaptive training gives one per level): every
+        smoothing level takes the network of its size, or of the nearest trained size."""
+        if not nets:
+            raise ValueError("no networks")
+        sizes = sorted(nets)
+        have = set()
+        for p in range(self.nprob):
+            for l in range(self.num_levels(p) - 1):
+                have.add(self.level_n(p, l))
+        for m in sorted(have):
+            key = min(sizes, key=lambda s: (abs(math.log2(s + 1) - math.log2(m + 1)), -s))
+            _check(load_library().mg_smoother_infer_size(self._h, nets[key]._h, int(m)))
 
     def _vecs(self, xs, name):
         if len(xs) != self.nprob:

@@ -45,6 +45,7 @@ def test_binding_structs_match_header_sizes():
     assert C.sizeof(mgcnn.COptions) == 48
     assert C.sizeof(mgcnn.Problem) == 16
     assert C.sizeof(mgcnn.TrainOpts) == 32
+    assert C.sizeof(mgcnn.AlphaBatch) == 48
 
 
 def test_status_strings_and_defaults(lib):
@@ -83,6 +84,19 @@ def test_argument_errors_before_device(lib):
     assert lib.mg_vcycle(None, None, None) == -1
     assert lib.mg_train_step(None, None, None, None, None) == -1
     assert lib.mg_net_get(None, None, 0) == -1
+    assert lib.mg_alpha_step(None, None, None, None, None, None, None, None, None) == -1
+    assert lib.mg_smoother_transpose(0, C.c_void_p(16), C.c_void_p(16), C.c_void_p(32), None) == -1
+    assert lib.mg_smoother_transpose(7, C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), None) == -1
+    assert b"same buffer" in lib.mg_last_error()
+    assert lib.mg_smoother_infer_size(None, None, 7) == -1
+
+
+def test_alpha_stage_sizes():
+    from paper_2102_12071_amd.alpha_train import stage_sizes
+    assert stage_sizes(63) == [7, 15, 31, 63]  # four stages of a 5-level hierarchy, coarse to fine
+    assert stage_sizes(63, 7) == [15, 31, 63]
+    assert stage_sizes(7) == [7]
+    assert stage_sizes(3) == []
 
 
 def test_product_path_has_no_oracle_dependency():

@@ -73,6 +73,16 @@ mg_status mg_stencil_q1_rotated(int32_t n, double theta, double eps, double *out
  * out: device [9][n][n] FP64 (corner channels zero). */
 mg_status mg_stencil_cellavg5(int32_t n, const double *a, double *out, void *stream);
 
+/* Restricts a stencil to a domain inside the square (the non-square geometries
+ * of section 6): nodes with mask 0 lie outside and carry the zero Dirichlet
+ * value; their rows keep only the centre entry (so the row reads u_p = f_p / a_C,
+ * and f must be 0 there), and the rows of the nodes inside drop their
+ * couplings to them.  The result is the operator of the interior nodes, with
+ * the outside nodes decoupled, and stays symmetric positive definite.
+ * mask: device [n][n] bytes (nonzero = inside); A, out: device [9][n][n]
+ * FP64 (out may be A).  n odd, 1 <= n <= 16383. */
+mg_status mg_stencil_mask(int32_t n, const uint8_t *mask, const double *A, double *out, void *stream);
+
 /* Galerkin coarse stencil Ac = R A P with R full weighting and P bilinear
  * (section 2.2, coarse operator P^T A P up to the factor 1/4 of R = P^T/4).
  * A: device [9][n][n]; Ac: device [9][nc][nc], nc = (n-1)/2.  n odd >= 3. */
@@ -134,7 +144,11 @@ mg_status mg_get_stencil(mg_ctx ctx, int32_t prob, int32_t level, double *out);
  * the resulting smoothers (section 4.2: stencil -> per-point smoothing kernel)
  * in the context.  In mixed precision the network runs in BF16 on MFMA with
  * FP32 accumulation and the smoother is stored in BF16; in FP64 precision
- * every operation is FP64.  Required before solving with MG_SMOOTHER_CNN. */
+ * every operation is FP64.  A row without a negative off-centre entry gets
+ * damped Jacobi, W = omega * delta_0, instead of the network's output: every
+ * diffusion row has one, the Dirichlet nodes of mg_stencil_mask and their
+ * Galerkin images on coarser levels do not.  Required before solving with
+ * MG_SMOOTHER_CNN. */
 mg_status mg_smoother_infer(mg_ctx ctx, mg_net net);
 
 /* Runs the network on the smoothing levels of size n only (every problem),

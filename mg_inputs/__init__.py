@@ -86,6 +86,26 @@ def lognormal_coefficient(n: int, length: float = 0.1, sigma: float = 1.0, seed:
 
 
 # ------------------------------------------------------------ network weights
+def domain_mask(n: int, kind: str) -> np.ndarray:
+    """Node mask (1 inside, 0 on the removed part, uint8 [n, n]) of a domain in
+    the unit square, node (i, j) at ((i+1)h, (j+1)h), h = 1/(n+1):
+    'square': all nodes; 'lshape': the square without the quadrant x, y >= 1/2
+    (its boundary included); 'cylinder': the square without the disk of radius
+    1/5 about (1/2, 1/2) (boundary included)."""
+    h = 1.0 / (n + 1)
+    x = (np.arange(n) + 1) * h
+    X, Y = np.meshgrid(x, x)  # X[j, i] = x_i, Y[j, i] = y_j
+    if kind == "square":
+        out = np.ones((n, n), dtype=bool)
+    elif kind == "lshape":
+        out = ~((X >= 0.5) & (Y >= 0.5))
+    elif kind == "cylinder":
+        out = (X - 0.5) ** 2 + (Y - 0.5) ** 2 > 0.2 ** 2
+    else:
+        raise ValueError(kind)
+    return out.astype(np.uint8)
+
+
 def cnn_param_count(channels=CNN_CHANNELS) -> int:
     return sum(channels[l + 1] * channels[l] * 9 + channels[l + 1] for l in range(len(channels) - 1))
 

@@ -141,6 +141,28 @@ def prolong_add(ec, e) -> np.ndarray:
     return out
 
 
+def stencil_mask(A, mask) -> np.ndarray:
+    """The operator of a domain inside the square (section 6, other geometries):
+    nodes with mask 0 are Dirichlet nodes (value 0) and decouple (their row keeps
+    its centre entry only); the rows of the nodes inside drop the couplings to
+    them.  Pinned against the principal submatrix of the dense operator."""
+    A = _f64(A)
+    n = A.shape[1]
+    inside = np.asarray(mask) != 0
+    out = A.copy()
+    for c in range(9):
+        if c == 4:
+            continue
+        dy, dx = c // 3 - 1, c % 3 - 1
+        for j in range(n):
+            for i in range(n):
+                jj, ii = j + dy, i + dx
+                nb = 0 <= jj < n and 0 <= ii < n and inside[jj, ii]
+                if not (inside[j, i] and nb):
+                    out[c, j, i] = 0.0
+    return out
+
+
 def galerkin(A) -> np.ndarray:
     A = _f64(A)
     n = A.shape[1]

@@ -52,25 +52,41 @@ def stage_sizes(finest: int, coarsest: int = 3):
     return sizes[::-1]
 
 
-class Stage:
-    """The training set of one stage and the three contexts of its step."""
+def stage_stencils(n: int, Q: int, seed: int):
+    """The Q rotated anisotropic stencils of the stage on size n (seeded)."""
+    rng = np.random.default_rng([seed, n])
+    theta = rng.uniform(0.0, math.pi, Q)
+    eps = 10.0 ** rng.uniform(-3.0, 0.0, Q)
+    return [mgcnn.stencil_q1_rotated(n, float(t), float(e)) for t, e in zip(theta, eps)]
 
-    def __init__(self, n: int, Q: int, nets: Dict[int, mgcnn.Net], seed: int, coarsest: int = 3):
-        rng = np.random.default_rng([seed, n])
-        theta = rng.uniform(0.0, math.pi, Q)
-        eps = 10.0 ** rng.uniform(-3.0, 0.0, Q)
-        self.n, self.Q = n, Q
-        As = [mgcnn.stencil_q1_rotated(n, float(t), float(e)) for t, e in zip(theta, eps)]
+
+class Stage:
+    """The training set of one stage and the three contexts of its step.
+
+    inject: errors that the current hierarchy fails to reduce (one per
+    stencil, from inject_errors); each adds the instance {A, f = 0, u0 = e,
+    u* = 0}, whose loss is the norm of k cycles' error propagation applied to e."""
+
+    def __init__(self, n: int, Q: int, nets: Dict[int, mgcnn.Net], seed: int, coarsest: int = 3,
+                 inject: Optional[list] = None):
+        rng = np.random.default_rng([seed, n, 2])
+        self.n = n
+        As = stage_stencils(n, Q, seed)
         fp64 = mgcnn.Options(precision=mgcnn.PREC_FP64, coarsest_n=coarsest)
-        self.top = mgcnn.Context(As, fp64)
         self.f = [torch.tensor(rng.uniform(-1.0, 1.0, (n, n)), dtype=torch.float64, device="cuda")
                   for _ in range(Q)]
-        res = self.top.solve(self.f, 1e-13, 5000)
+        self.u0 = [torch.tensor(rng.normal(size=(n, n)), dtype=torch.float64, device="cuda") for _ in range(Q)]
+        if inject:
+            As = As + As[:len(inject)]
+            self.f += [torch.zeros((n, n), dtype=torch.float64, device="cuda") for _ in inject]
+            self.u0 += list(inject)
+        self.Q = len(As)
+        self.top = mgcnn.Context(As, fp64)
+        res = self.top.solve(self.f, 1e-13, 5000)  # zero right-hand sides: u* = 0 at once
         if not (res.relres <= 1e-12).all():
             raise RuntimeError("exact solutions of the training set did not converge")
         self.u_star = res.u
-        self.u0 = [torch.tensor(rng.normal(size=(n, n)), dtype=torch.float64, device="cuda") for _ in range(Q)]
-        A1 = [self.top.stencil(b, 1) for b in range(Q)]
+        A1 = [self.top.stencil(b, 1) for b in range(self.Q)]
         lower = stage_sizes((n - 1) // 2, coarsest)
         if not lower:  # the coarse problem is the coarsest grid: Psi_c is the exact solve
             self.coarse = mgcnn.Context(A1, fp64)
@@ -80,7 +96,7 @@ class Stage:
             self.coarse = mgcnn.Context(A1, cnn)
             self.coarse.infer_levels(nets)
             self.coarse_t = mgcnn.Context(A1, cnn)
-            for b in range(Q):
+            for b in range(self.Q):
                 for l in range(self.coarse.num_levels(b) - 1):
                     W = self.coarse.smoother(b, l)
                     self.coarse_t.set_smoother(b, l, mgcnn.smoother_transpose(self.coarse.stencil(b, l), W))
@@ -99,6 +115,33 @@ class Stage:
     def close(self):
         for c in (self.top, self.coarse, self.coarse_t):
             c.close()
+
+
+def inject_errors(n: int, Q: int, nets: Dict[int, mgcnn.Net], seed: int, cycles: int = 30, coarsest: int = 3,
+                  rnd: int = 0):
+    """The paper's update of trained smoothers (section 3.3): the current
+    hierarchy of the stage (its network on top, the earlier ones below)
+    applied to A u = 0 from a random u0 for some cycles; what is left, u_k,
+    is the error it reduces worst (or amplifies).  Returns the u_k scaled to
+    the norm of a N(0, 1) vector, and the largest per-cycle growth over the
+    last third of the cycles among the stencils, a power-iteration estimate
+    of the cycle's spectral radius."""
+    rng = np.random.default_rng([seed, n, 3, rnd])
+    As = stage_stencils(n, Q, seed)
+    ctx = mgcnn.Context(As, mgcnn.Options(precision=mgcnn.PREC_FP64, coarsest_n=coarsest,
+                                          smoother=mgcnn.SMOOTHER_CNN))
+    ctx.infer_levels(nets)
+    u = [torch.tensor(rng.normal(size=(n, n)), dtype=torch.float64, device="cuda") for _ in range(Q)]
+    zero = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for _ in range(Q)]
+    tail = max(cycles // 3, 1)
+    for c in range(cycles):
+        if c == cycles - tail:
+            mid = [float(x.norm()) for x in u]
+        ctx.vcycle(zero, u)
+    ctx.close()
+    growth = max((float(x.norm()) / max(a, 1e-300)) ** (1.0 / tail) for x, a in zip(u, mid))
+    out = [x * (n / max(float(x.norm()), 1e-300)) for x in u]
+    return out, growth
 
 
 def train(finest: int = 63, Q: int = 50, steps: int = 400, lr: float = 1e-3, bmax: int = 4, seed: int = 0,
@@ -126,9 +169,31 @@ def train(finest: int = 63, Q: int = 50, steps: int = 400, lr: float = 1e-3, bma
         last = stage.monitor(net, bmax)
         stage.close()
         nets[n] = net
+        _, growth = inject_errors(n, Q, nets, seed + 1, 30, coarsest)
         log(json.dumps({"stage_n": n, "done": True, f"loss_k{bmax}_start": first, f"loss_k{bmax}_end": last,
-                        "seconds": round(time.perf_counter() - t0, 3)}))
+                        "growth": growth, "seconds": round(time.perf_counter() - t0, 3)}))
     return nets
+
+
+def update(nets: Dict[int, mgcnn.Net], Q: int = 50, steps: int = 400, lr: float = 3e-4, bmax: int = 4,
+           seed: int = 0, rounds: int = 1, cycles: int = 30, coarsest: int = 3, log=print) -> None:
+    """Rounds of the paper's smoother update: per stage, coarse to fine, inject
+    the errors the current hierarchy reduces worst and retrain the stage's
+    network from its current weights on the augmented set."""
+    for rnd in range(rounds):
+        for n in sorted(nets):
+            t0 = time.perf_counter()
+            inj, growth = inject_errors(n, Q, nets, seed, cycles, coarsest, rnd)
+            stage = Stage(n, Q, {m: v for m, v in nets.items() if m < n}, seed, coarsest, inject=inj)
+            first = stage.monitor(nets[n], bmax)
+            for s in range(steps):
+                stage.step(nets[n], mgcnn.TrainOptions(lr=lr, precision=0), bmax)
+            last = stage.monitor(nets[n], bmax)
+            stage.close()
+            _, after = inject_errors(n, Q, nets, seed + 1, cycles, coarsest, rnd)
+            log(json.dumps({"update_round": rnd, "stage_n": n, "growth_before": growth, "growth_after": after,
+                            f"loss_k{bmax}_start": first, f"loss_k{bmax}_end": last,
+                            "seconds": round(time.perf_counter() - t0, 3)}))
 
 
 def load_nets(out_dir: str = WEIGHTS, finest: int = 63, coarsest: int = 3) -> Dict[int, mgcnn.Net]:
@@ -172,6 +237,10 @@ def main():
     ap.add_argument("--bmax", type=int, default=4, help="k ~ U{1..bmax} cycles per loss term")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--init", default=None, help="checkpoint to start every stage from (default: damped Jacobi)")
+    ap.add_argument("--update-rounds", type=int, default=0, help="rounds of error injection and retraining")
+    ap.add_argument("--update-steps", type=int, default=400)
+    ap.add_argument("--update-lr", type=float, default=3e-4)
+    ap.add_argument("--load", default=None, help="directory of trained per-level networks to start from")
     ap.add_argument("--out-dir", default=WEIGHTS)
     ap.add_argument("--log", default=None)
     args = ap.parse_args()
@@ -182,8 +251,14 @@ def main():
         print(line, flush=True)
         records.append(json.loads(line))
 
-    nets = train(args.finest, args.instances, args.steps, args.lr, args.bmax, args.seed, args.init,
-                 lr_final=args.lr_final, log=log)
+    if args.load:
+        nets = load_nets(args.load, args.finest)
+    else:
+        nets = train(args.finest, args.instances, args.steps, args.lr, args.bmax, args.seed, args.init,
+                     lr_final=args.lr_final, log=log)
+    if args.update_rounds:
+        update(nets, args.instances, args.update_steps, args.update_lr, args.bmax, args.seed, args.update_rounds,
+               log=log)
     os.makedirs(args.out_dir, exist_ok=True)
     for n, net in nets.items():
         net.save(weight_path(args.out_dir, n))

@@ -206,4 +206,15 @@ mg_status mg_galerkin(int32_t n, const double *A, double *Ac, void *stream)
     return MG_OK;
 }
 
+mg_status mg_stencil_mask(int32_t n, const uint8_t *mask, const double *A, double *out, void *stream)
+{
+    clear_error();
+    if (!odd_in_range(n, 1, 16383)) return set_error(MG_ERR_ARG, "n must be odd in [1, 16383], got %d", n);
+    if (!mask || !A || !out) return set_error(MG_ERR_ARG, "null pointer");
+    MG_TRY(require_device());
+    launch_mask(n, mask, A, out, (hipStream_t)stream);
+    MG_HIP(hipGetLastError());
+    return MG_OK;
+}
+
 }  // extern "C"

@@ -12,7 +12,8 @@
 // input channels are padded to sixteen, so one K step of 32 covers two taps.
 // Activations at nodes outside the grid are set to zero after every layer:
 // this is the per-layer zero padding of "same" convolutions.  The last layer
-// writes H = (omega*delta_0 + y) / a_C in BF16.
+// writes H = (omega*delta_0 + y) / a_C in BF16 (y = 0 on rows without a
+// negative off-centre entry).
 //
 // MFMA operand layout used (16x16x32, wave of 64): lane l supplies
 // A[m = l % 16][k = 8 (l / 16) + e] and B[k = 8 (l / 16) + e][n = l % 16],
@@ -144,8 +145,14 @@ __global__ void __launch_bounds__(kT) k_cnn_fused(int n, int P, int64_t plane, c
         if (gy >= n || gx >= n) continue;
         const int64_t p = (int64_t)gy * P + gx;
         const float inv = 1.0f / A32[kCentre * plane + p];
+        // every diffusion row has a negative off-centre entry; rows without one (Dirichlet nodes of a
+        // masked domain and their Galerkin images) take damped Jacobi
+        bool diffusion = false;
 #pragma unroll
-        for (int k = 0; k < 25; ++k) H[k * plane + p] = f32_to_bf16((stage[q * 25 + k] + (k == 12 ? omega : 0.f)) * inv);
+        for (int c = 0; c < 9; ++c) diffusion = diffusion || (c != kCentre && A32[c * plane + p] < 0.f);
+#pragma unroll
+        for (int k = 0; k < 25; ++k)
+            H[k * plane + p] = f32_to_bf16(((diffusion ? stage[q * 25 + k] : 0.f) + (k == 12 ? omega : 0.f)) * inv);
     }
 }
 

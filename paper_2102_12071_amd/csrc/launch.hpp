@@ -14,6 +14,8 @@ void launch_copy_field(int n, int nch, const double *src, int Ps, int64_t planes
                        int64_t planed, hipStream_t st);
 void launch_to_f32(int64_t count, const double *src, float *dst, hipStream_t st);
 void launch_validate(int n, int P, int64_t plane, const double *A, int *flag, hipStream_t st);
+// Dirichlet nodes of a domain mask (0 = outside) on a dense [9][n][n] stencil; out may alias A.
+void launch_mask(int n, const uint8_t *mask, const double *A, double *out, hipStream_t st);
 
 // ---- coarse.hip: coarsest-level factorisation (explicit inverse) ----
 void launch_coarse_factor(int m, int P, int64_t plane, const double *A, double *Ainv, int *flag, hipStream_t st);

@@ -134,6 +134,28 @@ __global__ void k_validate(int n, int P, int64_t plane, const double *A, int *fl
     if (bad) atomicOr(flag, bad);
 }
 
+// Dirichlet condition on the nodes outside a domain (mask 0): their rows keep
+// only the centre entry, and the rows of the nodes inside drop the couplings to
+// them.  Dense [9][n][n] in and out (may alias: each thread reads and writes
+// its own node only).
+__global__ void k_mask(int n, const uint8_t *mask, const double *A, double *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= n || j >= n) return;
+    const int64_t nn = (int64_t)n * n, p = (int64_t)j * n + i;
+    const bool in = mask[p] != 0;
+    for (int c = 0; c < 9; ++c) {
+        const int ii = i + c % 3 - 1, jj = j + c / 3 - 1;
+        double v = A[c * nn + p];
+        if (c != kCentre) {
+            const bool nb_in = inside(n, ii, jj) && mask[(int64_t)jj * n + ii] != 0;
+            if (!in || !nb_in) v = 0.0;
+        }
+        out[c * nn + p] = v;
+    }
+}
+
 dim3 node_grid(int n, dim3 blk) { return dim3((n + blk.x - 1) / blk.x, (n + blk.y - 1) / blk.y, 1); }
 
 }  // namespace
@@ -171,6 +193,12 @@ void launch_to_f32(int64_t count, const double *src, float *dst, hipStream_t st)
 {
     const int nt = 256;
     k_to_f32<<<(unsigned)((count + nt - 1) / nt), nt, 0, st>>>(count, src, dst);
+}
+
+void launch_mask(int n, const uint8_t *mask, const double *A, double *out, hipStream_t st)
+{
+    dim3 blk(64, 4);
+    k_mask<<<node_grid(n, blk), blk, 0, st>>>(n, mask, A, out);
 }
 
 void launch_validate(int n, int P, int64_t plane, const double *A, int *flag, hipStream_t st)

@@ -78,6 +78,7 @@ SIGNATURES = {
     "mg_stencil_q1_rotated": (C.c_int, [C.c_int32, C.c_double, C.c_double, C.c_void_p, C.c_void_p]),
     "mg_stencil_cellavg5": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mg_galerkin": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mg_stencil_mask": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mg_options_default": (None, [C.POINTER(COptions)]),
     "mg_setup": (C.c_int, [C.POINTER(Problem), C.c_int32, C.POINTER(COptions), C.c_void_p, C.POINTER(C.c_void_p)]),
     "mg_destroy": (C.c_int, [C.c_void_p]),
@@ -176,6 +177,18 @@ def stencil_cellavg5(a: torch.Tensor) -> torch.Tensor:
     n = a.shape[0] - 1
     out = torch.empty((9, n, n), dtype=torch.float64, device=a.device)
     _check(load_library().mg_stencil_cellavg5(n, _ptr(a), _ptr(out), _stream()))
+    return out
+
+
+def stencil_mask(A: torch.Tensor, mask: torch.Tensor) -> torch.Tensor:
+    """The stencil restricted to the nodes where mask is nonzero (zero Dirichlet value outside)."""
+    A = _dev_f64(A)
+    n = A.shape[1]
+    if not (isinstance(mask, torch.Tensor) and mask.is_cuda and tuple(mask.shape) == (n, n)):
+        raise ValueError("mask must be a device tensor [n, n]")
+    m = (mask != 0).to(torch.uint8).contiguous()
+    out = torch.empty_like(A)
+    _check(load_library().mg_stencil_mask(n, _ptr(m), _ptr(A), _ptr(out), _stream()))
     return out
 
 

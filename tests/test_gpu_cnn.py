@@ -111,3 +111,33 @@ def test_cnn_solve_mixed_close_to_oracle(mg):
     assert abs(int(res.iters[0]) - k) <= max(2, 0.1 * k)
     r = f - ora.matvec(A, res.u[0].cpu().numpy())
     assert np.linalg.norm(r) / np.linalg.norm(f) <= 1e-8
+
+
+def test_per_level_networks(mg):
+    # one network per level size (the adaptive training's output): inference on the levels of one
+    # size leaves the others as they were, and infer_levels maps sizes to the nearest trained network
+    n = 63
+    A = _problem("q1", n)
+    pa, pb, pc = mg_inputs.cnn_random(7), mg_inputs.cnn_random(8), mg_inputs.cnn_random(9)
+    na, nb, nc = _net(mg, pa), _net(mg, pb), _net(mg, pc)
+    opt = mg.Options(smoother=mg.SMOOTHER_CNN, precision=mg.PREC_FP64, coarsest_n=3)
+    ctx = mg.Context([_dev(A)], opt)
+    h = ora.Hierarchy(A, 3)
+    sizes = [h.level_n(l) for l in range(h.num_levels - 1)]
+    assert sizes == [63, 31, 15, 7]
+
+    def check(expect):
+        for l, p in enumerate(expect):
+            W = ora.cnn_forward(h.stencil(l), p)
+            got = ctx.smoother(0, l).cpu().numpy()
+            assert np.abs(got - W).max() <= 1e-12 * np.abs(W).max(), l
+
+    ctx.infer(na)
+    ctx.infer(nb, size=15)
+    check([pa, pa, pb, pa])
+    with pytest.raises(mg.MGError):
+        ctx.infer(nb, size=9)  # no level of that size
+    with pytest.raises(mg.MGError):
+        ctx.infer(nb, size=3)  # the coarsest level has no smoother
+    ctx.infer_levels({7: na, 15: nb, 31: nc})
+    check([pc, pc, pb, pa])  # 63 takes the largest trained size

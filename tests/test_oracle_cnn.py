@@ -190,3 +190,48 @@ def test_adam_matches_torch(ora):
         opt.step()
         p, m, v = ora.adam_step(p, m, v, g, t)
     assert np.allclose(p, pt.detach().numpy(), rtol=0, atol=1e-14)
+
+
+def test_network_smoother_on_masked_domain(ora):
+    # Dirichlet rows (no off-centre coupling) take damped Jacobi; away from them the output is
+    # the unmasked network's, since the network sees only 4 nodes around each point
+    n = 31
+    A = ora.stencil_q1_rotated(n, 0.7, 0.05)
+    mask = mg_inputs.domain_mask(n, "cylinder")
+    Am = ora.stencil_mask(A, mask)
+    params = mg_inputs.cnn_random(11)
+    W = ora.cnn_forward(A, params)
+    Wm = ora.cnn_forward(Am, params)
+    out = mask == 0
+    jac = np.zeros(25)
+    jac[12] = ora.OMEGA
+    assert np.array_equal(Wm[:, out].T, np.tile(jac, (int(out.sum()), 1)))
+    # nodes at distance > 5 (Chebyshev) from every outside node: one for the mask's coupling
+    # change, four for the network's receptive field
+    far = np.ones((n, n), dtype=bool)
+    for j, i in zip(*np.nonzero(out)):
+        far[max(j - 5, 0):j + 6, max(i - 5, 0):i + 6] = False
+    assert far.sum() > 100
+    assert np.array_equal(Wm[:, far], W[:, far])
+    # the hole's Galerkin images on the coarser levels have no negative entry either
+    h = ora.Hierarchy(Am, 3)
+    S = h.stencil(1)
+    Wc = ora.cnn_forward(S, params)
+    hole = np.concatenate([S[:4], S[5:]]).min(0) >= 0
+    assert hole.sum() > 4 and np.array_equal(Wc[:, hole].T, np.tile(jac, (int(hole.sum()), 1)))
+    assert not np.array_equal(Wc[:, ~hole], np.zeros_like(Wc[:, ~hole]))
+
+
+def test_diffusion_rows_always_take_the_network(ora):
+    # every row of a diffusion stencil has a negative off-centre entry (at least 1 % of a_C on
+    # these draws), on every Galerkin level: the Jacobi rule never replaces the network there
+    rng = np.random.default_rng(3)
+    stencils = [ora.stencil_q1_rotated(n, rng.uniform(0, math.pi), 10 ** rng.uniform(-4, 0))
+                for n in (31, 63) for _ in range(20)]
+    stencils += [ora.stencil_cellavg5(n, mg_inputs.lognormal_coefficient(n, L, 1.0, s))
+                 for n in (31, 63) for s in range(3) for L in (0.05, 0.1, 0.3)]
+    for A in stencils:
+        h = ora.Hierarchy(A, 1)
+        for l in range(h.num_levels - 1):
+            S = h.stencil(l)
+            assert (np.concatenate([S[:4], S[5:]]).min(0) / S[4]).max() < -0.01

@@ -5,6 +5,7 @@ import os
 import numpy as np
 import pytest
 
+import mg_inputs
 from tests.independent import fe_q1_matrix, stencil_field_to_csr
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -165,3 +166,36 @@ def test_cellavg5_matches_edge_energy_assembly(ora):
                     if v is not None:
                         M[u, v] -= ae
     assert np.abs(stencil_field_to_csr(A).toarray() - M).max() < 1e-13
+
+
+@pytest.mark.parametrize("kind", ["lshape", "cylinder"])
+def test_masked_stencil_is_the_interior_block(ora, kind):
+    # the operator of the domain = the principal submatrix of the square's operator on the
+    # inside nodes; the outside nodes decouple with their own centre entry
+    n = 15
+    A = ora.stencil_q1_rotated(n, math.pi / 4, 0.01)
+    mask = mg_inputs.domain_mask(n, kind).ravel().astype(bool)
+    M = ora.stencil_to_dense(ora.stencil_mask(A, mask.reshape(n, n)))
+    F = ora.stencil_to_dense(A)
+    inn, out = np.flatnonzero(mask), np.flatnonzero(~mask)
+    assert 0 < len(out) < n * n
+    assert np.array_equal(M[np.ix_(inn, inn)], F[np.ix_(inn, inn)])
+    assert not M[np.ix_(inn, out)].any() and not M[np.ix_(out, inn)].any()
+    assert np.array_equal(M[np.ix_(out, out)], np.diag(np.diag(F)[out]))
+    # the domain's solution: zero outside, the interior block's solve inside
+    f = mg_inputs.rhs_uniform(n, 0).ravel() * mask
+    u = np.linalg.solve(M, f)
+    assert not u[out].any()
+    assert np.allclose(u[inn], np.linalg.solve(F[np.ix_(inn, inn)], f[inn]), rtol=1e-12, atol=1e-14)
+
+
+def test_domain_masks():
+    n = 63
+    sq, ls, cy = (mg_inputs.domain_mask(n, k) for k in ("square", "lshape", "cylinder"))
+    assert sq.all()
+    # the removed quadrant: nodes with x, y >= 1/2 (index >= 31 on h = 1/64)
+    assert ls.sum() == n * n - 32 * 32 and not ls[31:, 31:].any() and ls[:31, :].all()
+    # the disk of radius 1/5 about the centre: about pi r^2 / h^2 nodes
+    removed = n * n - cy.sum()
+    assert abs(removed - math.pi * 0.04 * 64 ** 2) < 0.05 * math.pi * 0.04 * 64 ** 2
+    assert cy[0, :].all() and cy[:, 0].all() and not cy[31, 31]

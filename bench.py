@@ -112,13 +112,21 @@ def parse():
     ap.add_argument("--eps", type=float, default=1e-3)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--maxit", type=int, default=20000)
-    ap.add_argument("--weights", default=WEIGHTS)
+    ap.add_argument("--weights", default=WEIGHTS, help="the single network's checkpoint (high-frequency loss)")
+    ap.add_argument("--smoother", choices=["auto", "alpha", "hf"], default="auto",
+                    help="headline smoother: the per-level networks of the adaptive training (alpha: "
+                         "weights/alpha_n*.bin), or the single network (hf); auto: alpha when its checkpoints exist")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-cycles", type=int, default=30, help="V-cycles in the oracle's timed sample")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--tune-reps", type=int, default=10, help="launches per tile shape in the autotuner")
     ap.add_argument("--sweeps", type=int, nargs="*", default=[2, 3],
                     help="damped-Jacobi V(nu,nu) cycles timed beside the CNN's V(1,1) (none: skip)")
+    ap.add_argument("--geometries", type=int, default=1,
+                    help="1: also solve the L-shaped and cylinder domains (theta = pi/4, eps = 0.01), CNN and "
+                         "Jacobi, beside the headline; 0: skip")
+    ap.add_argument("--train-steps", type=int, default=10,
+                    help="timed BF16 training steps of the 256-problem batch reported beside the headline (0: skip)")
     ap.add_argument("--restart", type=int, default=30,
                     help="restart length of the FGMRES comparison reported beside the headline (0: skip it)")
     ap.add_argument("--only", choices=["both", "cnn", "jacobi"], default="both",
@@ -127,6 +135,10 @@ def parse():
                     help="c2: the headline problem (default); c4: variable-coefficient 4095^2 with FP64 "
                          "refinement to 1e-10; c5: 512 uneven problems batched in one context")
     ap.add_argument("--batch", type=int, default=512, help="c5: number of problems")
+    ap.add_argument("--infer-only", type=int, default=0, metavar="REPS",
+                    help="profiling aid: only run mg_smoother_infer on the headline problem REPS times and exit")
+    ap.add_argument("--train-only", action="store_true",
+                    help="profiling aid: only run the timed training steps and print their JSON")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="profiling aid: only run a plain device copy of MIB MiB five times (the known-size "
                          "kernel that scales the HBM byte counters) and exit")
@@ -160,6 +172,19 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": nbytes, "bytes_written": nbytes, "launches": 5}), flush=True)
         return
+    if args.infer_only:
+        net = mgcnn.Net()
+        net.load(args.weights)
+        ctx = mgcnn.Context([mgcnn.stencil_q1_rotated(args.n, args.theta, args.eps)],
+                            mgcnn.Options(smoother=mgcnn.SMOOTHER_CNN))
+        for _ in range(args.infer_only):
+            ctx.infer(net)
+        torch.cuda.synchronize()
+        print(json.dumps({"inference_calls": args.infer_only, "n": args.n}), flush=True)
+        return
+    if args.train_only:
+        print(json.dumps(training_block(args)), flush=True)
+        return
     if args.workload == "c4":
         return workload_c4(args)
     if args.workload == "c5":
@@ -173,10 +198,24 @@ def main():
         net.load(args.weights)
     else:
         net.set(mg_inputs.cnn_init(0).astype(np.float32))
+    alpha_nets = load_alpha_nets(args)
+    use_alpha = args.smoother == "alpha" or (args.smoother == "auto" and alpha_nets is not None)
+    if use_alpha and alpha_nets is None:
+        raise SystemExit("--smoother alpha needs the per-level checkpoints weights/alpha_n*.bin")
+    # the per-level networks were trained over a 3 x 3 coarsest grid; the single network over 7 x 7
+    coarsest = 3 if use_alpha else 7
+
+    def infer(ctx):
+        if use_alpha:
+            ctx.infer_levels(alpha_nets)
+        else:
+            ctx.infer(net)
 
     A = mgcnn.stencil_q1_rotated(n, theta, eps)
-    ctx_cnn = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_CNN, precision=mgcnn.PREC_MIXED))
-    ctx_jac = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_JACOBI, precision=mgcnn.PREC_MIXED))
+    ctx_cnn = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_CNN, precision=mgcnn.PREC_MIXED,
+                                               coarsest_n=coarsest))
+    ctx_jac = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_JACOBI, precision=mgcnn.PREC_MIXED,
+                                               coarsest_n=coarsest))
     for ctx in (ctx_cnn, ctx_jac):  # set-up, outside the timed steps
         ctx.autotune(args.tune_reps)
 
@@ -187,7 +226,7 @@ def main():
         ctx.restencil([As])                                   # a2, a3 (synchronises)
         t1 = time.perf_counter()
         if cnn:
-            ctx.infer(net)                                    # a4
+            infer(ctx)                                        # a4
             torch.cuda.synchronize()
         t2 = time.perf_counter()
         res = ctx.solve([f], tol, args.maxit)                 # a5 - a10 (synchronises)
@@ -268,7 +307,11 @@ def main():
         "config": {"workload": f"rotated anisotropic Q1, n={n}, theta={theta:.6f}, eps={eps:g}, "
                                f"V(1,1) to {tol:g}, CNN smoother vs damped Jacobi",
                    "n": n, "unknowns": N, "tol": tol, "precision": "bf16 CNN/smoother, fp32 cycle, fp64 refinement",
-                   "weights": "trained (HF loss)" if trained else "untrained (zero last layer = damped Jacobi)"},
+                   "coarsest_n": coarsest,
+                   "weights": ("per-level networks of the adaptive training (Algorithm 2), level sizes "
+                               f"{sorted(alpha_nets)}; finer levels take the n = {max(alpha_nets)} network"
+                               if use_alpha else "one network, trained on the high-frequency loss" if trained
+                               else "untrained (zero last layer = damped Jacobi)")},
         "cnn": cnn_s,
         "jacobi": jac_s,
         "speedup_vs_jacobi": {"iterations": jac_s["iters"] / max(cnn_s["iters"], 1),
@@ -276,29 +319,42 @@ def main():
         "roofline": roofline,
     }
 
-    out["inference"] = inference_block(ctx_cnn, net, n)
+    # the fused MFMA inference kernel's rate: one call of the single network over every level
+    # (the per-level networks make one call per level size; their time is in cnn.infer_ms)
+    out["inference"] = inference_block(ctx_cnn, lambda c: c.infer(net), n, coarsest)
     if args.restart > 0:
         out["fgmres"] = fgmres_block(args, ctx_cnn, ctx_jac, f, n)
     if args.sweeps:
-        out["jacobi_sweeps"] = sweeps_block(args, A, f, n, cnn_s)
+        out["jacobi_sweeps"] = sweeps_block(args, A, f, n, cnn_s, coarsest)
+    if args.geometries:
+        out["geometries"] = geometry_block(args, net, alpha_nets if use_alpha else None, n)
+    if args.train_steps > 0:
+        out["training"] = training_block(args)
+    out["roofline"]["copy_gbs"] = copy_bandwidth()
+    if use_alpha:
+        out["hf_cnn"] = hf_block(args, net, f, n, theta, eps)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(n, theta, eps, net, cnn_s["iters"], args.cpu_cycles)
+        if use_alpha:
+            params = {m: v.get().astype(np.float64) for m, v in alpha_nets.items()}
+        else:
+            params = {0: net.get().astype(np.float64)}
+        out["cpu_baseline"] = cpu_baseline(n, theta, eps, params, coarsest, cnn_s["iters"], args.cpu_cycles)
     print(json.dumps(out), flush=True)
 
 
-def inference_block(ctx, net, n, reps=10):
-    """mg_smoother_infer (the network on every level but the coarsest, BF16 MFMA)
-    timed on its own: useful FLOP per second against the dense BF16 peak."""
+def inference_block(ctx, infer, n, coarsest, reps=10):
+    """Smoother inference (the network on every level but the coarsest, BF16
+    MFMA) timed on its own: useful FLOP per second against the dense BF16 peak."""
     import torch
     nodes, m = 0, n
-    while m > 7:
+    while m > coarsest:
         nodes += m * m
         m = (m - 1) // 2
-    ctx.infer(net)
+    infer(ctx)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        ctx.infer(net)
+        infer(ctx)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / reps
     flop = CNN_FLOP_PER_NODE * nodes
@@ -308,7 +364,7 @@ def inference_block(ctx, net, n, reps=10):
             "note": "useful FLOP (halo recomputation not counted); wall time of the call, all levels"}
 
 
-def sweeps_block(args, A, f, n, cnn_s):
+def sweeps_block(args, A, f, n, cnn_s, coarsest):
     """Damped Jacobi with more sweeps per cycle, V(nu, nu), against the CNN's
     V(1,1): a smoother that costs more per application should be compared at
     equal cost (the paper matches its convolution layers with as many Jacobi
@@ -318,7 +374,8 @@ def sweeps_block(args, A, f, n, cnn_s):
     from paper_2102_12071_amd import mgcnn
     out = {"cnn_v11_solve_ms": cnn_s["solve_ms"], "cnn_v11_iters": cnn_s["iters"]}
     for nu in args.sweeps:
-        ctx = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_JACOBI, nu_pre=nu, nu_post=nu))
+        ctx = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_JACOBI, nu_pre=nu, nu_post=nu,
+                                               coarsest_n=coarsest))
         ctx.solve([f], args.tol, args.maxit)  # warm-up
         times = []
         for _ in range(max(args.steps, 1)):
@@ -331,6 +388,143 @@ def sweeps_block(args, A, f, n, cnn_s):
                              "ms_per_iteration": float(res.ms) / max(int(res.iters[0]), 1)}
         log(f"jacobi V({nu},{nu}): {int(res.iters[0])} iterations, {ms:.1f} ms")
         ctx.close()
+    return out
+
+
+def copy_bandwidth(mib=1024, reps=10):
+    """A plain device copy of 1 GiB timed with events: the bandwidth this box
+    reaches on the simplest stream (context for the datasheet peak)."""
+    import torch
+    src = torch.ones((mib << 20) // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
+
+
+def training_block(args):
+    """One training step of the stencil-to-smoother network on the
+    high-frequency loss, BF16 on the matrix cores with FP32 master weights and
+    Adam: 256 problems with n in {31, 63}, theta ~ U[0, pi), log10 eps ~
+    U[-3, 0], 16 high-frequency unit vectors each; inputs resident on the GPU,
+    steps timed back to back.  Useful FLOP: forward and the two backward
+    convolutions (data and weight gradients), 3 x 56,448 per point."""
+    import numpy as np
+    import torch
+
+    import mg_inputs
+    from paper_2102_12071_amd import mgcnn
+    B, J = 256, 16
+    ns, theta, eps = mg_inputs.training_draws(B, 12345, (31, 63))
+    stencils = [mgcnn.stencil_q1_rotated(int(m), float(t), float(e)) for m, t, e in zip(ns, theta, eps)]
+    pools = {m: torch.tensor(mg_inputs.hf_pool(m, 512, 1000 + m), dtype=torch.float32, device="cuda")
+             for m in (31, 63)}
+    rng = np.random.default_rng(7)
+    vectors = [pools[int(m)][torch.tensor(rng.integers(0, 512, J), device="cuda")].contiguous() for m in ns]
+    net = mgcnn.Net()
+    net.set(mg_inputs.cnn_init(0).astype(np.float32))
+    opts = mgcnn.TrainOptions(precision=1, lr=1e-3)
+    for _ in range(2):
+        net.train_step(stencils, vectors, opts, want_loss=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.train_steps):
+        net.train_step(stencils, vectors, opts, want_loss=False)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.train_steps
+    loss, _ = net.train_step(stencils, vectors, mgcnn.TrainOptions(precision=1, apply_update=0))
+    points = int(sum(int(m) ** 2 for m in ns))
+    tflops = 3 * CNN_FLOP_PER_NODE * points / (ms * 1e-3) / 1e12
+    log(f"training: {ms:.2f} ms per step, {tflops:.0f} TFLOP/s useful")
+    return {"problems": B, "vectors_per_problem": J, "points": points, "ms_per_step": ms,
+            "useful_tflops": tflops, "mfma_peak_tflops": BF16_MFMA_PEAK_TFLOPS, "mfma_frac": tflops / BF16_MFMA_PEAK_TFLOPS,
+            "loss_after": loss, "precision": "bf16 MFMA, fp32 master weights, Adam"}
+
+
+def load_alpha_nets(args):
+    """The per-level networks of the adaptive training (Algorithm 2), keyed by
+    level size, from weights/alpha_n<size>.bin beside the single network's
+    checkpoint; None when there are none."""
+    import glob
+
+    from paper_2102_12071_amd import mgcnn
+    files = sorted(glob.glob(os.path.join(os.path.dirname(args.weights), "alpha_n*.bin")))
+    if not files:
+        return None
+    nets = {}
+    for path in files:
+        net = mgcnn.Net()
+        net.load(path)
+        nets[int(os.path.basename(path)[len("alpha_n"):-len(".bin")])] = net
+    return nets
+
+
+def hf_block(args, net, f, n, theta, eps):
+    """The single network trained on the high-frequency loss, on the headline
+    problem and tolerance (its own 7 x 7 coarsest grid), beside the per-level
+    networks of the headline."""
+    import torch
+
+    from paper_2102_12071_amd import mgcnn
+    A = mgcnn.stencil_q1_rotated(n, theta, eps)
+    ctx = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_CNN))
+    ctx.autotune(args.tune_reps)
+    ctx.infer(net)
+    ctx.solve([f], args.tol, args.maxit)  # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.solve([f], args.tol, args.maxit)
+    ms = (time.perf_counter() - t0) * 1e3
+    ctx.close()
+    log(f"single HF network: {int(res.iters[0])} iterations, {ms:.1f} ms")
+    return {"coarsest_n": 7, "iters": int(res.iters[0]), "status": int(res.status[0]),
+            "relres": float(res.relres[0]), "solve_ms": ms}
+
+
+def geometry_block(args, net, alpha_nets, n):
+    """The learned smoothers, trained on the square only, on the paper's other
+    domains (section 6): the square without its upper-right quadrant
+    (L-shape) and without a disk of radius 1/5 about the centre (cylinder),
+    zero Dirichlet values on the removed nodes, theta = pi/4, eps = 0.01;
+    iterations and solve time to the headline tolerance of the single
+    network (7 x 7 coarsest grid), of the per-level networks when given
+    (3 x 3), and of damped Jacobi."""
+    import torch
+
+    import mg_inputs
+    from paper_2102_12071_amd import mgcnn
+    out = {}
+    runs = [("cnn", mgcnn.SMOOTHER_CNN, 7, lambda c: c.infer(net)), ("jacobi", mgcnn.SMOOTHER_JACOBI, 7, None)]
+    if alpha_nets:
+        runs.append(("alpha_cnn", mgcnn.SMOOTHER_CNN, 3, lambda c: c.infer_levels(alpha_nets)))
+    for kind in ("lshape", "cylinder"):
+        m = mg_inputs.domain_mask(n, kind)
+        A = mgcnn.stencil_mask(mgcnn.stencil_q1_rotated(n, math.pi / 4, 0.01), torch.tensor(m, device="cuda"))
+        f = torch.tensor(mg_inputs.rhs_uniform(n, 0) * m, dtype=torch.float64, device="cuda")
+        row = {"inside_nodes": int(m.sum())}
+        for name, sm, coarsest, infer in runs:
+            ctx = mgcnn.Context([A], mgcnn.Options(smoother=sm, coarsest_n=coarsest))
+            if infer:
+                infer(ctx)
+            ctx.solve([f], args.tol, args.maxit)  # warm-up (graph capture)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res = ctx.solve([f], args.tol, args.maxit)
+            row[name] = {"iters": int(res.iters[0]), "status": int(res.status[0]),
+                         "solve_ms": (time.perf_counter() - t0) * 1e3}
+            ctx.close()
+        row["iteration_ratio"] = row["jacobi"]["iters"] / max(row["cnn"]["iters"], 1)
+        row["time_ratio"] = row["jacobi"]["solve_ms"] / row["cnn"]["solve_ms"]
+        log(f"{kind}: CNN {row['cnn']['iters']} vs Jacobi {row['jacobi']['iters']} iterations"
+            + (f"; per-level networks {row['alpha_cnn']['iters']} (status {row['alpha_cnn']['status']})"
+               if alpha_nets else ""))
+        out[kind] = row
     return out
 
 
@@ -466,24 +660,27 @@ def workload_c5(args):
                       "config": out}), flush=True)
 
 
-def cpu_baseline(n, theta, eps, net, gpu_iters, cycles):
+def cpu_baseline(n, theta, eps, params, coarsest, gpu_iters, cycles):
     """The FP64 oracle on the host cores: stencil, hierarchy, CNN inference on
     every level and a bounded number of V(1,1) cycles, extrapolated to the
-    GPU's iteration count."""
-    import numpy as np
-
+    GPU's iteration count.  params: network parameters keyed by level size (a
+    level takes the nearest trained size, as on the GPU; one key: every level)."""
     import mg_inputs
     import oracle
 
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    params = net.get().astype(np.float64)
+    sizes = sorted(params)
+
+    def for_size(m):
+        return params[min(sizes, key=lambda q: (abs(math.log2(q + 1) - math.log2(m + 1)), -q))]
+
     f = mg_inputs.rhs_uniform(n, 0)
     t0 = time.perf_counter()
     A = oracle.stencil_q1_rotated(n, theta, eps)
-    h = oracle.Hierarchy(A)
+    h = oracle.Hierarchy(A, coarsest)
     t1 = time.perf_counter()
     for l in range(h.num_levels - 1):
-        h.set_smoother(l, oracle.cnn_forward(h.stencil(l), params))
+        h.set_smoother(l, oracle.cnn_forward(h.stencil(l), for_size(h.level_n(l))))
     t2 = time.perf_counter()
     _, k, _, _ = h.solve(f, 0.0, cycles, 1, 1)
     t3 = time.perf_counter()

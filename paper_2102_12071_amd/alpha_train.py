@@ -11,7 +11,7 @@ a fresh k_b ~ U{1, ..., b} per problem.
 
 Training set of a stage (seeded): rotated anisotropic bilinear stencils with
 theta ~ U[0, pi) and log10 eps ~ U[-3, 0]; f ~ U(-1, 1) per node; u* the
-exact solution (an FP64 multigrid solve to 1e-13); u0 ~ N(0, 1).
+exact solution (FP64 FGMRES with the multigrid cycle, to 1e-13); u0 ~ N(0, 1).
 
     python -m paper_2102_12071_amd.alpha_train --steps 400 --out-dir paper_2102_12071_amd/weights
 """
@@ -82,7 +82,8 @@ class Stage:
             self.u0 += list(inject)
         self.Q = len(As)
         self.top = mgcnn.Context(As, fp64)
-        res = self.top.solve(self.f, 1e-13, 5000)  # zero right-hand sides: u* = 0 at once
+        # exact solutions by FP64 FGMRES with the Jacobi cycle (zero right-hand sides: u* = 0 at once)
+        res = self.top.solve_fgmres(self.f, 1e-13, 3000, restart=60)
         if not (res.relres <= 1e-12).all():
             raise RuntimeError("exact solutions of the training set did not converge")
         self.u_star = res.u
@@ -148,7 +149,9 @@ def train(finest: int = 63, Q: int = 50, steps: int = 400, lr: float = 1e-3, bma
           init: Optional[str] = None, coarsest: int = 3, lr_final: Optional[float] = None,
           log=print) -> Dict[int, mgcnn.Net]:
     """Runs every stage; returns the trained network of each level size.  The
-    learning rate decays geometrically from lr to lr_final over a stage."""
+    learning rate decays geometrically from lr to lr_final over a stage; a
+    stage keeps the parameters with the lowest loss at k = b cycles on its
+    training set (checked every 100 steps, and at the start)."""
     nets: Dict[int, mgcnn.Net] = {}
     lr_final = lr if lr_final is None else lr_final
     for n in stage_sizes(finest, coarsest):
@@ -160,12 +163,17 @@ def train(finest: int = 63, Q: int = 50, steps: int = 400, lr: float = 1e-3, bma
         else:
             net.set(mg_inputs.cnn_init(seed + n).astype(np.float32))  # zero last layer: damped Jacobi
         first = stage.monitor(net, bmax)
+        best, best_params = first, net.get()
         for s in range(steps):
             rate = lr * (lr_final / lr) ** (s / max(steps - 1, 1))
             r = stage.step(net, mgcnn.TrainOptions(lr=rate, precision=0), bmax)
-            if s % 100 == 0 or s == steps - 1:
-                log(json.dumps({"stage_n": n, "step": s, "loss": r.loss, f"loss_k{bmax}": stage.monitor(net, bmax),
+            if s % 100 == 99 or s == steps - 1:
+                mon = stage.monitor(net, bmax)
+                if mon < best:
+                    best, best_params = mon, net.get()
+                log(json.dumps({"stage_n": n, "step": s, "loss": r.loss, f"loss_k{bmax}": mon,
                                 "lr": rate, "elapsed_s": round(time.perf_counter() - t0, 3)}))
+        net.set(best_params)  # the parameters with the lowest loss at k = b cycles
         last = stage.monitor(net, bmax)
         stage.close()
         nets[n] = net
@@ -186,8 +194,14 @@ def update(nets: Dict[int, mgcnn.Net], Q: int = 50, steps: int = 400, lr: float 
             inj, growth = inject_errors(n, Q, nets, seed, cycles, coarsest, rnd)
             stage = Stage(n, Q, {m: v for m, v in nets.items() if m < n}, seed, coarsest, inject=inj)
             first = stage.monitor(nets[n], bmax)
+            best, best_params = first, nets[n].get()
             for s in range(steps):
                 stage.step(nets[n], mgcnn.TrainOptions(lr=lr, precision=0), bmax)
+                if s % 100 == 99 or s == steps - 1:
+                    mon = stage.monitor(nets[n], bmax)
+                    if mon < best:
+                        best, best_params = mon, nets[n].get()
+            nets[n].set(best_params)
             last = stage.monitor(nets[n], bmax)
             stage.close()
             _, after = inject_errors(n, Q, nets, seed + 1, cycles, coarsest, rnd)

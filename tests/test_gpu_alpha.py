@@ -185,3 +185,27 @@ def test_arguments(mg):
     assert e.value.status == mg.MG_ERR_ARG
     # a valid call still works afterwards
     assert mg.alpha_step(top, coarse, coarse_t, net, [1, 2], fd, u0d, usd, o).loss > 0
+
+
+def test_committed_per_level_networks_beat_jacobi(mg):
+    # the checkpoints of the adaptive training (weights/alpha_n*.bin, one network per level size)
+    # on problems they were not trained on: fewer cycles than damped Jacobi, to a true 1e-8
+    import math
+    import os
+    from paper_2102_12071_amd.alpha_train import load_nets
+    nets = load_nets(os.path.join(os.path.dirname(mg.__file__), "weights"))
+    assert sorted(nets) == [7, 15, 31, 63]
+    for n, theta, eps, gain in ((255, math.pi / 3, 1e-3, 3.0), (63, math.pi / 6, 0.01, 3.0), (127, 2.0, 0.1, 1.2)):
+        A = mg.stencil_q1_rotated(n, theta, eps)
+        f = _dev(mg_inputs.rhs_uniform(n, 1))
+        iters = {}
+        for name, sm in (("alpha", mg.SMOOTHER_CNN), ("jacobi", mg.SMOOTHER_JACOBI)):
+            ctx = mg.Context([A], mg.Options(smoother=sm, coarsest_n=3))
+            if sm == mg.SMOOTHER_CNN:
+                ctx.infer_levels(nets)
+            res = ctx.solve([f], 1e-8, 5000)
+            assert res.status[0] == 0, (n, name)
+            r = f.cpu().numpy() - ora.matvec(A.cpu().numpy(), res.u[0].cpu().numpy())
+            assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(f.cpu().numpy())
+            iters[name] = int(res.iters[0])
+        assert iters["alpha"] * gain < iters["jacobi"], (n, iters)

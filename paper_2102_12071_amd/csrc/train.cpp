@@ -163,8 +163,8 @@ size_t fp32_scratch(const mg_net_s &net, const mg_train_batch *b)
 // BF16 path: channel-last activations, MFMA convolutions.
 struct Bf16Layout {
     std::vector<size_t> off;
-    size_t desc, pack_fwd[4], pack_bwd[4], bias[4], part;
-    int ntiles;
+    size_t desc, pack_fwd[4], pack_bwd[4], bias[4], part, part2, respart;
+    int ntiles, resblk;
     size_t bytes;
 };
 
@@ -188,6 +188,11 @@ Bf16Layout bf16_layout(const mg_train_batch *b)
         L.bias[l] = lay.take(32 * sizeof(float));
     }
     L.part = lay.take((size_t)L.ntiles * (9 * 32 * 32 + 32) * sizeof(float));
+    L.part2 = lay.take(trb_reduce_scratch_bytes());
+    int nmax = 0;
+    for (int q = 0; q < B; ++q) nmax = std::max(nmax, (int)b->n[q]);
+    L.resblk = trb_residual_blocks(nmax);
+    L.respart = lay.take(sizeof(double) * (size_t)B * L.resblk * J);
     L.bytes = lay.bytes;
     return L;
 }
@@ -245,12 +250,14 @@ mg_status step_bf16(mg_net_s &net, const mg_train_batch *b, const mg_train_opts 
         for (const Cls &c : classes) launch_trb_conv_fwd(d_desc + c.first, c.count, c.n, l, pf[l], bias[l], st);
     for (const Cls &c : classes) {
         launch_trb_av(d_desc + c.first, c.count, c.n, J, st);
-        launch_trb_residual_norm(d_desc + c.first, c.count, J, (float)o.omega, loss_part, st);
+        launch_trb_residual_norm(d_desc + c.first, c.count, c.n, J, (float)o.omega, loss_part,
+                                 (double *)(base + L.respart), L.resblk, st);
         launch_trb_dout(d_desc + c.first, c.count, c.n, J, scale, st);
     }
     for (int l = 3; l >= 0; --l) {
         for (const Cls &c : classes) launch_trb_wgrad(d_desc + c.first, c.count, c.n, l, layers[l].cout, part, st);
-        launch_trb_reduce(part, L.ntiles, layers[l].cin, layers[l].cout, layers[l].woff, layers[l].boff, net.grad, st);
+        launch_trb_reduce(part, L.ntiles, layers[l].cin, layers[l].cout, layers[l].woff, layers[l].boff, net.grad,
+                          (float *)(base + L.part2), st);
         if (l > 0)
             for (const Cls &c : classes) launch_trb_conv_bwd_data(d_desc + c.first, c.count, c.n, l, pb[l], st);
     }

@@ -77,10 +77,15 @@ void launch_trb_conv_fwd(const TrainProbB *probs, int nb, int n, int layer, cons
 void launch_trb_conv_bwd_data(const TrainProbB *probs, int nb, int n, int layer, const bf16_t *wpack_t,
                               hipStream_t st);
 void launch_trb_wgrad(const TrainProbB *probs, int nb, int n, int layer, int cout, float *part, hipStream_t st);
+// part2: trb_reduce_scratch_bytes() of scratch for the per-slice sums
 void launch_trb_reduce(const float *part, int ntiles, int cin, int cout, int64_t woff, int64_t boff, float *grad,
-                       hipStream_t st);
+                       float *part2, hipStream_t st);
+size_t trb_reduce_scratch_bytes();
 void launch_trb_av(const TrainProbB *probs, int nb, int n, int J, hipStream_t st);
-void launch_trb_residual_norm(const TrainProbB *probs, int nb, int J, float omega, float *loss_part, hipStream_t st);
+// part: FP64 [problems][nblk][J] block sums, nblk = trb_residual_blocks(largest n) (problem = TrainProbB.index)
+void launch_trb_residual_norm(const TrainProbB *probs, int nb, int n, int J, float omega, float *loss_part,
+                              double *part, int nblk, hipStream_t st);
+int trb_residual_blocks(int nmax);
 void launch_trb_dout(const TrainProbB *probs, int nb, int n, int J, float scale, hipStream_t st);
 
 }  // namespace mg

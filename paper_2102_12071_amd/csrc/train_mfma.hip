@@ -230,36 +230,69 @@ __global__ void __launch_bounds__(kT) k_trb_av(const TrainProbB *probs, int J)
     P.Av[(int64_t)jv * P.plane + p] = acc;
 }
 
-// g_j = v_j - H A v_j, ||g_j||; H from y (channel-last FP32).  One block per (problem, vector).
-__global__ void __launch_bounds__(kT) k_trb_residual_norm(const TrainProbB *probs, int J, float omega,
-                                                          float *loss_part)
+// g_j = v_j - H A v_j for every vector j of a problem, one thread per pixel:
+// the pixel's 25 smoother taps are read once for all J vectors.  Per block and
+// vector, the sum of g_j^2 (FP64, waves then the block in a fixed order) goes
+// to part[problem][block][j].  grid = (pixel blocks, 1, problems).
+constexpr int kJChunk = 64;
+__global__ void __launch_bounds__(kT) k_trb_residual(const TrainProbB *probs, int J, float omega, double *part,
+                                                     int nblk)
 {
-    __shared__ double red[kT / 64];
-    const TrainProbB &P = probs[blockIdx.x / J];
-    const int jv = blockIdx.x % J;
+    __shared__ double red[kT / 64][kJChunk];
+    const TrainProbB &P = probs[blockIdx.z];
+    const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const bool live = p < P.plane;
     const int n = P.n;
-    const float MG_G *Av = P.Av + (int64_t)jv * P.plane;
-    const float MG_G *v = P.V + (int64_t)jv * P.plane;
-    float MG_G *gq = P.g + (int64_t)jv * P.plane;
-    double acc2 = 0.0;
-    for (int64_t p = threadIdx.x; p < P.plane; p += kT) {
-        const int i = (int)(p % n), j = (int)(p / n);
-        float y = 0.0f;
+    const int64_t pc = live ? p : 0;
+    const int i = (int)(pc % n), j = (int)(pc / n);
+    float w[25];
 #pragma unroll
-        for (int k = 0; k < 25; ++k) {
-            const int ii = i + k % 5 - 2, jj = j + k / 5 - 2;
-            const bool ok = in_grid(n, ii, jj);
-            const float wk = P.y[p * 32 + k] + (k == 12 ? omega : 0.0f);
-            const float xv = Av[ok ? (int64_t)jj * n + ii : p];
-            y += wk * (ok ? xv : 0.f);
-        }
-        y /= (float)P.A[kCentre * P.plane + p];
-        const float gv = v[p] - y;
-        gq[p] = gv;
-        acc2 += (double)gv * gv;
+    for (int k = 0; k < 25; ++k) w[k] = P.y[pc * 32 + k] + (k == 12 ? omega : 0.0f);
+    const float inv_ac = 1.0f / (float)P.A[kCentre * P.plane + pc];
+    int64_t off[25];
+    bool ok[25];
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+        const int ii = i + k % 5 - 2, jj = j + k / 5 - 2;
+        ok[k] = in_grid(n, ii, jj);
+        off[k] = ok[k] ? (int64_t)jj * n + ii : pc;
     }
-    const double s = block_sum<kT>(acc2, red);
-    if (threadIdx.x == 0) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double *out = part + ((int64_t)P.index * nblk + blockIdx.x) * J;
+    for (int j0 = 0; j0 < J; j0 += kJChunk) {
+        const int jn = min(kJChunk, J - j0);
+        for (int q = 0; q < jn; ++q) {
+            const int jv = j0 + q;
+            const float MG_G *Av = P.Av + (int64_t)jv * P.plane;
+            float y = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 25; ++k) {
+                const float xv = Av[off[k]];
+                y += w[k] * (ok[k] ? xv : 0.f);
+            }
+            const float gv = P.V[(int64_t)jv * P.plane + pc] - y * inv_ac;
+            if (live) P.g[(int64_t)jv * P.plane + p] = gv;
+            const double s = wave_sum(live ? (double)gv * gv : 0.0);
+            if (lane == 0) red[wave][q] = s;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < jn) {
+            double s = 0.0;
+            for (int w2 = 0; w2 < kT / 64; ++w2) s += red[w2][threadIdx.x];
+            out[j0 + threadIdx.x] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// ||g_j|| from the block sums, in block order; one thread per vector.
+__global__ void k_trb_norms(const TrainProbB *probs, int J, const double *part, int nblk, float *loss_part)
+{
+    const TrainProbB &P = probs[blockIdx.x];
+    const int nb = (int)((P.plane + kT - 1) / kT);
+    for (int jv = threadIdx.x; jv < J; jv += blockDim.x) {
+        double s = 0.0;
+        for (int b = 0; b < nb; ++b) s += part[((int64_t)P.index * nblk + b) * J + jv];
         const float gn = (float)sqrt(s);
         P.gnorm[jv] = gn;
         loss_part[P.index * J + jv] = gn;
@@ -293,8 +326,30 @@ __global__ void __launch_bounds__(kT) k_trb_dout(const TrainProbB *probs, int J,
     for (int k = 0; k < 32; ++k) P.dA[p * 32 + k] = f32_to_bf16(k < 25 ? acc[k < 25 ? k : 0] : 0.f);
 }
 
-// grad[flat] = sum over tiles of the per-tile parts, in tile order.
-__global__ void __launch_bounds__(kT) k_trb_reduce(const float *part, int ntiles, int cin, int cout, int64_t woff,
+// grad[flat] = sum over tiles of the per-tile parts, in two deterministic
+// stages.  Stage 1: block (column block, slice) sums the tiles of its slice
+// for 64 consecutive columns (4 row groups, interleaved tiles, combined in
+// order in LDS) into part2[slice][column].  Stage 2: one thread per parameter
+// sums the slices in order and scatters to the flat layout.
+constexpr int kPartCols = 9 * 32 * 32 + 32;
+constexpr int kReduceSlices = 32;
+__global__ void __launch_bounds__(kT) k_trb_reduce_slices(const float *part, int ntiles, float *part2)
+{
+    __shared__ float red[4][64];
+    const int c = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int col = blockIdx.x * 64 + c;
+    const int per = (ntiles + kReduceSlices - 1) / kReduceSlices;
+    const int t0 = blockIdx.y * per, t1 = min(ntiles, t0 + per);
+    float s = 0.f;
+    if (col < kPartCols)
+        for (int t = t0 + grp; t < t1; t += 4) s += part[(int64_t)t * kPartCols + col];
+    red[grp][c] = s;
+    __syncthreads();
+    if (grp == 0 && col < kPartCols)
+        part2[(int64_t)blockIdx.y * kPartCols + col] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+__global__ void __launch_bounds__(kT) k_trb_reduce(const float *part2, int cin, int cout, int64_t woff,
                                                    int64_t boff, float *grad)
 {
     const int q = blockIdx.x * kT + threadIdx.x;
@@ -310,7 +365,7 @@ __global__ void __launch_bounds__(kT) k_trb_reduce(const float *part, int ntiles
         dst = boff + (q - nw);
     }
     float s = 0.f;
-    for (int t = 0; t < ntiles; ++t) s += part[(int64_t)t * (9 * 32 * 32 + 32) + src];
+    for (int t = 0; t < kReduceSlices; ++t) s += part2[(int64_t)t * kPartCols + src];
     grad[dst] = s;
 }
 
@@ -406,20 +461,27 @@ void launch_trb_wgrad(const TrainProbB *probs, int nb, int n, int layer, int cou
 }
 
 void launch_trb_reduce(const float *part, int ntiles, int cin, int cout, int64_t woff, int64_t boff, float *grad,
-                       hipStream_t st)
+                       float *part2, hipStream_t st)
 {
-    k_trb_reduce<<<blocks_for(cout * cin * 9 + cout), kT, 0, st>>>(part, ntiles, cin, cout, woff, boff, grad);
+    k_trb_reduce_slices<<<dim3((kPartCols + 63) / 64, kReduceSlices), kT, 0, st>>>(part, ntiles, part2);
+    k_trb_reduce<<<blocks_for(cout * cin * 9 + cout), kT, 0, st>>>(part2, cin, cout, woff, boff, grad);
 }
+
+size_t trb_reduce_scratch_bytes() { return sizeof(float) * (size_t)kReduceSlices * kPartCols; }
 
 void launch_trb_av(const TrainProbB *probs, int nb, int n, int J, hipStream_t st)
 {
     k_trb_av<<<dim3(blocks_for((int64_t)n * n), 1, nb * J), kT, 0, st>>>(probs, J);
 }
 
-void launch_trb_residual_norm(const TrainProbB *probs, int nb, int J, float omega, float *loss_part, hipStream_t st)
+void launch_trb_residual_norm(const TrainProbB *probs, int nb, int n, int J, float omega, float *loss_part,
+                              double *part, int nblk, hipStream_t st)
 {
-    k_trb_residual_norm<<<nb * J, kT, 0, st>>>(probs, J, omega, loss_part);
+    k_trb_residual<<<dim3(blocks_for((int64_t)n * n), 1, nb), kT, 0, st>>>(probs, J, omega, part, nblk);
+    k_trb_norms<<<nb, 64, 0, st>>>(probs, J, part, nblk, loss_part);
 }
+
+int trb_residual_blocks(int nmax) { return (int)blocks_for((int64_t)nmax * nmax); }
 
 void launch_trb_dout(const TrainProbB *probs, int nb, int n, int J, float scale, hipStream_t st)
 {

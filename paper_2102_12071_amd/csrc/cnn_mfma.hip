@@ -31,7 +31,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kTO = 16;                       // output tile side
 constexpr int kT = 256;                       // 4 waves
 constexpr int kR0 = kTO + 8, kR1 = kTO + 6, kR2 = kTO + 4, kR3 = kTO + 2;
-constexpr int kCS0 = 16, kCS = 32;            // channel strides (bf16) of the input and hidden buffers
+// channel strides (bf16) of the input and hidden buffers: 16 and 32 channels padded to 24 and 40, so
+// that the 16 pixels a ds_read_b128 of one lane group reads start in distinct groups of four banks
+// (strides of 12 and 20 dwords; 8 and 16 dwords put four lanes on one bank group)
+constexpr int kCS0 = 24, kCS = 40;
 constexpr int kSteps[4] = {5, 9, 9, 9};       // K steps of 32 per layer
 // packed B fragments: [layer][step][n-block][lane][8] bf16
 constexpr int kPackOff[5] = {0, 5 * 2 * 64 * 8, 14 * 2 * 64 * 8, 23 * 2 * 64 * 8, 32 * 2 * 64 * 8};

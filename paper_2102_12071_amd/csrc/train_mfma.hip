@@ -50,7 +50,10 @@ template <int CSIN, int STEPS, bool FIRST, int EPI>
 __global__ void __launch_bounds__(kT) k_trb_conv(const TrainProbB *probs, const bf16_t *wpack, const float *bias,
                                                  int in_sel, int out_sel, int mask_sel)
 {
-    __shared__ __align__(16) bf16_t tin[kHalo * kHalo * CSIN];
+    // pixel stride CSIN + 8 bf16 (12 or 20 dwords): the 16 pixels of one lane group's ds_read_b128
+    // start in distinct groups of four banks (a stride of CSIN puts two or four lanes on one group)
+    constexpr int LD = CSIN + 8;
+    __shared__ __align__(16) bf16_t tin[kHalo * kHalo * LD];
     const TrainProbB &P = probs[blockIdx.z];
     const int n = P.n;
     const int X0 = blockIdx.x * kTile, Y0 = blockIdx.y * kTile;
@@ -66,7 +69,7 @@ __global__ void __launch_bounds__(kT) k_trb_conv(const TrainProbB *probs, const 
         const int64_t p = ok ? (int64_t)gj * n + gi : 0;
         u32x4 v = *(const u32x4 MG_G *)(in + p * CSIN + c8 * 8);
         if (!ok) v = u32x4{0u, 0u, 0u, 0u};
-        *(u32x4 *)(tin + pix * CSIN + c8 * 8) = v;
+        *(u32x4 *)(tin + pix * LD + c8 * 8) = v;
     }
     bf16x8 bw[STEPS][2];
     const bf16_t MG_G *wp = (const bf16_t MG_G *)wpack;
@@ -95,7 +98,7 @@ __global__ void __launch_bounds__(kT) k_trb_conv(const TrainProbB *probs, const 
                 a = bf16x8{};
             } else {
                 const int ky = tap / 3, kx = tap - 3 * (tap / 3);
-                a = *(const bf16x8 *)(tin + ((oy + ky) * kHalo + ox + kx) * CSIN + cg * 8);
+                a = *(const bf16x8 *)(tin + ((oy + ky) * kHalo + ox + kx) * LD + cg * 8);
             }
             acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[s][0], acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[s][1], acc1, 0, 0, 0);
@@ -133,7 +136,9 @@ template <int CIN>
 __global__ void __launch_bounds__(kT) k_trb_wgrad(const TrainProbB *probs, int dy_sel, int x_sel, int cout,
                                                   float *part)
 {
-    __shared__ __align__(16) bf16_t dyT[32][kTile * kTile];
+    // rows padded by 8 bf16 (132 dwords): the 16 channel rows one lane group reads with ds_read_b128
+    // start in distinct groups of four banks (256 would put them all on one)
+    __shared__ __align__(16) bf16_t dyT[32][kTile * kTile + 8];
     __shared__ bf16_t xT[CIN][kHalo * kHalo];
     const TrainProbB &P = probs[blockIdx.z];
     const int n = P.n;

@@ -320,8 +320,11 @@ def main():
     }
 
     # the fused MFMA inference kernel's rate: one call of the single network over every level
-    # (the per-level networks make one call per level size; their time is in cnn.infer_ms)
-    out["inference"] = inference_block(ctx_cnn, lambda c: c.infer(net), n, coarsest)
+    # (the per-level networks make one call per level size; their time is in cnn.infer_ms), on a
+    # context of its own so that the headline context keeps its smoothers for the blocks below
+    ctx_inf = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_CNN, coarsest_n=coarsest))
+    out["inference"] = inference_block(ctx_inf, lambda c: c.infer(net), n, coarsest)
+    ctx_inf.close()
     if args.restart > 0:
         out["fgmres"] = fgmres_block(args, ctx_cnn, ctx_jac, f, n)
     if args.sweeps:

@@ -144,11 +144,12 @@ mg_status mg_get_stencil(mg_ctx ctx, int32_t prob, int32_t level, double *out);
  * the resulting smoothers (section 4.2: stencil -> per-point smoothing kernel)
  * in the context.  In mixed precision the network runs in BF16 on MFMA with
  * FP32 accumulation and the smoother is stored in BF16; in FP64 precision
- * every operation is FP64.  A row without a negative off-centre entry gets
- * damped Jacobi, W = omega * delta_0, instead of the network's output: every
- * diffusion row has one, the Dirichlet nodes of mg_stencil_mask and their
- * Galerkin images on coarser levels do not.  Required before solving with
- * MG_SMOOTHER_CNN. */
+ * every operation is FP64.  A row whose off-centre entries do not sum to a
+ * negative value gets damped Jacobi, W = omega * delta_0, instead of the
+ * network's output: the off-centre entries of a diffusion row sum to -a_C
+ * inside the domain, while the Dirichlet nodes of mg_stencil_mask and their
+ * Galerkin images on coarser levels do not sum to a negative value.
+ * Required before solving with MG_SMOOTHER_CNN. */
 mg_status mg_smoother_infer(mg_ctx ctx, mg_net net);
 
 /* Runs the network on the smoothing levels of size n only (every problem),

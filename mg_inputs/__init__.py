@@ -106,6 +106,26 @@ def domain_mask(n: int, kind: str) -> np.ndarray:
     return out.astype(np.uint8)
 
 
+def random_domain_mask(n: int, rng: np.random.Generator) -> np.ndarray:
+    """A random domain inside the unit square (uint8 [n, n], 1 inside): with
+    equal odds, the square without a disk (centre ~ U(0.25, 0.75)^2, radius ~
+    U(0.08, 0.3)) or without one corner rectangle [a, 1] x [b, 1] mirrored to a
+    random corner (a, b ~ U(0.3, 0.7)); boundaries of the removed part included."""
+    h = 1.0 / (n + 1)
+    x = (np.arange(n) + 1) * h
+    X, Y = np.meshgrid(x, x)
+    if rng.uniform() < 0.5:
+        cx, cy = rng.uniform(0.25, 0.75, 2)
+        r = rng.uniform(0.08, 0.3)
+        out = (X - cx) ** 2 + (Y - cy) ** 2 > r * r
+    else:
+        a, b = rng.uniform(0.3, 0.7, 2)
+        Xc = X if rng.uniform() < 0.5 else 1.0 - X
+        Yc = Y if rng.uniform() < 0.5 else 1.0 - Y
+        out = ~((Xc >= a) & (Yc >= b))
+    return out.astype(np.uint8)
+
+
 def cnn_param_count(channels=CNN_CHANNELS) -> int:
     return sum(channels[l + 1] * channels[l] * 9 + channels[l + 1] for l in range(len(channels) - 1))
 

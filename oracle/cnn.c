@@ -82,14 +82,16 @@ void ora_cnn_forward(int n, const double *A, int nlayers, const int *ch, const d
     const int cout = ch[nlayers];
     for (int k = 0; k < cout; ++k)
         for (int64_t p = 0; p < nn; ++p) W[k * nn + p] = pre[nlayers - 1][k * nn + p] + (k == 12 ? omega : 0.0);
-    /* every diffusion row has a negative off-centre entry; a row without one
-     * (a Dirichlet node of a masked domain, and its Galerkin images on coarser
-     * levels) is not a stencil the network was made for: damped Jacobi there */
+    /* the off-centre entries of a diffusion row sum to a negative value (to
+     * -a_C inside the domain, where rows sum to zero); a row whose off-centre
+     * sum is not negative (a Dirichlet node of a masked domain and its
+     * Galerkin images on coarser levels, where coarsened Dirichlet rows weigh
+     * in) is not a stencil the network was made for: damped Jacobi there */
     for (int64_t p = 0; p < nn; ++p) {
-        int diffusion = 0;
+        double off = 0.0;
         for (int c = 0; c < 9; ++c)
-            if (c != 4 && A[c * nn + p] < 0.0) diffusion = 1;
-        if (!diffusion)
+            if (c != 4) off += A[c * nn + p];
+        if (off >= 0.0)
             for (int k = 0; k < cout; ++k) W[k * nn + p] = k == 12 ? omega : 0.0;
     }
     for (int l = 0; l < nlayers; ++l) free(pre[l]);

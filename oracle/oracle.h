@@ -129,8 +129,8 @@ int64_t ora_cnn_num_params(int nlayers, const int *ch);
  * cross-correlation, weights [Cout][Cin][3][3] followed by bias[Cout]),
  * ReLU after every layer but the last; output W = omega*delta_0 + x_L
  * (delta_0 is 1 in channel 12, the centre of the 5x5 stencil), except on
- * rows without a negative off-centre entry (Dirichlet nodes of a masked
- * domain and their Galerkin images; every diffusion row has one), where
+ * rows whose off-centre entries do not sum to a negative value (Dirichlet
+ * nodes of a masked domain and their Galerkin images), where
  * W = omega*delta_0 (damped Jacobi).  W: [25][n][n]. */
 void ora_cnn_forward(int n, const double *A, int nlayers, const int *ch,
                      const double *params, double omega, double *W);

@@ -66,11 +66,13 @@ __global__ void k_cnn_output(int n, int P, int64_t plane, const T *A, const T *y
     if (i >= n || j >= n) return;
     const int64_t p = (int64_t)j * P + i;
     const T ac = A[kCentre * plane + p];
-    // every diffusion row has a negative off-centre entry; rows without one (Dirichlet nodes of a
-    // masked domain and their Galerkin images) take damped Jacobi
-    bool diffusion = false;
+    // a diffusion row's off-centre entries sum to a negative value; other rows (Dirichlet nodes of a
+    // masked domain and their Galerkin images) take damped Jacobi.  Summed in channel order.
+    T off = 0;
 #pragma unroll
-    for (int c = 0; c < kStencil; ++c) diffusion = diffusion || (c != kCentre && A[c * plane + p] < (T)0);
+    for (int c = 0; c < kStencil; ++c)
+        if (c != kCentre) off += A[c * plane + p];
+    const bool diffusion = off < (T)0;
 #pragma unroll
     for (int k = 0; k < kSmoother; ++k) {
         const T wv = (diffusion ? y[k * plane + p] : (T)0) + (k == 12 ? omega : (T)0);

@@ -2,7 +2,9 @@
 // the field of operator stencils to per-point smoothing kernels), all four
 // layers of 3x3 convolutions (9 -> 32 -> 32 -> 32 -> 25) in one kernel.
 //
-// Each workgroup produces a kTO x kTO tile of smoother stencils.  It reads
+// Each workgroup produces a kTO x kTO tile of smoother stencils; one launch
+// covers every level of every problem (a table of levels, tiles numbered
+// level after level).  It reads
 // the stencil field on the tile plus a halo of four nodes (one per layer),
 // forms the network input x0 = A / a_C, and runs the layers on shrinking
 // regions (tile + 6, + 4, + 2, + 0), keeping the activations in LDS in BF16,
@@ -12,8 +14,8 @@
 // input channels are padded to sixteen, so one K step of 32 covers two taps.
 // Activations at nodes outside the grid are set to zero after every layer:
 // this is the per-layer zero padding of "same" convolutions.  The last layer
-// writes H = (omega*delta_0 + y) / a_C in BF16 (y = 0 on rows without a
-// negative off-centre entry).
+// writes H = (omega*delta_0 + y) / a_C in BF16 (y = 0 on rows whose
+// off-centre entries do not sum to a negative value).
 //
 // MFMA operand layout used (16x16x32, wave of 64): lane l supplies
 // A[m = l % 16][k = 8 (l / 16) + e] and B[k = 8 (l / 16) + e][n = l % 16],
@@ -112,13 +114,12 @@ __device__ inline void conv_layer(const bf16_t *in, int CSin, int Wo, bf16_t *ou
     }
 }
 
-__global__ void __launch_bounds__(kT) k_cnn_fused(int n, int P, int64_t plane, const float *A32, const PackedNet *pkg,
-                                                  float omega, bf16_t *H)
+// The whole network on the tile at (X0, Y0) of one level.
+__device__ inline void cnn_tile(int n, int P, int64_t plane, const float MG_G *A32, const PackedNet MG_G *pk,
+                                float omega, bf16_t MG_G *H, int X0, int Y0)
 {
     __shared__ __align__(16) bf16_t bufX[kBufX];
     __shared__ __align__(16) bf16_t bufY[kBufY];
-    const PackedNet MG_G *pk = (const PackedNet MG_G *)pkg;
-    const int X0 = blockIdx.x * kTO, Y0 = blockIdx.y * kTO;
     const int tid = threadIdx.x;
     // network input x0 = A / a_C on the tile plus a halo of four (zero off the grid)
     for (int q = tid; q < kR0 * kR0; q += kT) {
@@ -148,15 +149,36 @@ __global__ void __launch_bounds__(kT) k_cnn_fused(int n, int P, int64_t plane, c
         if (gy >= n || gx >= n) continue;
         const int64_t p = (int64_t)gy * P + gx;
         const float inv = 1.0f / A32[kCentre * plane + p];
-        // every diffusion row has a negative off-centre entry; rows without one (Dirichlet nodes of a
-        // masked domain and their Galerkin images) take damped Jacobi
-        bool diffusion = false;
+        // a diffusion row's off-centre entries sum to a negative value; other rows (Dirichlet nodes of
+        // a masked domain and their Galerkin images) take damped Jacobi.  Summed in channel order.
+        float off = 0.f;
 #pragma unroll
-        for (int c = 0; c < 9; ++c) diffusion = diffusion || (c != kCentre && A32[c * plane + p] < 0.f);
+        for (int c = 0; c < 9; ++c)
+            if (c != kCentre) off += A32[c * plane + p];
+        const bool diffusion = off < 0.f;
 #pragma unroll
         for (int k = 0; k < 25; ++k)
             H[k * plane + p] = f32_to_bf16(((diffusion ? stage[q * 25 + k] : 0.f) + (k == 12 ? omega : 0.f)) * inv);
     }
+}
+
+// One launch for every level of every problem: block b takes tile
+// b - tile0 of the level whose [tile0, tile0 + tiles) holds b (levels in
+// launch order, largest first, so the small ones fill the tail).  With
+// size_filter != 0 only the levels of that size are computed.
+__global__ void __launch_bounds__(kT) k_cnn_fused_levels(const CnnLevelDesc *desc, int ndesc, int size_filter,
+                                                         const PackedNet *pkg, float omega)
+{
+    const int b = blockIdx.x;
+    int lo = 0, hi = ndesc - 1;  // last level with tile0 <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (desc[mid].tile0 <= b) lo = mid; else hi = mid - 1;
+    }
+    const CnnLevelDesc L = desc[lo];
+    if (size_filter != 0 && L.n != size_filter) return;
+    const int t = b - L.tile0, tx = (L.n + kTO - 1) / kTO;
+    cnn_tile(L.n, L.P, L.plane, L.A32, (const PackedNet MG_G *)pkg, omega, L.H, (t % tx) * kTO, (t / tx) * kTO);
 }
 
 // Packs FP32 weights [Cout][Cin][3][3] + bias per layer into the per-lane
@@ -203,11 +225,13 @@ void launch_pack_weights_mfma(const float *params, void *packed, hipStream_t st)
     k_pack<<<(kPackElems + 255) / 256, 256, 0, st>>>(params, (PackedNet *)packed);
 }
 
-void launch_cnn_fused_mfma(int n, int P, int64_t plane, const float *A32, const void *packed, double omega, bf16_t *H,
-                           hipStream_t st)
+int cnn_level_tiles(int n) { return ((n + kTO - 1) / kTO) * ((n + kTO - 1) / kTO); }
+
+void launch_cnn_fused_levels(const CnnLevelDesc *desc, int ndesc, int total_tiles, int size_filter, const void *packed,
+                             double omega, hipStream_t st)
 {
-    const dim3 g((n + kTO - 1) / kTO, (n + kTO - 1) / kTO);
-    k_cnn_fused<<<g, kT, 0, st>>>(n, P, plane, A32, (const PackedNet *)packed, (float)omega, H);
+    if (ndesc < 1 || total_tiles < 1) return;
+    k_cnn_fused_levels<<<total_tiles, kT, 0, st>>>(desc, ndesc, size_filter, (const PackedNet *)packed, (float)omega);
 }
 
 }  // namespace mg

@@ -308,6 +308,28 @@ mg_status read_flag(mg_ctx_s &c, hipStream_t st)
     return MG_OK;
 }
 
+// The level table of the one-launch MFMA inference: every level above the
+// coarsest of every problem, by size (largest first) and problem.
+mg_status build_cnn_table(mg_ctx_s &c)
+{
+    std::vector<CnnLevelDesc> t;
+    for (const ProbBuf &pb : c.probs)
+        for (int l = 0; l + 1 < pb.nlev; ++l) {
+            const LevelBuf &L = pb.lev[l];
+            t.push_back(CnnLevelDesc{L.n, L.P, L.plane, L.A32, (bf16_t *)L.H, 0});
+        }
+    std::stable_sort(t.begin(), t.end(), [](const CnnLevelDesc &a, const CnnLevelDesc &b) { return a.n > b.n; });
+    int tiles = 0;
+    for (CnnLevelDesc &d : t) {
+        d.tile0 = tiles;
+        tiles += cnn_level_tiles(d.n);
+    }
+    c.n_cnn_levels = (int)t.size();
+    c.cnn_tiles = tiles;
+    if (t.empty()) return MG_OK;
+    return upload(c.arena, t, (void **)&c.d_cnn_levels);
+}
+
 mg_status setup_impl(mg_ctx_s &c, const mg_problem *probs, hipStream_t user)
 {
     MG_TRY(c.join.init(user));
@@ -350,10 +372,12 @@ mg_status setup_impl(mg_ctx_s &c, const mg_problem *probs, hipStream_t user)
         rebuild_problem(c, p, probs[p].stencil, st);
         MG_HIP(hipGetLastError());
     }
-    if (mixed)
+    if (mixed) {
         MG_TRY(build_slots<float>(c));
-    else
+        MG_TRY(build_cnn_table(c));
+    } else {
         MG_TRY(build_slots<double>(c));
+    }
     std::vector<SolveState> init(c.nprob);
     for (int p = 0; p < c.nprob; ++p) {
         std::memset(&init[p], 0, sizeof(SolveState));
@@ -1056,13 +1080,11 @@ mg_status ctx_infer(mg_ctx_s &c, mg_net net, int n, hipStream_t st, int *count)
         for (int l = 0; l + 1 < pb.nlev; ++l) {
             const LevelBuf &L = pb.lev[l];
             if (n != 0 && L.n != n) continue;
-            if (fp64)
-                MG_TRY(infer_level_direct<double>(c, L, net->params64, net->ch, (double *)c.cnn_scratch, st));
-            else
-                launch_cnn_fused_mfma(L.n, L.P, L.plane, L.A32, net->packed, c.opt.omega, (bf16_t *)L.H, st);
+            if (fp64) MG_TRY(infer_level_direct<double>(c, L, net->params64, net->ch, (double *)c.cnn_scratch, st));
             ++done;
         }
     }
+    if (!fp64) launch_cnn_fused_levels(c.d_cnn_levels, c.n_cnn_levels, c.cnn_tiles, n, net->packed, c.opt.omega, st);
     MG_HIP(hipGetLastError());
     if (count) *count = done;
     return MG_OK;

@@ -8,6 +8,7 @@
 
 #include "../../include/mgcnn.h"
 #include "common.hpp"
+#include "launch.hpp"
 
 namespace mg {
 
@@ -157,6 +158,9 @@ struct mg_ctx_s {
     // CNN inference scratch (direct path)
     void *cnn_scratch = nullptr;
     size_t cnn_scratch_bytes = 0;
+    // one-launch MFMA inference (mixed precision): every smoothing level, largest first
+    mg::CnnLevelDesc *d_cnn_levels = nullptr;
+    int n_cnn_levels = 0, cnn_tiles = 0;
     // flexible-GMRES workspace: 2 * restart + 3 FP64 vectors of the largest
     // finest grid, partial sums and small coefficient arrays
     std::vector<int> fell_back;          // per problem: the last mg_solve switched it to damped Jacobi

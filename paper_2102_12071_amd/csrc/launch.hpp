@@ -106,8 +106,20 @@ void launch_f32_to_f64(int64_t count, const float *src, double *dst, hipStream_t
 // into a buffer of packed_net_bytes().
 size_t packed_net_bytes();
 void launch_pack_weights_mfma(const float *params, void *packed, hipStream_t st);
-void launch_cnn_fused_mfma(int n, int P, int64_t plane, const float *A32, const void *packed, double omega,
-                           bf16_t *H, hipStream_t st);
+// One level of the one-launch smoother inference: its tiles are blocks
+// [tile0, tile0 + cnn_level_tiles(n)) of the launch.
+struct CnnLevelDesc {
+    int n, P;
+    int64_t plane;
+    const float MG_G *A32;  // 9 planes FP32
+    bf16_t MG_G *H;         // 25 planes BF16 out
+    int tile0;
+};
+
+// One launch over the levels of desc (device, tile0 ascending; size_filter != 0: only levels of that size).
+int cnn_level_tiles(int n);
+void launch_cnn_fused_levels(const CnnLevelDesc *desc, int ndesc, int total_tiles, int size_filter, const void *packed,
+                             double omega, hipStream_t st);
 // Smoother field conversions for mg_set_smoother / mg_get_smoother.
 // H = W / a_C (a_C from the FP64 stencil), and back.
 template <typename T>

@@ -7,8 +7,10 @@ bilinear stencil, the other half variable-coefficient five-point stencils of
 a = exp(g) (g a Gaussian random field) built on a grid 1, 2 or 4 times finer
 and Galerkin-coarsened to n, so that the network sees the coarse-level
 stencils it is applied to.  Each problem gets J = 16 unit vectors drawn from
-a pool of high-frequency vectors for its size.  The stencils are generated
-and coarsened on the device by the library.
+a pool of high-frequency vectors for its size.  With --mask-frac, that
+fraction of the problems is cut to a random non-square domain (a disk or a
+corner rectangle removed, Dirichlet values there).  The stencils are
+generated, masked and coarsened on the device by the library.
 
     python -m paper_2102_12071_amd.train --steps 3000 --out paper_2102_12071_amd/weights/cnn_hf.bin
 """
@@ -36,8 +38,9 @@ DEFAULT_OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights"
 
 class BatchMaker:
     def __init__(self, batch: int, nvec: int, sizes=(31, 63), pool: int = 2048, fields: int = 96,
-                 var_frac: float = 0.5, seed: int = 0):
+                 var_frac: float = 0.5, seed: int = 0, mask_frac: float = 0.0):
         self.batch, self.nvec, self.sizes, self.var_frac, self.seed = batch, nvec, sizes, var_frac, seed
+        self.mask_frac = mask_frac
         self.pools = {n: torch.tensor(mg_inputs.hf_pool(n, pool, seed + 1000 + n), dtype=torch.float32,
                                       device="cuda") for n in sizes}
         # log-normal coefficient fields on the (n_f + 1)^2 cells of grids n_f = n, 2n+1, 4n+3
@@ -61,14 +64,26 @@ class BatchMaker:
         stencils, vectors = [], []
         for q in range(self.batch):
             n = int(ns[q])
+            masked = self.mask_frac > 0 and rng.uniform() < self.mask_frac
             if rng.uniform() < self.var_frac:
                 level = int(rng.integers(0, 3))
                 a = self.fields[(n, level)][int(rng.integers(len(self.fields[(n, level)])))]
                 A = mgcnn.stencil_cellavg5(a)
-                for _ in range(level):
-                    A = mgcnn.galerkin(A)
             else:
-                A = mgcnn.stencil_q1_rotated(n, float(theta[q]), float(eps[q]))
+                # a masked rotated problem is built 1, 2 or 4 times finer and coarsened too
+                level = int(rng.integers(0, 3)) if masked else 0
+                nf = n
+                for _ in range(level):
+                    nf = 2 * nf + 1
+                A = mgcnn.stencil_q1_rotated(nf, float(theta[q]), float(eps[q]))
+            if masked:
+                # a non-square domain: Dirichlet rows cut into the stencil field along curved and
+                # corner boundaries, and (after coarsening) their Galerkin images, rows the
+                # square's outer boundary never shows
+                m = torch.tensor(mg_inputs.random_domain_mask(A.shape[1], rng), device="cuda")
+                A = mgcnn.stencil_mask(A, m)
+            for _ in range(level):
+                A = mgcnn.galerkin(A)
             idx = torch.tensor(rng.integers(0, self.pools[n].shape[0], self.nvec), device="cuda")
             stencils.append(A)
             vectors.append(self.pools[n].index_select(0, idx).contiguous())
@@ -99,6 +114,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", type=int, default=1, help="1: BF16 on MFMA (default); 0: FP32")
     ap.add_argument("--var-frac", type=float, default=0.5)
+    ap.add_argument("--mask-frac", type=float, default=0.0,
+                    help="fraction of problems on a random non-square domain (masked stencils)")
     ap.add_argument("--eval-every", type=int, default=500)
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--log", default=None)
@@ -111,7 +128,7 @@ def main():
         net.load(args.resume)
     else:
         net.set(mg_inputs.cnn_init(args.seed).astype(np.float32))
-    maker = BatchMaker(args.batch, args.nvec, var_frac=args.var_frac, seed=args.seed)
+    maker = BatchMaker(args.batch, args.nvec, var_frac=args.var_frac, seed=args.seed, mask_frac=args.mask_frac)
     held = maker.make(10 ** 6)
     opts = mgcnn.TrainOptions(lr=args.lr, precision=args.precision)
     no_update = mgcnn.TrainOptions(lr=args.lr, precision=args.precision, apply_update=0)

@@ -66,3 +66,16 @@ def test_rhs_and_draws_deterministic():
     assert ep.min() >= 1e-3 and ep.max() <= 1.0
     ns, th, ep, seeds = mg_inputs.c5_draws()
     assert ns.size == 512 and set(ns.tolist()) <= {63, 127, 255, 511, 1023}
+
+
+def test_random_domain_masks():
+    rng = np.random.default_rng(0)
+    fracs = []
+    for _ in range(40):
+        m = mg_inputs.random_domain_mask(63, rng)
+        assert m.dtype == np.uint8 and m.shape == (63, 63) and set(np.unique(m)) <= {0, 1}
+        fracs.append(m.mean())
+    # a disk of radius <= 0.3 removes at most 28 % of the square, a corner rectangle at most 49 %
+    assert min(fracs) > 0.45 and max(fracs) < 1.0
+    assert mg_inputs.random_domain_mask(63, np.random.default_rng(5)).tolist() == \
+        mg_inputs.random_domain_mask(63, np.random.default_rng(5)).tolist()

@@ -213,25 +213,34 @@ def test_network_smoother_on_masked_domain(ora):
         far[max(j - 5, 0):j + 6, max(i - 5, 0):i + 6] = False
     assert far.sum() > 100
     assert np.array_equal(Wm[:, far], W[:, far])
-    # the hole's Galerkin images on the coarser levels have no negative entry either
+    # the hole's Galerkin images on the coarser levels: off-centre sums not negative either
     h = ora.Hierarchy(Am, 3)
     S = h.stencil(1)
     Wc = ora.cnn_forward(S, params)
-    hole = np.concatenate([S[:4], S[5:]]).min(0) >= 0
+    hole = (S.sum(0) - S[4]) >= 0
     assert hole.sum() > 4 and np.array_equal(Wc[:, hole].T, np.tile(jac, (int(hole.sum()), 1)))
     assert not np.array_equal(Wc[:, ~hole], np.zeros_like(Wc[:, ~hole]))
 
 
-def test_diffusion_rows_always_take_the_network(ora):
-    # every row of a diffusion stencil has a negative off-centre entry (at least 1 % of a_C on
-    # these draws), on every Galerkin level: the Jacobi rule never replaces the network there
+def test_diffusion_rows_take_the_network(ora):
+    # Galerkin coarsening keeps the row sums of interior rows at zero, so their off-centre entries
+    # sum to -a_C; the rule can only act on rows next to the Dirichlet boundary.  Rotated Q1
+    # stencils never trigger it on any level (off-centre sum at most -18 % of a_C on these draws);
+    # strongly varying cell-average coefficients can on a boundary row of a very coarse level
     rng = np.random.default_rng(3)
-    stencils = [ora.stencil_q1_rotated(n, rng.uniform(0, math.pi), 10 ** rng.uniform(-4, 0))
-                for n in (31, 63) for _ in range(20)]
-    stencils += [ora.stencil_cellavg5(n, mg_inputs.lognormal_coefficient(n, L, 1.0, s))
-                 for n in (31, 63) for s in range(3) for L in (0.05, 0.1, 0.3)]
-    for A in stencils:
-        h = ora.Hierarchy(A, 1)
-        for l in range(h.num_levels - 1):
-            S = h.stencil(l)
-            assert (np.concatenate([S[:4], S[5:]]).min(0) / S[4]).max() < -0.01
+    for n in (31, 63):
+        for _ in range(20):
+            h = ora.Hierarchy(ora.stencil_q1_rotated(n, rng.uniform(0, math.pi), 10 ** rng.uniform(-4, 0)), 1)
+            for l in range(h.num_levels - 1):
+                S = h.stencil(l)
+                assert ((S.sum(0) - S[4]) / S[4]).max() < -0.15
+    for n in (31, 63):
+        for s in range(3):
+            for L in (0.05, 0.1, 0.3):
+                h = ora.Hierarchy(ora.stencil_cellavg5(n, mg_inputs.lognormal_coefficient(n, L, 1.0, s)), 1)
+                for l in range(h.num_levels - 1):
+                    S = h.stencil(l)
+                    m = S.shape[1]
+                    off = (S.sum(0) - S[4]) / S[4]
+                    inner = off[1:m - 1, 1:m - 1]
+                    assert np.allclose(inner, -1.0, atol=1e-9)  # interior rows sum to zero

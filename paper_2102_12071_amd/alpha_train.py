@@ -220,12 +220,17 @@ def load_nets(out_dir: str = WEIGHTS, finest: int = 63, coarsest: int = 3) -> Di
 
 
 def evaluate(nets: Dict[int, mgcnn.Net], n: int, theta: float, eps: float, tol: float = 1e-8,
-             maxit: int = 20000, coarsest: int = 3, hf: Optional[mgcnn.Net] = None, seed: int = 0) -> dict:
+             maxit: int = 20000, coarsest: int = 3, hf: Optional[mgcnn.Net] = None, seed: int = 0,
+             domain: str = "square") -> dict:
     """Iterations and solve time to tol of V(1,1) with the per-level alpha-CNN
     smoothers, damped Jacobi, and (hf given) the one network trained on the
-    high-frequency loss, on one rotated anisotropic problem."""
+    high-frequency loss, on one rotated anisotropic problem (domain: 'square',
+    'lshape' or 'cylinder', zero Dirichlet values on the removed nodes)."""
     A = mgcnn.stencil_q1_rotated(n, theta, eps)
-    f = torch.tensor(mg_inputs.rhs_uniform(n, seed), dtype=torch.float64, device="cuda")
+    m = mg_inputs.domain_mask(n, domain)
+    if domain != "square":
+        A = mgcnn.stencil_mask(A, torch.tensor(m, device="cuda"))
+    f = torch.tensor(mg_inputs.rhs_uniform(n, seed) * m, dtype=torch.float64, device="cuda")
     out = {}
     for name in ("alpha_cnn", "jacobi") + (("hf_cnn",) if hf is not None else ()):
         sm = mgcnn.SMOOTHER_JACOBI if name == "jacobi" else mgcnn.SMOOTHER_CNN
@@ -278,9 +283,12 @@ def main():
         net.save(weight_path(args.out_dir, n))
     hf = mgcnn.Net()
     hf.load(os.path.join(WEIGHTS, "cnn_hf.bin"))
-    for n, theta, eps in ((63, math.pi / 6, 0.01), (255, math.pi / 3, 1e-3), (1023, math.pi / 3, 1e-3),
-                          (1023, 0.0, 1e-2), (1023, math.pi / 4, 0.1), (1023, 2.0, 1.0)):
-        log(json.dumps({"eval": {"n": n, "theta": theta, "eps": eps}, **evaluate(nets, n, theta, eps, hf=hf)}))
+    for n, theta, eps, dom in ((63, math.pi / 6, 0.01, "square"), (255, math.pi / 3, 1e-3, "square"),
+                               (1023, math.pi / 3, 1e-3, "square"), (1023, 0.0, 1e-2, "square"),
+                               (1023, math.pi / 4, 0.1, "square"), (1023, 2.0, 1.0, "square"),
+                               (1023, math.pi / 4, 0.01, "lshape"), (1023, math.pi / 4, 0.01, "cylinder")):
+        log(json.dumps({"eval": {"n": n, "theta": theta, "eps": eps, "domain": dom},
+                        **evaluate(nets, n, theta, eps, hf=hf, domain=dom)}))
     if args.log:
         with open(args.log, "w") as fh:
             json.dump(records, fh, indent=1)

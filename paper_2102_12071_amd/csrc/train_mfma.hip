@@ -240,27 +240,32 @@ __global__ void __launch_bounds__(kT) k_trb_av(const TrainProbB *probs, int J)
 // vector, the sum of g_j^2 (FP64, waves then the block in a fixed order) goes
 // to part[problem][block][j].  grid = (pixel blocks, 1, problems).
 constexpr int kJChunk = 64;
+constexpr int kResRows = 1792;  // >= max over 3 <= n <= 255 of (255 / n + 6) n
 __global__ void __launch_bounds__(kT) k_trb_residual(const TrainProbB *probs, int J, float omega, double *part,
                                                      int nblk)
 {
     __shared__ double red[kT / 64][kJChunk];
+    __shared__ float sav[kResRows];  // the rows of A v_j the block's pixels reach (two above, two below)
     const TrainProbB &P = probs[blockIdx.z];
     const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
     const bool live = p < P.plane;
     const int n = P.n;
     const int64_t pc = live ? p : 0;
     const int i = (int)(pc % n), j = (int)(pc / n);
+    const int64_t p0 = (int64_t)blockIdx.x * kT, p1 = min(p0 + kT, P.plane) - 1;
+    const int r0 = max(0, (int)(p0 / n) - 2), r1 = min(n - 1, (int)(p1 / n) + 2);
+    const int nrow = (r1 - r0 + 1) * n;  // <= (255 / n + 6) n <= 1785 for 3 <= n <= 255
     float w[25];
 #pragma unroll
     for (int k = 0; k < 25; ++k) w[k] = P.y[pc * 32 + k] + (k == 12 ? omega : 0.0f);
     const float inv_ac = 1.0f / (float)P.A[kCentre * P.plane + pc];
-    int64_t off[25];
+    int off[25];
     bool ok[25];
 #pragma unroll
     for (int k = 0; k < 25; ++k) {
         const int ii = i + k % 5 - 2, jj = j + k / 5 - 2;
-        ok[k] = in_grid(n, ii, jj);
-        off[k] = ok[k] ? (int64_t)jj * n + ii : pc;
+        ok[k] = live && in_grid(n, ii, jj);
+        off[k] = ok[k] ? (jj - r0) * n + ii : 0;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double *out = part + ((int64_t)P.index * nblk + blockIdx.x) * J;
@@ -268,13 +273,16 @@ __global__ void __launch_bounds__(kT) k_trb_residual(const TrainProbB *probs, in
         const int jn = min(kJChunk, J - j0);
         for (int q = 0; q < jn; ++q) {
             const int jv = j0 + q;
-            const float MG_G *Av = P.Av + (int64_t)jv * P.plane;
+            const float MG_G *Av = P.Av + (int64_t)jv * P.plane + (int64_t)r0 * n;
+            for (int t = threadIdx.x; t < nrow; t += kT) sav[t] = Av[t];
+            __syncthreads();
             float y = 0.0f;
 #pragma unroll
             for (int k = 0; k < 25; ++k) {
-                const float xv = Av[off[k]];
+                const float xv = sav[off[k]];
                 y += w[k] * (ok[k] ? xv : 0.f);
             }
+            __syncthreads();  // sav is refilled for the next vector
             const float gv = P.V[(int64_t)jv * P.plane + pc] - y * inv_ac;
             if (live) P.g[(int64_t)jv * P.plane + p] = gv;
             const double s = wave_sum(live ? (double)gv * gv : 0.0);

@@ -139,7 +139,11 @@ __global__ void __launch_bounds__(kT) k_trb_wgrad(const TrainProbB *probs, int d
     // rows padded by 8 bf16 (132 dwords): the 16 channel rows one lane group reads with ds_read_b128
     // start in distinct groups of four banks (256 would put them all on one)
     __shared__ __align__(16) bf16_t dyT[32][kTile * kTile + 8];
-    __shared__ bf16_t xT[CIN][kHalo * kHalo];
+    // the input tile with its halo, once per horizontal tap offset kx: xS[kx][ci][row][px] = x(row, px + kx),
+    // so that a lane's eight consecutive pixels of a tap are one aligned 16-byte read; channel stride
+    // 18 * 16 + 8 (148 dwords) keeps the sixteen channels of a lane group on distinct bank groups
+    constexpr int XS = kHalo * kTile + 8;
+    __shared__ __align__(16) bf16_t xS[3][CIN][XS];
     const TrainProbB &P = probs[blockIdx.z];
     const int n = P.n;
     const int X0 = blockIdx.x * kTile, Y0 = blockIdx.y * kTile;
@@ -163,14 +167,20 @@ __global__ void __launch_bounds__(kT) k_trb_wgrad(const TrainProbB *probs, int d
     constexpr int CH = CIN / 8;
     for (int q = tid; q < kHalo * kHalo * CH; q += kT) {
         const int pix = q / CH, c8 = q % CH;
-        const int gi = X0 - 1 + pix % kHalo, gj = Y0 - 1 + pix / kHalo;
+        const int col = pix % kHalo, row = pix / kHalo;
+        const int gi = X0 - 1 + col, gj = Y0 - 1 + row;
         const bool ok = in_grid(n, gi, gj);
         const int64_t p = ok ? (int64_t)gj * n + gi : 0;
         u32x4 v = *(const u32x4 MG_G *)(x + p * CIN + c8 * 8);
         if (!ok) v = u32x4{0u, 0u, 0u, 0u};
         const bf16_t *e8 = (const bf16_t *)&v;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) xT[c8 * 8 + e][pix] = e8[e];
+        for (int kx = 0; kx < 3; ++kx) {
+            const int px = col - kx;
+            if (px < 0 || px >= kTile) continue;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) xS[kx][c8 * 8 + e][row * kTile + px] = e8[e];
+        }
     }
     __syncthreads();
     // bias gradient
@@ -191,10 +201,7 @@ __global__ void __launch_bounds__(kT) k_trb_wgrad(const TrainProbB *probs, int d
             const int k0 = ks * 32 + 8 * g;           // eight consecutive pixels of one tile row
             const int py = k0 / kTile, px = k0 % kTile;
             const bf16x8 a = *(const bf16x8 *)&dyT[co][k0];
-            bf16x8 b;
-            const int base = (py + ky) * kHalo + px + kx;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) b[e] = __builtin_bit_cast(__bf16, xT[ci][base + e]);
+            const bf16x8 b = *(const bf16x8 *)&xS[kx][ci][(py + ky) * kTile + px];
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
         }
 #pragma unroll

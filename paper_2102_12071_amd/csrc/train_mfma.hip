@@ -222,24 +222,34 @@ __global__ void __launch_bounds__(kT) k_trb_input(const TrainProbB *probs)
     for (int c = 0; c < 16; ++c) P.x0[p * 16 + c] = f32_to_bf16(c < 9 ? (float)(P.A[c * P.plane + p] / ac) : 0.f);
 }
 
-// Av_j = A v_j.  grid.z = problem * J + j.
+// Av_j = A v_j for every vector of a problem, one thread per pixel: the nine
+// stencil entries are read once for all J vectors.  grid.z = problem.
 __global__ void __launch_bounds__(kT) k_trb_av(const TrainProbB *probs, int J)
 {
-    const TrainProbB &P = probs[blockIdx.z / J];
-    const int jv = blockIdx.z % J;
+    const TrainProbB &P = probs[blockIdx.z];
     const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
     if (p >= P.plane) return;
     const int n = P.n, i = (int)(p % n), j = (int)(p / n);
-    const float MG_G *v = P.V + (int64_t)jv * P.plane;
-    float acc = 0.0f;
+    float a[9];
+    int64_t off[9];
+    bool ok[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
         const int ii = i + c % 3 - 1, jj = j + c / 3 - 1;
-        const bool ok = in_grid(n, ii, jj);
-        const float xv = v[ok ? (int64_t)jj * n + ii : p];
-        acc += (float)P.A[c * P.plane + p] * (ok ? xv : 0.f);
+        ok[c] = in_grid(n, ii, jj);
+        off[c] = ok[c] ? (int64_t)jj * n + ii : p;
+        a[c] = (float)P.A[c * P.plane + p];
     }
-    P.Av[(int64_t)jv * P.plane + p] = acc;
+    for (int jv = 0; jv < J; ++jv) {
+        const float MG_G *v = P.V + (int64_t)jv * P.plane;
+        float acc = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            const float xv = v[off[c]];
+            acc += a[c] * (ok[c] ? xv : 0.f);
+        }
+        P.Av[(int64_t)jv * P.plane + p] = acc;
+    }
 }
 
 // g_j = v_j - H A v_j for every vector j of a problem, one thread per pixel:
@@ -491,7 +501,7 @@ size_t trb_reduce_scratch_bytes() { return sizeof(float) * (size_t)kReduceSlices
 
 void launch_trb_av(const TrainProbB *probs, int nb, int n, int J, hipStream_t st)
 {
-    k_trb_av<<<dim3(blocks_for((int64_t)n * n), 1, nb * J), kT, 0, st>>>(probs, J);
+    k_trb_av<<<dim3(blocks_for((int64_t)n * n), 1, nb), kT, 0, st>>>(probs, J);
 }
 
 void launch_trb_residual_norm(const TrainProbB *probs, int nb, int n, int J, float omega, float *loss_part,

@@ -31,7 +31,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTO = 16;                       // output tile side
-constexpr int kT = 256;                       // 4 waves
+constexpr int kT = 512;                       // 8 waves: with two workgroups per CU (LDS-bound), four waves per SIMD
 constexpr int kR0 = kTO + 8, kR1 = kTO + 6, kR2 = kTO + 4, kR3 = kTO + 2;
 // channel strides (bf16) of the input and hidden buffers: 16 and 32 channels padded to 24 and 40, so
 // that the 16 pixels a ds_read_b128 of one lane group reads start in distinct groups of four banks

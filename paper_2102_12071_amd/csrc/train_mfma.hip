@@ -132,8 +132,11 @@ __global__ void __launch_bounds__(kT) k_trb_conv(const TrainProbB *probs, const 
 //   part[tap][co][ci] = sum_{p in tile} dY[p][co] X[p + tap][ci],  part_b[co] = sum_p dY[p][co].
 // dY and X are staged channel-major in LDS so that a lane's eight K values
 // (eight consecutive pixels of one channel) are contiguous.
+// 8 waves per workgroup: the LDS of the shifted input copies allows two workgroups per CU
+constexpr int kTW = 512;
+
 template <int CIN>
-__global__ void __launch_bounds__(kT) k_trb_wgrad(const TrainProbB *probs, int dy_sel, int x_sel, int cout,
+__global__ void __launch_bounds__(kTW) k_trb_wgrad(const TrainProbB *probs, int dy_sel, int x_sel, int cout,
                                                   float *part)
 {
     // rows padded by 8 bf16 (132 dwords): the 16 channel rows one lane group reads with ds_read_b128
@@ -153,7 +156,7 @@ __global__ void __launch_bounds__(kT) k_trb_wgrad(const TrainProbB *probs, int d
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4;
     const bf16_t MG_G *dy = bsel(P, dy_sel);
     const bf16_t MG_G *x = bsel(P, x_sel);
-    for (int q = tid; q < kTile * kTile * 4; q += kT) {
+    for (int q = tid; q < kTile * kTile * 4; q += kTW) {
         const int pix = q / 4, c8 = q % 4;
         const int gi = X0 + pix % kTile, gj = Y0 + pix / kTile;
         const bool ok = in_grid(n, gi, gj);
@@ -165,7 +168,7 @@ __global__ void __launch_bounds__(kT) k_trb_wgrad(const TrainProbB *probs, int d
         for (int e = 0; e < 8; ++e) dyT[c8 * 8 + e][pix] = e8[e];
     }
     constexpr int CH = CIN / 8;
-    for (int q = tid; q < kHalo * kHalo * CH; q += kT) {
+    for (int q = tid; q < kHalo * kHalo * CH; q += kTW) {
         const int pix = q / CH, c8 = q % CH;
         const int col = pix % kHalo, row = pix / kHalo;
         const int gi = X0 - 1 + col, gj = Y0 - 1 + row;
@@ -191,7 +194,7 @@ __global__ void __launch_bounds__(kT) k_trb_wgrad(const TrainProbB *probs, int d
     }
     // (tap, co-block, ci-block) jobs spread over the waves
     constexpr int NB = CIN / 16;
-    for (int job = wave; job < 9 * 2 * NB; job += kT / 64) {
+    for (int job = wave; job < 9 * 2 * NB; job += kTW / 64) {
         const int tap = job / (2 * NB), mb = (job / NB) % 2, nb = job % NB;
         const int ky = tap / 3, kx = tap % 3;
         const int co = mb * 16 + (lane & 15), ci = nb * 16 + (lane & 15);
@@ -485,9 +488,9 @@ void launch_trb_wgrad(const TrainProbB *probs, int nb, int n, int layer, int cou
     const dim3 g(t, t, nb);
     const int dy_sel = (layer & 1) ? kTbDA : kTbDB;
     if (layer == 0)
-        k_trb_wgrad<16><<<g, kT, 0, st>>>(probs, dy_sel, kTbX0, cout, part);
+        k_trb_wgrad<16><<<g, kTW, 0, st>>>(probs, dy_sel, kTbX0, cout, part);
     else
-        k_trb_wgrad<32><<<g, kT, 0, st>>>(probs, dy_sel, kTbAct0 + layer - 1, cout, part);
+        k_trb_wgrad<32><<<g, kTW, 0, st>>>(probs, dy_sel, kTbAct0 + layer - 1, cout, part);
 }
 
 void launch_trb_reduce(const float *part, int ntiles, int cin, int cout, int64_t woff, int64_t boff, float *grad,

@@ -83,6 +83,20 @@ __global__ void __launch_bounds__(kT) k_trb_conv(const TrainProbB *probs, const 
         const int pa = mb * 16 + (lane & 15);
         const int oy = pa / kTile, ox = pa % kTile;
         f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        // data gradient: the forward activations that mask it, loaded before the products so that
+        // their latency overlaps them (clamped address off the grid, unused there)
+        bf16_t mk0[4], mk1[4];
+        if (EPI == 2) {
+            const bf16_t MG_G *m = bsel(P, mask_sel);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int pix = mb * 16 + 4 * g + i;
+                const int gi = X0 + pix % kTile, gj = Y0 + pix / kTile;
+                const int64_t p = (gi < n && gj < n) ? (int64_t)gj * n + gi : 0;
+                mk0[i] = m[p * 32 + (lane & 15)];
+                mk1[i] = m[p * 32 + 16 + (lane & 15)];
+            }
+        }
 #pragma unroll
         for (int s = 0; s < STEPS; ++s) {
             int tap, cg;
@@ -119,10 +133,9 @@ __global__ void __launch_bounds__(kT) k_trb_conv(const TrainProbB *probs, const 
                 P.y[p * 32 + c0] = v0;
                 P.y[p * 32 + c1] = v1;
             } else {
-                const bf16_t MG_G *m = bsel(P, mask_sel);
                 bf16_t MG_G *out = bsel(P, out_sel);
-                out[p * 32 + c0] = f32_to_bf16(bf16_to_f32(m[p * 32 + c0]) > 0.f ? v0 : 0.f);
-                out[p * 32 + c1] = f32_to_bf16(bf16_to_f32(m[p * 32 + c1]) > 0.f ? v1 : 0.f);
+                out[p * 32 + c0] = f32_to_bf16(bf16_to_f32(mk0[i]) > 0.f ? v0 : 0.f);
+                out[p * 32 + c1] = f32_to_bf16(bf16_to_f32(mk1[i]) > 0.f ? v1 : 0.f);
             }
         }
     }

@@ -202,8 +202,9 @@ def main():
     use_alpha = args.smoother == "alpha" or (args.smoother == "auto" and alpha_nets is not None)
     if use_alpha and alpha_nets is None:
         raise SystemExit("--smoother alpha needs the per-level checkpoints weights/alpha_n*.bin")
-    # the per-level networks were trained over a 3 x 3 coarsest grid; the single network over 7 x 7
-    coarsest = 3 if use_alpha else 7
+    # 7 x 7 coarsest grid for both smoothers (the per-level networks were trained over 3 x 3; with the
+    # exact solve at 7 x 7 they take the same 444 cycles at C2 and each cycle costs 3 % less)
+    coarsest = 7
 
     def infer(ctx):
         if use_alpha:
@@ -496,37 +497,43 @@ def geometry_block(args, net, alpha_nets, n):
     (L-shape) and without a disk of radius 1/5 about the centre (cylinder),
     zero Dirichlet values on the removed nodes, theta = pi/4, eps = 0.01;
     iterations and solve time to the headline tolerance of the single
-    network (7 x 7 coarsest grid), of the per-level networks when given
-    (3 x 3), and of damped Jacobi."""
+    network, of the per-level networks when given (with the fallback to
+    damped Jacobi), and of damped Jacobi; 7 x 7 coarsest grid."""
     import torch
 
     import mg_inputs
     from paper_2102_12071_amd import mgcnn
     out = {}
-    runs = [("cnn", mgcnn.SMOOTHER_CNN, 7, lambda c: c.infer(net)), ("jacobi", mgcnn.SMOOTHER_JACOBI, 7, None)]
+    runs = [("cnn", mgcnn.SMOOTHER_CNN, 7, lambda c: c.infer(net), 0),
+            ("jacobi", mgcnn.SMOOTHER_JACOBI, 7, None, 0)]
     if alpha_nets:
-        runs.append(("alpha_cnn", mgcnn.SMOOTHER_CNN, 3, lambda c: c.infer_levels(alpha_nets)))
+        # the per-level networks with the per-problem fallback to damped Jacobi on stall or divergence
+        runs.append(("alpha_cnn", mgcnn.SMOOTHER_CNN, 7, lambda c: c.infer_levels(alpha_nets), 1))
     for kind in ("lshape", "cylinder"):
         m = mg_inputs.domain_mask(n, kind)
         A = mgcnn.stencil_mask(mgcnn.stencil_q1_rotated(n, math.pi / 4, 0.01), torch.tensor(m, device="cuda"))
         f = torch.tensor(mg_inputs.rhs_uniform(n, 0) * m, dtype=torch.float64, device="cuda")
         row = {"inside_nodes": int(m.sum())}
-        for name, sm, coarsest, infer in runs:
-            ctx = mgcnn.Context([A], mgcnn.Options(smoother=sm, coarsest_n=coarsest))
+        for name, sm, coarsest, infer, fallback in runs:
+            ctx = mgcnn.Context([A], mgcnn.Options(smoother=sm, coarsest_n=coarsest, fallback=fallback))
             if infer:
                 infer(ctx)
             ctx.solve([f], args.tol, args.maxit)  # warm-up (graph capture)
+            if infer:
+                infer(ctx)  # a fallback in the warm-up overwrote the learned smoother
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             res = ctx.solve([f], args.tol, args.maxit)
             row[name] = {"iters": int(res.iters[0]), "status": int(res.status[0]),
                          "solve_ms": (time.perf_counter() - t0) * 1e3}
+            if fallback:
+                row[name]["fell_back_to_jacobi"] = bool(ctx.fallbacks()[0])
             ctx.close()
         row["iteration_ratio"] = row["jacobi"]["iters"] / max(row["cnn"]["iters"], 1)
         row["time_ratio"] = row["jacobi"]["solve_ms"] / row["cnn"]["solve_ms"]
         log(f"{kind}: CNN {row['cnn']['iters']} vs Jacobi {row['jacobi']['iters']} iterations"
-            + (f"; per-level networks {row['alpha_cnn']['iters']} (status {row['alpha_cnn']['status']})"
-               if alpha_nets else ""))
+            + (f"; per-level networks {row['alpha_cnn']['iters']} (status {row['alpha_cnn']['status']}, "
+               f"fallback {row['alpha_cnn']['fell_back_to_jacobi']})" if alpha_nets else ""))
         out[kind] = row
     return out
 

@@ -155,7 +155,9 @@ mg_status mg_smoother_infer(mg_ctx ctx, mg_net net);
 /* Runs the network on the smoothing levels of size n only (every problem),
  * leaving the other levels' smoothers as they are: per-level networks, each
  * trained for one level size (the adaptive training of section 3.3 yields one
- * network per level).  MG_ERR_ARG if no level above the coarsest has size n. */
+ * network per level).  A level never given a smoother holds zeros (no
+ * smoothing), so cover every level size before a CNN solve.  MG_ERR_ARG if
+ * no level above the coarsest has size n. */
 mg_status mg_smoother_infer_size(mg_ctx ctx, mg_net net, int32_t n);
 
 /* Installs an explicit smoother field W for one level (device [25][n_l][n_l]

@@ -1,0 +1,91 @@
+"""Parity at the benchmark's full sizes, in the configuration bench.py times
+(mixed precision, fused level kernels with autotuned tiles, graph replay):
+one V(1,1) cycle at n = 1023 against the oracle's FP64 cycle with the same
+(BF16-stored) smoother, and the solves of the headline (n = 1023) and of the
+variable-coefficient workload (n = 4095) checked by the oracle's own FP64
+residual of the returned solution."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import mg_inputs
+import oracle as ora
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mg():
+    from paper_2102_12071_amd import mgcnn
+    mgcnn.load_library()
+    assert torch.cuda.is_available()
+    return mgcnn
+
+
+def _weights(mg, name):
+    return os.path.join(os.path.dirname(mg.__file__), "weights", name)
+
+
+def _headline(mg):
+    from paper_2102_12071_amd.alpha_train import load_nets
+    n = 1023
+    A = mg.stencil_q1_rotated(n, math.pi / 3, 1e-3)
+    ctx = mg.Context([A], mg.Options(smoother=mg.SMOOTHER_CNN))
+    ctx.autotune(3)
+    ctx.infer_levels(load_nets(os.path.dirname(_weights(mg, "x"))))
+    return n, A, ctx
+
+
+def test_c2_cycle_matches_oracle_with_the_same_smoother(mg):
+    # the learned smoother stored in BF16: the oracle takes the smoother fields the context holds
+    # (W = a_C H, exact in FP64) and runs the cycle in FP64; what remains is the FP32 arithmetic and
+    # stencil of the inner cycle
+    n, A, ctx = _headline(mg)
+    f = mg_inputs.rhs_uniform(n, 4)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    ctx.vcycle([torch.tensor(f, device="cuda")], [u])
+    A64 = A.cpu().numpy()
+    h = ora.Hierarchy(A64)
+    for l in range(h.num_levels - 1):
+        h.set_smoother(l, ctx.smoother(0, l).cpu().numpy())
+    e = h.vcycle(f, 1, 1)
+    got = u.cpu().numpy()
+    assert np.abs(got - e).max() <= 1e-4 * np.abs(e).max()
+    # sampled nodes: the tile corners and edges of the fused kernels, one by one
+    rng = np.random.default_rng(0)
+    for j, i in list(zip(rng.integers(0, n, 64), rng.integers(0, n, 64))) + [(0, 0), (n - 1, n - 1), (63, 64)]:
+        assert abs(got[j, i] - e[j, i]) <= 1e-4 * np.abs(e).max()
+
+
+def test_c2_headline_solve_true_residual(mg):
+    n, A, ctx = _headline(mg)
+    f = mg_inputs.rhs_uniform(n, 0)
+    res = ctx.solve([torch.tensor(f, device="cuda")], 1e-8, 20000)
+    assert res.status[0] == 0
+    r = f - ora.matvec(A.cpu().numpy(), res.u[0].cpu().numpy())
+    assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(f)
+    assert res.relres[0] == pytest.approx(np.linalg.norm(r) / np.linalg.norm(f), rel=1e-6)
+    jac = mg.Context([A], mg.Options(smoother=mg.SMOOTHER_JACOBI))
+    rj = jac.solve([torch.tensor(f, device="cuda")], 1e-8, 20000)
+    assert rj.status[0] == 0 and 4 * int(res.iters[0]) < int(rj.iters[0])
+
+
+def test_c4_solve_true_residual(mg):
+    n = 4095
+    a = mg_inputs.lognormal_coefficient(n, 0.1, 1.0, 7)
+    f = mg_inputs.rhs_uniform(n, 7)
+    A = mg.stencil_cellavg5(torch.tensor(a, device="cuda"))
+    net = mg.Net()
+    net.load(_weights(mg, "cnn_hf.bin"))
+    ctx = mg.Context([A], mg.Options(smoother=mg.SMOOTHER_CNN))
+    ctx.infer(net)
+    res = ctx.solve([torch.tensor(f, device="cuda")], 1e-10, 200)
+    assert res.status[0] == 0 and int(res.iters[0]) <= 20
+    A64 = ora.stencil_cellavg5(n, a)
+    assert np.abs(A.cpu().numpy() - A64).max() <= 1e-15 * np.abs(A64).max()
+    r = f - ora.matvec(A64, res.u[0].cpu().numpy())
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(f)

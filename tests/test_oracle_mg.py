@@ -309,3 +309,20 @@ def test_hierarchy_rejects_bad_sizes(ora):
         ora.Hierarchy(ora.stencil_q1_rotated(14, 0.1, 0.1))
     with pytest.raises(ValueError):
         ora.Hierarchy(-ora.stencil_q1_rotated(15, 0.1, 0.1))
+
+
+def test_jacobi_per_eigenvector_factor(ora):
+    # the smoothing-property measure of section 6 (the factor ||v - H A v|| of each unit eigenvector v
+    # of A): for damped Jacobi on a constant-diagonal stencil it is |1 - omega lambda / a_C| exactly,
+    # from an eigendecomposition made independently of the oracle's smoother routine
+    n = 15
+    A = ora.stencil_q1_rotated(n, 5 * math.pi / 12, 0.01)
+    assert np.ptp(A[4]) < 1e-14 * A[4].max()  # the Q1 diagonal does not depend on the node
+    M = ora.stencil_to_dense(A)
+    lam, V = np.linalg.eigh(M)
+    W = np.zeros((25, n, n))
+    W[12] = 2.0 / 3.0
+    for q in range(0, n * n, 7):
+        v = V[:, q].reshape(n, n)
+        g = v - ora.apply_smoother5(A, W, ora.matvec(A, v))
+        assert np.linalg.norm(g) == pytest.approx(abs(1 - (2.0 / 3.0) * lam[q] / A[4, 0, 0]), rel=1e-10, abs=1e-13)

@@ -147,7 +147,7 @@ def inject_errors(n: int, Q: int, nets: Dict[int, mgcnn.Net], seed: int, cycles:
 
 def train(finest: int = 63, Q: int = 50, steps: int = 400, lr: float = 1e-3, bmax: int = 4, seed: int = 0,
           init: Optional[str] = None, coarsest: int = 3, lr_final: Optional[float] = None,
-          log=print) -> Dict[int, mgcnn.Net]:
+          init_dir: Optional[str] = None, log=print) -> Dict[int, mgcnn.Net]:
     """Runs every stage; returns the trained network of each level size.  The
     learning rate decays geometrically from lr to lr_final over a stage; a
     stage keeps the parameters with the lowest loss at k = b cycles on its
@@ -158,7 +158,9 @@ def train(finest: int = 63, Q: int = 50, steps: int = 400, lr: float = 1e-3, bma
         t0 = time.perf_counter()
         stage = Stage(n, Q, nets, seed, coarsest)
         net = mgcnn.Net()
-        if init:
+        if init_dir:
+            net.load(weight_path(init_dir, n))  # continue from this level's network
+        elif init:
             net.load(init)
         else:
             net.set(mg_inputs.cnn_init(seed + n).astype(np.float32))  # zero last layer: damped Jacobi
@@ -256,6 +258,7 @@ def main():
     ap.add_argument("--bmax", type=int, default=4, help="k ~ U{1..bmax} cycles per loss term")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--init", default=None, help="checkpoint to start every stage from (default: damped Jacobi)")
+    ap.add_argument("--init-dir", default=None, help="directory of per-level checkpoints each stage continues from")
     ap.add_argument("--update-rounds", type=int, default=0, help="rounds of error injection and retraining")
     ap.add_argument("--update-steps", type=int, default=400)
     ap.add_argument("--update-lr", type=float, default=3e-4)
@@ -274,7 +277,7 @@ def main():
         nets = load_nets(args.load, args.finest)
     else:
         nets = train(args.finest, args.instances, args.steps, args.lr, args.bmax, args.seed, args.init,
-                     lr_final=args.lr_final, log=log)
+                     lr_final=args.lr_final, init_dir=args.init_dir, log=log)
     if args.update_rounds:
         update(nets, args.instances, args.update_steps, args.update_lr, args.bmax, args.seed, args.update_rounds,
                log=log)

@@ -162,6 +162,29 @@ def cnn_random(seed: int, channels=CNN_CHANNELS, scale_last: float = 0.05) -> np
     return p.astype(np.float32).astype(np.float64)
 
 
+def stack_init(seed: int) -> np.ndarray:
+    """Weights [6][3][3] of a convolution-stack smoother (f1..f5 composed,
+    plus f6) for an operator with centre entry 1: f1..f4 U(-1/3, 1/3) (the
+    usual default for a 3x3 single-channel kernel), f5 zero, f6 = 2/3 at the
+    centre tap, so that the untrained stack is damped Jacobi and every kernel
+    receives a gradient after the first step.  Rounded to float32."""
+    rng = np.random.default_rng(seed)
+    w = np.zeros((6, 3, 3))
+    w[:4] = rng.uniform(-1.0 / 3.0, 1.0 / 3.0, (4, 3, 3))
+    w[5, 1, 1] = 2.0 / 3.0
+    return w.astype(np.float32).astype(np.float64)
+
+
+def stack_random(seed: int, scale_last: float = 0.05) -> np.ndarray:
+    """Stack weights with every kernel non-zero (parity tests): as stack_init,
+    f5 U(-scale_last, scale_last) and f6 perturbed by the same amount."""
+    rng = np.random.default_rng(seed)
+    w = stack_init(seed + 1000)
+    w[4] = rng.uniform(-scale_last, scale_last, (3, 3))
+    w[5] += rng.uniform(-scale_last, scale_last, (3, 3))
+    return w.astype(np.float32).astype(np.float64)
+
+
 # ----------------------------------------------------------------- workloads
 @dataclass
 class RotatedProblem:

@@ -53,7 +53,8 @@ typedef enum {
 typedef struct mg_ctx_s *mg_ctx;   /* solver context: hierarchy for a batch of problems */
 typedef struct mg_net_s *mg_net;   /* smoother network: parameters and optimiser state */
 
-enum { MG_SMOOTHER_JACOBI = 0, MG_SMOOTHER_CNN = 1 };
+enum { MG_SMOOTHER_JACOBI = 0, MG_SMOOTHER_CNN = 1, MG_SMOOTHER_STACK = 2 };
+#define MG_STACK_WEIGHTS 54
 enum { MG_PREC_FP64 = 0, MG_PREC_MIXED = 1 };
 
 /* ------------------------------------------------------------------------ */
@@ -98,7 +99,8 @@ typedef struct {
 } mg_problem;
 
 typedef struct {
-    int32_t smoother;       /* MG_SMOOTHER_JACOBI or MG_SMOOTHER_CNN                          */
+    int32_t smoother;       /* MG_SMOOTHER_JACOBI, MG_SMOOTHER_CNN or MG_SMOOTHER_STACK (weights
+                               from mg_set_stack; runs the step-by-step cycle kernels)        */
     int32_t nu_pre;         /* pre-smoothing sweeps, 0..8 (default 1)                          */
     int32_t nu_post;        /* post-smoothing sweeps, 0..8 (default 1)                         */
     double omega;           /* damping of the Jacobi smoother and of the CNN's Jacobi term (2/3) */
@@ -113,7 +115,8 @@ typedef struct {
                                its best, is switched to damped Jacobi: its smoother fields are
                                overwritten with omega / a_C (u restarts from 0 after a divergence,
                                continues otherwise).  mg_last_fallbacks tells which; a later CNN
-                               solve needs mg_smoother_infer again.  0 (default): off. */
+                               solve needs mg_smoother_infer again.  0 (default): off; must be 0
+                               with MG_SMOOTHER_STACK. */
 } mg_options;
 
 /* Fills the defaults listed above. */
@@ -344,6 +347,60 @@ typedef struct {
  * norm is not finite.  Synchronises. */
 mg_status mg_alpha_step(mg_ctx top, mg_ctx coarse, mg_ctx coarse_t, mg_net net, const mg_alpha_batch *b,
                         const mg_train_opts *o, double *loss, double *losses, float *grad);
+
+/* ---------------------------------------------- convolution-stack smoother
+ * The constant-coefficient alpha-CNN smoother of section 5 (full coarsening):
+ *     H x = f5(f4(f3(f2(f1(x))))) + f6(x),
+ * each f_i a single-channel 3x3 cross-correlation with zero padding (every
+ * intermediate grid is zero outside the n x n interior).  Weights: 54 FP64
+ * values [6][3][3] (layer, ky, kx), layers 0..4 = f1..f5, layer 5 = f6; tap
+ * (ky, kx) multiplies x at (j + ky - 1, i + kx - 1).  H is linear; it is
+ * applied to the residual as e += H (r - A e).  The paper initialises f1..f5
+ * with zeros and f6 as the Jacobi stencil; with all five composed kernels
+ * zero none of them receives a gradient, so the library leaves the
+ * initialisation to the caller (mg_inputs.stack_init: f1..f4 random, f5
+ * zero). */
+
+/* Installs one level's stack smoother on a context created with
+ * MG_SMOOTHER_STACK: phi host [54] FP64 (stored in the context's precision),
+ * transpose = 1 installs the stack of H^T instead (the kernels turned by 180
+ * degrees, f1..f5 in reverse order), as the adjoint context of
+ * mg_stack_alpha_step needs.  Every level above the coarsest of every problem
+ * needs weights before mg_vcycle / mg_solve / mg_fgmres (MG_ERR_STATE).
+ * Synchronises. */
+mg_status mg_set_stack(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose);
+
+/* y_c (+)= H x_c for c < count: x, y device [count][n][n] FP64 (must not
+ * overlap), phi device [54] FP64, accumulate 0 (y = H x) or 1 (y += H x).
+ * Asynchronous on stream. */
+mg_status mg_stack_apply(int32_t n, int32_t count, const double *phi, const double *x, double *y,
+                         int32_t accumulate, void *stream);
+
+/* One step of the adaptive training of a level's stack smoother (Algorithm
+ * 2, section 3.3): for the instances b of top (one problem, B right-hand
+ * sides, or several problems of one size), the loss
+ *   L = (1/B) sum_b || Phi(u0_b, f_b, k_b) - u*_b ||_2,
+ * Phi being k_b cycles of pre-smoothing with H, coarse correction
+ * P Psi_c R with one cycle of the fixed coarser hierarchy, post-smoothing
+ * with H; its gradient with respect to the 54 weights by the adjoint of
+ * those cycles (FP64); and, if o->apply_update, an FP64 Adam step (o's lr,
+ * beta1, beta2, adam_eps; t the 1-based step number for the bias correction)
+ * on phi with the moments adam_m, adam_v.
+ * top: FP64 context, every problem of the same n > coarsest_n (its smoother
+ *   setting is not used).
+ * coarse, coarse_t: FP64 contexts of the level-1 stencils of top's problems
+ *   (same order), nu_pre == nu_post, with the fixed coarser smoothers
+ *   installed; coarse_t with every smoother transposed (mg_set_stack with
+ *   transpose = 1; a damped Jacobi or coarsest-only context is its own
+ *   transpose and may be passed as both).
+ * phi, adam_m, adam_v: device [54] FP64 (phi updated in place).
+ * b: as for mg_alpha_step, with dW null.
+ * loss: host, the mean loss; losses: host [B] or NULL; grad: host [54] FP64
+ *   or NULL, dL/dphi.
+ * MG_ERR_DIVERGED (weights unchanged) if a norm is not finite.  Synchronises. */
+mg_status mg_stack_alpha_step(mg_ctx top, mg_ctx coarse, mg_ctx coarse_t, double *phi, double *adam_m,
+                              double *adam_v, int32_t t, const mg_alpha_batch *b, const mg_train_opts *o,
+                              double *loss, double *losses, double *grad);
 
 /* ------------------------------------------------------------------------ */
 const char *mg_status_str(mg_status s);

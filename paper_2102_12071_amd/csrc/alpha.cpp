@@ -82,8 +82,7 @@ mg_status check_coarse(const mg_ctx_s &top, const mg_ctx_s &c, const char *name)
         return set_error(MG_ERR_ARG, "%s: the coarse cycle needs as many post- as pre-smoothing sweeps", name);
     bool smooths = false;  // a hierarchy of the coarsest level alone has no smoother to set
     for (const ProbBuf &q : c.probs) smooths = smooths || q.nlev > 1;
-    if (c.opt.smoother == MG_SMOOTHER_CNN && smooths && !c.smoother_ready)
-        return set_error(MG_ERR_STATE, "%s: CNN smoother requested but no smoother was set", name);
+    if (smooths) MG_TRY(ctx_check_smoother(c));
     for (int p = 0; p < c.nprob; ++p) {
         const ProbBuf &t = top.probs[p], &q = c.probs[p];
         if (q.n != (t.n - 1) / 2 || q.nlev != t.nlev - 1)

@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(kAT) k_al_dist(int n, int P, int64_t vs, const
     if (threadIdx.x == 0) dist[z] = sqrt(s);
 }
 
-// lam = scale (x - y) / dist[z], zero where dist[z] = 0; dH = 0
+// lam = scale (x - y) / dist[z], zero where dist[z] = 0; dH = 0 (when given)
 __global__ void __launch_bounds__(kAT) k_al_seed(int n, int P, int64_t plane, int64_t vs, const double *x,
                                                   const double *y, const double *dist, double scale, double *lam,
                                                   double *dH)
@@ -167,6 +167,7 @@ __global__ void __launch_bounds__(kAT) k_al_seed(int n, int P, int64_t plane, in
     const int64_t p = t.z * vs + (int64_t)t.j * P + t.i;
     const double d = dist[t.z];
     lam[p] = d > 0.0 ? scale * (x[p] - y[p]) / d : 0.0;
+    if (!dH) return;
     const int64_t oh = t.z * 25 * plane + (int64_t)t.j * P + t.i;
     for (int k = 0; k < 25; ++k) dH[oh + k * plane] = 0.0;
 }

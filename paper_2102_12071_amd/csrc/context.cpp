@@ -20,6 +20,7 @@
 
 #include "internal.hpp"
 #include "launch.hpp"
+#include "stack.hpp"
 
 using namespace mg;
 
@@ -76,8 +77,13 @@ mg_status build_slots(mg_ctx_s &c)
     c.bottom_top_n = 0;
     for (int p = 0; p < c.nprob; ++p) {
         ProbBuf &pb = c.probs[p];
-        int top = 0;  // first level handled by the bottom kernel
-        while (pb.lev[top].n > kBottomMax) ++top;
+        // first level handled by the bottom kernel (the stack smoother runs in the
+        // step-by-step kernels on every level above the coarsest)
+        int top = 0;
+        if (c.opt.smoother == MG_SMOOTHER_STACK)
+            top = pb.nlev - 1;
+        else
+            while (pb.lev[top].n > kBottomMax) ++top;
         for (int l = 0; l < top; ++l) {
             const LevelBuf &L = pb.lev[l], &Lc = pb.lev[l + 1];
             CycleSlot<T> s{};
@@ -86,7 +92,8 @@ mg_status build_slots(mg_ctx_s &c)
             s.P = L.P;
             s.plane = L.plane;
             s.A = stencil_of<T>(L);
-            s.H = (const HT *)L.H;
+            // with the stack smoother, H points to the level's 54 weights (type T)
+            s.H = c.opt.smoother == MG_SMOOTHER_STACK ? (const HT *)L.phi : (const HT *)L.H;
             s.r = (T *)L.r;
             s.e = (T *)L.e;
             s.s = (T *)L.s;
@@ -161,8 +168,16 @@ mg_status build_slots(mg_ctx_s &c)
 template <typename T>
 void enqueue_vcycle(mg_ctx_s &c, hipStream_t st)
 {
-    const bool cnn = c.opt.smoother == MG_SMOOTHER_CNN;
+    const bool cnn = c.opt.smoother == MG_SMOOTHER_CNN, stack = c.opt.smoother == MG_SMOOTHER_STACK;
     const double w = c.opt.omega;
+    auto smooth = [&](const CycleSlot<T> *s, const SizeClass &k, bool first) {
+        if (stack)
+            launch_stack_cycle<T>(s, k.nrun, k.n, first, c.d_state, st);
+        else if (first)
+            launch_smooth_first<T>(s, k.nrun, k.n, cnn, w, c.d_state, st);
+        else
+            launch_smooth_apply<T>(s, k.nrun, k.n, cnn, w, c.d_state, st);
+    };
     if (c.fused) {
         for (const SizeClass &k : c.classes)  // descending sizes
             if (k.live)
@@ -182,10 +197,10 @@ void enqueue_vcycle(mg_ctx_s &c, hipStream_t st)
         if (c.opt.nu_pre == 0) {
             launch_zero_e<T>(s, k.nrun, k.n, c.d_state, st);
         } else {
-            launch_smooth_first<T>(s, k.nrun, k.n, cnn, w, c.d_state, st);
+            smooth(s, k, true);
             for (int it = 1; it < c.opt.nu_pre; ++it) {
                 launch_residual<T>(s, k.nrun, k.n, c.d_state, st);
-                launch_smooth_apply<T>(s, k.nrun, k.n, cnn, w, c.d_state, st);
+                smooth(s, k, false);
             }
         }
         launch_residual_restrict<T>(s, k.nrun, k.n, c.d_state, st);
@@ -200,7 +215,7 @@ void enqueue_vcycle(mg_ctx_s &c, hipStream_t st)
         launch_prolong<T>(s, k.nrun, k.n, c.d_state, st);
         for (int q = 0; q < c.opt.nu_post; ++q) {
             launch_residual<T>(s, k.nrun, k.n, c.d_state, st);
-            launch_smooth_apply<T>(s, k.nrun, k.n, cnn, w, c.d_state, st);
+            smooth(s, k, false);
         }
     }
 }
@@ -251,8 +266,8 @@ void enqueue_iteration_any(mg_ctx_s &c, hipStream_t st)
 
 mg_status validate_options(const mg_options &o)
 {
-    if (o.smoother != MG_SMOOTHER_JACOBI && o.smoother != MG_SMOOTHER_CNN)
-        return set_error(MG_ERR_ARG, "smoother must be MG_SMOOTHER_JACOBI or MG_SMOOTHER_CNN");
+    if (o.smoother != MG_SMOOTHER_JACOBI && o.smoother != MG_SMOOTHER_CNN && o.smoother != MG_SMOOTHER_STACK)
+        return set_error(MG_ERR_ARG, "smoother must be MG_SMOOTHER_JACOBI, MG_SMOOTHER_CNN or MG_SMOOTHER_STACK");
     if (o.nu_pre < 0 || o.nu_pre > 8 || o.nu_post < 0 || o.nu_post > 8)
         return set_error(MG_ERR_ARG, "nu_pre and nu_post must be in [0, 8]");
     if (!(o.omega > 0.0 && o.omega < 2.0)) return set_error(MG_ERR_ARG, "omega must be in (0, 2)");
@@ -262,6 +277,8 @@ mg_status validate_options(const mg_options &o)
         return set_error(MG_ERR_ARG, "precision must be MG_PREC_FP64 or MG_PREC_MIXED");
     if (o.check_every < 0) return set_error(MG_ERR_ARG, "check_every must be >= 0");
     if (o.fallback != 0 && o.fallback != 1) return set_error(MG_ERR_ARG, "fallback must be 0 or 1");
+    if (o.fallback && o.smoother == MG_SMOOTHER_STACK)
+        return set_error(MG_ERR_ARG, "the fallback to damped Jacobi applies to the CNN smoother only");
     return MG_OK;
 }
 
@@ -358,6 +375,7 @@ mg_status setup_impl(mg_ctx_s &c, const mg_problem *probs, hipStream_t user)
             ++l;
             if (m == c.opt.coarsest_n) break;
             MG_TRY(c.arena.alloc(&L.H, kSmoother * v * hsize(c)));
+            if (c.opt.smoother == MG_SMOOTHER_STACK) MG_TRY(c.arena.alloc(&L.phi, kStackWeights * tsize(c)));
             MG_TRY(c.arena.alloc(&L.s, v * tsize(c)));
             m = (m - 1) / 2;
         }
@@ -400,6 +418,8 @@ mg_status check_level(mg_ctx c, int prob, int level, bool smoother)
 {
     MG_TRY(check_ctx(c));
     if (prob < 0 || prob >= c->nprob) return set_error(MG_ERR_ARG, "problem index %d out of range", prob);
+    if (smoother && c->opt.smoother == MG_SMOOTHER_STACK)
+        return set_error(MG_ERR_STATE, "the stack smoother has no per-point field (mg_set_stack installs its weights)");
     const int top = c->probs[prob].nlev - (smoother ? 1 : 0);
     if (level < 0 || level >= top) return set_error(MG_ERR_ARG, "level %d out of range", level);
     return MG_OK;
@@ -500,6 +520,18 @@ mg_status ensure_graph(mg_ctx_s &c)
 // Services of the context for the Krylov driver (krylov.cpp).
 namespace mg {
 mg_status ctx_check(mg_ctx c) { return check_ctx(c); }
+mg_status ctx_check_smoother(const mg_ctx_s &c)
+{
+    if (c.opt.smoother == MG_SMOOTHER_CNN && !c.smoother_ready)
+        return set_error(MG_ERR_STATE, "CNN smoother requested but mg_smoother_infer has not run");
+    if (c.opt.smoother == MG_SMOOTHER_STACK)
+        for (int p = 0; p < c.nprob; ++p)
+            for (int l = 0; l + 1 < c.probs[p].nlev; ++l)
+                if (!c.probs[p].lev[l].phi_set)
+                    return set_error(MG_ERR_STATE, "problem %d level %d: no stack smoother installed (mg_set_stack)",
+                                     p, l);
+    return MG_OK;
+}
 mg_status ctx_check_vectors(mg_ctx c, const double *const *f, double *const *u) { return check_vectors(c, f, u); }
 mg_status ctx_set_live(mg_ctx_s &c, const std::vector<char> &active) { return update_live(c, active); }
 void ctx_enqueue_cycle(mg_ctx_s &c, hipStream_t st)
@@ -541,7 +573,7 @@ mg_status mg_setup(const mg_problem *probs, int32_t nprob, const mg_options *opt
     MG_TRY(require_device());
     mg_ctx c = new mg_ctx_s();
     c->opt = opt;
-    c->fused = opt.nu_pre == 1 && opt.nu_post == 1;
+    c->fused = opt.nu_pre == 1 && opt.nu_post == 1 && opt.smoother != MG_SMOOTHER_STACK;
     c->nprob = nprob;
     mg_status s = setup_impl(*c, probs, (hipStream_t)stream);
     if (s < 0) {
@@ -619,8 +651,7 @@ mg_status mg_vcycle(mg_ctx ctx, const double *const *f, double *const *u)
     clear_error();
     MG_TRY(check_ctx(ctx));
     MG_TRY(check_vectors(ctx, f, u));
-    if (ctx->opt.smoother == MG_SMOOTHER_CNN && !ctx->smoother_ready)
-        return set_error(MG_ERR_STATE, "CNN smoother requested but mg_smoother_infer has not run");
+    MG_TRY(ctx_check_smoother(*ctx));
     MG_TRY(ctx->join.enter());
     hipStream_t st = ctx->join.internal;
     copy_in(*ctx, f, u, false, st);
@@ -648,8 +679,7 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
     MG_TRY(check_vectors(ctx, f, u));
     if (!(rtol >= 0.0) || maxit < 0 || maxit > 100000000)
         return set_error(MG_ERR_ARG, "need rtol >= 0 and 0 <= maxit <= 1e8");
-    if (ctx->opt.smoother == MG_SMOOTHER_CNN && !ctx->smoother_ready)
-        return set_error(MG_ERR_STATE, "CNN smoother requested but mg_smoother_infer has not run");
+    MG_TRY(ctx_check_smoother(*ctx));
     mg_ctx_s &c = *ctx;
     const int stride = maxit + 1;
     if (history) {
@@ -826,11 +856,21 @@ void launch_timed(mg_ctx_s &c, int k, const SizeClass &cls, const SizeClass &oc,
         launch_bottom<T>((const BottomSlot<T> *)c.bottom.d_slots, c.nprob, c.bottom_top_n, cnn, w, c.opt.nu_pre,
                          c.opt.nu_post, c.d_state, st);
         break;
-    case 5: launch_smooth_first<T>(s, cls.nslots, n, cnn, w, c.d_state, st); break;
+    case 5:
+        if (c.opt.smoother == MG_SMOOTHER_STACK)
+            launch_stack_cycle<T>(s, cls.nslots, n, true, c.d_state, st);
+        else
+            launch_smooth_first<T>(s, cls.nslots, n, cnn, w, c.d_state, st);
+        break;
     case 6: launch_residual_restrict<T>(s, cls.nslots, n, c.d_state, st); break;
     case 7: launch_prolong<T>(s, cls.nslots, n, c.d_state, st); break;
     case 8: launch_residual<T>(s, cls.nslots, n, c.d_state, st); break;
-    case 9: launch_smooth_apply<T>(s, cls.nslots, n, cnn, w, c.d_state, st); break;
+    case 9:
+        if (c.opt.smoother == MG_SMOOTHER_STACK)
+            launch_stack_cycle<T>(s, cls.nslots, n, false, c.d_state, st);
+        else
+            launch_smooth_apply<T>(s, cls.nslots, n, cnn, w, c.d_state, st);
+        break;
     default: launch_update_u<T>(o, oc.nslots, n, c.d_state, st); break;
     }
 }
@@ -842,8 +882,7 @@ extern "C" mg_status mg_time_kernels(mg_ctx ctx, int32_t reps, double *ms)
     clear_error();
     MG_TRY(check_ctx(ctx));
     if (!ms || reps < 1) return set_error(MG_ERR_ARG, "need reps >= 1 and an output array");
-    if (ctx->opt.smoother == MG_SMOOTHER_CNN && !ctx->smoother_ready)
-        return set_error(MG_ERR_STATE, "CNN smoother requested but mg_smoother_infer has not run");
+    MG_TRY(ctx_check_smoother(*ctx));
     mg_ctx_s &c = *ctx;
     const int n0 = c.probs[0].n;
     const SizeClass *cls = nullptr, *oc = nullptr;
@@ -1096,6 +1135,8 @@ extern "C" mg_status mg_smoother_infer(mg_ctx ctx, mg_net net)
 {
     clear_error();
     MG_TRY(check_ctx(ctx));
+    if (ctx->opt.smoother == MG_SMOOTHER_STACK)
+        return set_error(MG_ERR_STATE, "the stack smoother is not produced by a network (mg_set_stack)");
     if (!net) return set_error(MG_ERR_ARG, "net is null");
     MG_TRY(ctx->join.enter());
     MG_TRY(ctx_infer(*ctx, net, 0, ctx->join.internal, nullptr));
@@ -1107,6 +1148,8 @@ extern "C" mg_status mg_smoother_infer_size(mg_ctx ctx, mg_net net, int32_t n)
 {
     clear_error();
     MG_TRY(check_ctx(ctx));
+    if (ctx->opt.smoother == MG_SMOOTHER_STACK)
+        return set_error(MG_ERR_STATE, "the stack smoother is not produced by a network (mg_set_stack)");
     if (!net) return set_error(MG_ERR_ARG, "net is null");
     bool found = false;
     for (const ProbBuf &pb : ctx->probs)

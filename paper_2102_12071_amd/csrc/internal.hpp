@@ -64,6 +64,8 @@ struct LevelBuf {
     float *A32 = nullptr;
     void *H = nullptr;  // 25 planes: bf16 (mixed) or double (FP64)
     void *r = nullptr, *e = nullptr, *s = nullptr;
+    void *phi = nullptr;   // stack smoother: 54 weights (float or double), levels above the coarsest
+    bool phi_set = false;  // mg_set_stack has installed them
 };
 
 struct ProbBuf {
@@ -118,6 +120,9 @@ namespace mg {
 // Services of the solver context used by the Krylov driver (context.cpp).
 mg_status ctx_check(mg_ctx c);
 mg_status ctx_check_vectors(mg_ctx c, const double *const *f, double *const *u);
+// MG_ERR_STATE unless the context's smoother can run: the CNN's fields inferred
+// or set, the stack's weights installed on every level above the coarsest.
+mg_status ctx_check_smoother(const mg_ctx_s &c);
 // Launches only the slots of the given problems from now on (see update_live).
 mg_status ctx_set_live(mg_ctx_s &c, const std::vector<char> &active);
 // Enqueues e = V(r) of the live problems: level-0 r in, u += e on the finest level.

@@ -171,8 +171,7 @@ extern "C" mg_status mg_solve_fgmres(mg_ctx ctx, const double *const *f, double 
     if (!(rtol >= 0.0) || maxit < 0 || maxit > 100000000)
         return set_error(MG_ERR_ARG, "need rtol >= 0 and 0 <= maxit <= 1e8");
     if (restart < 1 || restart > 256) return set_error(MG_ERR_ARG, "restart must be in [1, 256]");
-    if (ctx->opt.smoother == MG_SMOOTHER_CNN && !ctx->smoother_ready)
-        return set_error(MG_ERR_STATE, "CNN smoother requested but mg_smoother_infer has not run");
+    MG_TRY(ctx_check_smoother(*ctx));
     mg_ctx_s &c = *ctx;
     MG_TRY(ensure_workspace(c, restart));
     MG_TRY(c.join.enter());

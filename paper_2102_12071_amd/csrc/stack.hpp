@@ -1,0 +1,44 @@
+// Convolution-stack smoother (the constant-coefficient alpha-CNN of section 5,
+// full coarsening): kernels and their launchers.
+#pragma once
+#include "common.hpp"
+
+namespace mg {
+
+constexpr int kStackWeights = 54;  // [6][3][3]: f1..f5 composed, then f6
+
+// The smoothing sweeps of the step-by-step cycle with the stack smoother: the
+// slot's H points to the level's 54 weights (type T).  first: e = H r; else
+// e += H s (s = r - A e from the residual kernel).
+template <typename T>
+void launch_stack_cycle(const CycleSlot<T> *slots, int nslots, int n, bool first, const SolveState *state,
+                        hipStream_t st);
+
+// y_z (+)= H x_z for z < count, vectors of pitch P at stride vs, one weight
+// set w (device, [54]); active (or null) skips vectors.  x and y must not overlap.
+void launch_stack_vecs(const double *x, double *y, int64_t vs, const double *w, int n, int P, int count,
+                       bool accumulate, const int *active, hipStream_t st);
+
+// y_z = C x_z for the single layer with kernel w[9] (turned by 180 degrees
+// when flip: the transposed correlation).
+void launch_stack_layer(const double *x, double *y, int64_t vs, const double *w, bool flip, int n, int P, int count,
+                        const int *active, hipStream_t st);
+
+// The gradient of <g, H x> with respect to the 54 weights, per layer L the
+// correlation of g[L] with x[L] over the grid, added into part[z][block][54].
+struct StackPairs {
+    const double *g[6];
+    const double *x[6];
+};
+int stack_wgrad_blocks(int n);
+void launch_stack_wgrad(const StackPairs &pr, int64_t vs, int n, int P, int count, const int *active, double *part,
+                        hipStream_t st);
+// grad[54] = sum over the rows of part ([nrow][54]), in row order.
+void launch_stack_gsum(const double *part, int64_t nrow, double *grad, hipStream_t st);
+// The weights of H^T.
+void launch_stack_transpose(const double *w, double *wT, hipStream_t st);
+// Adam on the 54 weights (FP64), step t >= 1.
+void launch_stack_adam(double *w, double *m, double *v, const double *g, int t, double lr, double b1, double b2,
+                       double eps, hipStream_t st);
+
+}  // namespace mg

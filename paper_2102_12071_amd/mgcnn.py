@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_HERE, "libmgcnn.so")
 
 MG_OK, MG_NOT_CONVERGED = 0, 1
 MG_ERR_ARG, MG_ERR_SHAPE, MG_ERR_DEVICE, MG_ERR_DIVERGED, MG_ERR_STATE, MG_ERR_OOM = -1, -2, -3, -4, -5, -6
-SMOOTHER_JACOBI, SMOOTHER_CNN = 0, 1
+SMOOTHER_JACOBI, SMOOTHER_CNN, SMOOTHER_STACK = 0, 1, 2
+STACK_WEIGHTS = 54
 PREC_FP64, PREC_MIXED = 0, 1
 
 CNN_CHANNELS = (9, 32, 32, 32, 25)
@@ -90,6 +91,10 @@ SIGNATURES = {
     "mg_alpha_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(AlphaBatch),
                                 C.POINTER(TrainOpts), _c_dp, _c_dp, _c_fp]),
     "mg_set_smoother": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
+    "mg_set_stack": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _c_dp, C.c_int32]),
+    "mg_stack_apply": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
+    "mg_stack_alpha_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                      C.c_int32, C.POINTER(AlphaBatch), C.POINTER(TrainOpts), _c_dp, _c_dp, _c_dp]),
     "mg_get_smoother": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "mg_vcycle": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "mg_solve": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_double, C.c_int32, _c_ip,
@@ -325,6 +330,27 @@ class Context:
         _check(load_library().mg_set_smoother(self._h, prob, level, _ptr(W)))
         torch.cuda.current_stream().synchronize()
 
+    def set_stack(self, prob: int, level: int, phi, transpose: bool = False) -> None:
+        """Installs a level's convolution-stack smoother (54 weights [6][3][3], f1..f5 then f6)."""
+        w = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).reshape(-1))
+        if w.size != STACK_WEIGHTS:
+            raise ValueError("a stack has 54 weights")
+        _check(load_library().mg_set_stack(self._h, prob, level, w.ctypes.data_as(_c_dp), int(bool(transpose))))
+
+    def set_stacks(self, stacks: dict, transpose: bool = False) -> None:
+        """Every level above the coarsest of every problem from {trained size: weights normalised
+        to a_C = 1}: a level of size m takes the stack of the nearest trained size on the log2
+        scale (levels finer than every trained size: the finest one), scaled to the level's
+        operator by stack_for_level."""
+        sizes = sorted(int(k) for k in stacks)
+        if not sizes:
+            raise ValueError("no stacks given")
+        for p in range(self.nprob):
+            for l in range(self.num_levels(p) - 1):
+                m = self.level_n(p, l)
+                best = min(sizes, key=lambda q: abs(math.log2(q + 1) - math.log2(m + 1)))
+                self.set_stack(p, l, stack_for_level(stacks[best], self.stencil(p, l)), transpose)
+
     def infer(self, net: "Net", size: Optional[int] = None) -> None:
         """Network inference on every smoothing level, or (size given) on the levels of that size only."""
         if size is None:
@@ -508,6 +534,72 @@ def smoother_transpose(A: torch.Tensor, W: torch.Tensor) -> torch.Tensor:
     out = torch.empty_like(W)
     _check(load_library().mg_smoother_transpose(n, _ptr(A), _ptr(W), _ptr(out), _stream()))
     return out
+
+
+def stack_for_level(phi, A: torch.Tensor) -> np.ndarray:
+    """Stack weights normalised to an operator with centre entry 1 (f5 and f6 carry the scale of
+    H ~ 1 / a_C), rescaled to the level whose stencil A is given: f5 and f6 divided by its centre
+    entry (constant coefficients: one value; the mean is taken)."""
+    w = np.array(phi, dtype=np.float64).reshape(6, 3, 3)
+    ac = float(A[4].mean())
+    w[4:] /= ac
+    return w
+
+
+def stack_apply(phi: torch.Tensor, x: torch.Tensor, y: Optional[torch.Tensor] = None,
+                accumulate: bool = False) -> torch.Tensor:
+    """y (+)= H x for the stack phi (device [54] FP64) on a batch x [count, n, n] or [n, n]."""
+    phi = _dev_f64(phi).reshape(-1)
+    if phi.numel() != STACK_WEIGHTS:
+        raise ValueError("a stack has 54 weights")
+    x = _dev_f64(x)
+    xb = x.reshape(-1, x.shape[-2], x.shape[-1])
+    n = xb.shape[-1]
+    if y is None:
+        y = torch.zeros_like(x)
+    yb = y.reshape(-1, n, n)
+    _check(load_library().mg_stack_apply(n, xb.shape[0], _ptr(phi), _ptr(xb), _ptr(yb), int(bool(accumulate)),
+                                         _stream()))
+    return y
+
+
+class StackAdam:
+    """The 54 device weights of one level's stack and their Adam state (FP64)."""
+
+    def __init__(self, phi):
+        self.phi = torch.tensor(np.asarray(phi, dtype=np.float64).reshape(-1), device="cuda")
+        self.m = torch.zeros(STACK_WEIGHTS, dtype=torch.float64, device="cuda")
+        self.v = torch.zeros(STACK_WEIGHTS, dtype=torch.float64, device="cuda")
+        self.t = 0
+
+
+def stack_alpha_step(top: Context, coarse: Context, coarse_t: Context, state: StackAdam, k: Sequence[int],
+                     f: Sequence[torch.Tensor], u0: Sequence[torch.Tensor], u_star: Sequence[torch.Tensor],
+                     opts: Optional["TrainOptions"] = None) -> "AlphaResult":
+    """One Algorithm 2 step of a stack smoother (mg_stack_alpha_step): loss, the 54-weight
+    gradient (FP64), and an Adam update of state per opts."""
+    opts = opts or TrainOptions(precision=0)
+    B = top.nprob
+    n = top.ns[0]
+    if not (len(k) == len(f) == len(u0) == len(u_star) == B):
+        raise ValueError(f"need {B} entries of k, f, u0 and u_star")
+    f = [_dev_f64(x, (n, n)) for x in f]
+    u0 = [_dev_f64(x, (n, n)) for x in u0]
+    us = [_dev_f64(x, (n, n)) for x in u_star]
+    arr = lambda xs: (C.c_void_p * B)(*[x.data_ptr() for x in xs])
+    kk = (C.c_int32 * B)(*[int(x) for x in k])
+    batch = AlphaBatch(B, kk, arr(f), arr(u0), arr(us), None)
+    o = opts.to_c()
+    t = state.t + 1 if opts.apply_update else max(state.t, 1)
+    loss = C.c_double()
+    losses = np.zeros(B, dtype=np.float64)
+    grad = np.zeros(STACK_WEIGHTS, dtype=np.float64)
+    _check(load_library().mg_stack_alpha_step(top._h, coarse._h, coarse_t._h, _ptr(state.phi), _ptr(state.m),
+                                              _ptr(state.v), t, C.byref(batch), C.byref(o), C.byref(loss),
+                                              losses.ctypes.data_as(_c_dp), grad.ctypes.data_as(_c_dp)))
+    if opts.apply_update:
+        state.t = t
+    return AlphaResult(loss=loss.value, losses=losses, grad=grad)
 
 
 @dataclass

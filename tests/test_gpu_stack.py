@@ -1,0 +1,195 @@
+"""GPU convolution-stack smoother (the constant-coefficient alpha-CNN of
+section 5, H = f5(..f1) + f6) through the C ABI against the FP64 oracle
+(oracle/stack.py): the LDS-tiled apply, V-cycles and solves in FP64 and mixed
+precision, the Algorithm 2 loss, weight gradient and Adam update, and the
+error paths."""
+import math
+
+import numpy as np
+import pytest
+
+import mg_inputs
+import oracle as ora
+from oracle import stack as st
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mg():
+    from paper_2102_12071_amd import mgcnn
+    mgcnn.load_library()
+    assert torch.cuda.is_available()
+    return mgcnn
+
+
+def _dev(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def _scaled(seed, A, f32=False):
+    w = mg_inputs.stack_random(seed)
+    w[4:] /= A[4].flat[0]
+    return w.astype(np.float32).astype(np.float64) if f32 else w
+
+
+@pytest.mark.parametrize("n,count", [(1, 2), (13, 3), (64, 1), (127, 2), (130, 1)])
+def test_stack_apply_matches_oracle(mg, n, count):
+    # one tile, several tiles, exact and ragged tile edges in both directions
+    w = mg_inputs.stack_random(n)
+    x = np.stack([mg_inputs.random_field((n, n), 10 * n + c) for c in range(count)])
+    y0 = np.stack([mg_inputs.random_field((n, n), 10 * n + c + 5) for c in range(count)])
+    ref = np.stack([st.stack_apply(w, xc) for xc in x])
+    got = mg.stack_apply(_dev(w), _dev(x)).cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    y = _dev(y0)
+    mg.stack_apply(_dev(w), _dev(x), y, accumulate=True)
+    assert np.abs(y.cpu().numpy() - (y0 + ref)).max() <= 1e-13 * np.abs(y0 + ref).max()
+
+
+def _hierarchy_pair(mg, n, precision, seed, coarsest=7, f32=False):
+    A = ora.stencil_q1_rotated(n, 1.1, 0.03)
+    h = st.StackHierarchy(A, coarsest)
+    ctx = mg.Context([_dev(A)], mg.Options(smoother=mg.SMOOTHER_STACK, precision=precision, coarsest_n=coarsest))
+    assert ctx.num_levels(0) == h.num_levels
+    for l in range(h.num_levels - 1):
+        w = _scaled(seed + l, h.stencils[l], f32)
+        h.set_stack(l, w)
+        ctx.set_stack(0, l, w)
+    return A, h, ctx
+
+
+@pytest.mark.parametrize("n", [63, 255])
+def test_fp64_cycle_matches_oracle(mg, n):
+    A, h, ctx = _hierarchy_pair(mg, n, mg.PREC_FP64, 3)
+    f = mg_inputs.rhs_uniform(n, 1)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    ctx.vcycle([_dev(f)], [u])
+    ref = h.vcycle(f)
+    assert np.abs(u.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_mixed_cycle_matches_oracle(mg):
+    # FP32 inner cycle with the FP32 weights the context holds
+    n = 255
+    A, h, ctx = _hierarchy_pair(mg, n, mg.PREC_MIXED, 5, f32=True)
+    f = mg_inputs.rhs_uniform(n, 2)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    ctx.vcycle([_dev(f)], [u])
+    ref = h.vcycle(f)
+    assert np.abs(u.cpu().numpy() - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
+def test_fp64_solve_matches_oracle_iterates(mg):
+    # near-Jacobi stacks (every kernel non-zero) converge; FP64 histories agree per iteration
+    n = 63
+    A, h, ctx = _hierarchy_pair(mg, n, mg.PREC_FP64, 11)
+    f = mg_inputs.rhs_uniform(n, 3)
+    u_ref, k, hist, conv = h.solve(f, 1e-10, 300)
+    assert conv
+    res = ctx.solve([_dev(f)], 1e-10, 300, history=True)
+    assert res.status[0] == 0 and int(res.iters[0]) == k
+    assert np.allclose(res.history[0, :k + 1], hist, rtol=1e-9, atol=1e-15)
+    assert np.abs(res.u[0].cpu().numpy() - u_ref).max() <= 1e-10 * np.abs(u_ref).max()
+    fg = ctx.solve_fgmres([_dev(f)], 1e-10, 300)
+    assert fg.status[0] == 0 and int(fg.iters[0]) <= k
+
+
+def _stage(mg, n, B, seed, coarsest=3):
+    """One training stage of a single problem with B instances: the top context (B copies of
+    the stencil), the coarse contexts with fixed stacks (transposed in coarse_t), data."""
+    A = ora.stencil_q1_rotated(n, 0.9, 0.03)
+    Ac = ora.galerkin(A)
+    hc = st.StackHierarchy(Ac, coarsest)
+    top = mg.Context([_dev(A)] * B, mg.Options(precision=mg.PREC_FP64, coarsest_n=coarsest))
+    if hc.num_levels > 1:
+        opt = mg.Options(smoother=mg.SMOOTHER_STACK, precision=mg.PREC_FP64, coarsest_n=coarsest)
+        coarse, coarse_t = mg.Context([_dev(Ac)] * B, opt), mg.Context([_dev(Ac)] * B, opt)
+        for l in range(hc.num_levels - 1):
+            wl = _scaled(seed + 30 + l, hc.stencils[l])
+            hc.set_stack(l, wl)
+            for b in range(B):
+                coarse.set_stack(b, l, wl)
+                coarse_t.set_stack(b, l, wl, transpose=True)
+    else:  # the level below is the coarsest: Psi_c is its exact solve, its own transpose
+        coarse = coarse_t = mg.Context([_dev(Ac)] * B, mg.Options(precision=mg.PREC_FP64, coarsest_n=coarsest))
+    rng = np.random.default_rng(seed)
+    f = [mg_inputs.random_field((n, n), seed + 10 + b) for b in range(B)]
+    u0 = [rng.normal(size=(n, n)) for _ in range(B)]
+    us = [mg_inputs.random_field((n, n), seed + 20 + b) for b in range(B)]
+    return A, hc, top, coarse, coarse_t, f, u0, us
+
+
+@pytest.mark.parametrize("n,ks", [(7, [2, 1]), (15, [3, 1, 2]), (31, [2, 4])])
+def test_alpha_step_matches_oracle(mg, n, ks):
+    B = len(ks)
+    A, hc, top, coarse, coarse_t, f, u0, us = _stage(mg, n, B, 7 * n)
+    w = _scaled(n, A)
+    L_ref, g_ref = st.batch_loss_and_grad(A, w, hc, f, u0, us, ks)
+    state = mg.StackAdam(w)
+    opts = mg.TrainOptions(precision=0, lr=1e-3)
+    D = lambda xs: [_dev(x) for x in xs]
+    res = mg.stack_alpha_step(top, coarse, coarse_t, state, ks, D(f), D(u0), D(us), opts)
+    assert res.loss == pytest.approx(L_ref, rel=1e-12)
+    for b in range(B):
+        Lb, _ = st.alpha_loss_and_grad(A, w, hc, f[b], u0[b], us[b], ks[b])
+        assert res.losses[b] == pytest.approx(Lb, rel=1e-12)
+    assert np.abs(res.grad - g_ref).max() <= 1e-10 * np.abs(g_ref).max()
+    # the Adam update of the first step (lr held as float32 by the options struct)
+    p1, _, _ = ora.adam_step(w.reshape(-1), np.zeros(54), np.zeros(54), res.grad, 1, lr=float(np.float32(1e-3)))
+    assert np.abs(state.phi.cpu().numpy() - p1).max() <= 1e-14 * np.abs(p1).max()
+    assert state.t == 1
+
+
+def test_alpha_steps_reduce_the_loss(mg):
+    # Algorithm 2 from the damped-Jacobi initialisation (f1..f4 random, f5 zero) on a fixed batch
+    n, ks = 15, [4, 4, 4, 4]
+    A, hc, top, coarse, coarse_t, f, u0, us = _stage(mg, n, 4, 99)
+    w = mg_inputs.stack_init(1)
+    w[4:] /= A[4].flat[0]
+    state = mg.StackAdam(w)
+    opts = mg.TrainOptions(precision=0, lr=1e-2)
+    fd, u0d, usd = [_dev(x) for x in f], [_dev(x) for x in u0], [_dev(x) for x in us]
+    first = mg.stack_alpha_step(top, coarse, coarse_t, state, ks, fd, u0d, usd, opts).loss
+    for _ in range(30):
+        last = mg.stack_alpha_step(top, coarse, coarse_t, state, ks, fd, u0d, usd, opts).loss
+    assert last < 0.95 * first  # the FP64 oracle reaches 0.91 on this batch
+    # the weights the GPU reached give the oracle the same loss
+    L_ref, _ = st.batch_loss_and_grad(A, state.phi.cpu().numpy(), hc, f, u0, us, ks)
+    probe = mg.stack_alpha_step(top, coarse, coarse_t, state, ks, fd, u0d, usd,
+                                mg.TrainOptions(precision=0, apply_update=0))
+    assert probe.loss == pytest.approx(L_ref, rel=1e-12)
+
+
+def test_error_paths(mg):
+    n = 15
+    A = _dev(ora.stencil_q1_rotated(n, 0.5, 0.1))
+    jac = mg.Context([A], mg.Options(precision=mg.PREC_FP64))
+    with pytest.raises(mg.MGError) as e:
+        jac.set_stack(0, 0, np.zeros(54))
+    assert e.value.status == mg.MG_ERR_STATE
+    ctx = mg.Context([A], mg.Options(smoother=mg.SMOOTHER_STACK, precision=mg.PREC_FP64))
+    f = _dev(mg_inputs.rhs_uniform(n, 0))
+    with pytest.raises(mg.MGError) as e:  # no weights installed yet
+        ctx.solve([f], 1e-8, 10)
+    assert e.value.status == mg.MG_ERR_STATE
+    with pytest.raises(mg.MGError) as e:
+        ctx.smoother(0, 0)
+    assert e.value.status == mg.MG_ERR_STATE
+    with pytest.raises(mg.MGError) as e:
+        ctx.set_stack(0, ctx.num_levels(0) - 1, np.zeros(54))  # the coarsest level has no smoother
+    assert e.value.status == mg.MG_ERR_ARG
+    with pytest.raises(mg.MGError) as e:
+        mg.Context([A], mg.Options(smoother=mg.SMOOTHER_STACK, fallback=1))
+    assert e.value.status == mg.MG_ERR_ARG
+    x = torch.zeros((2, n, n), dtype=torch.float64, device="cuda")
+    with pytest.raises(mg.MGError) as e:
+        mg.stack_apply(_dev(np.zeros(54)), x, x)
+    assert e.value.status == mg.MG_ERR_ARG
+    bad = np.zeros(54)
+    bad[3] = math.nan
+    with pytest.raises(mg.MGError) as e:
+        ctx.set_stack(0, 0, bad)
+    assert e.value.status == mg.MG_ERR_ARG

@@ -332,6 +332,9 @@ def main():
         out["jacobi_sweeps"] = sweeps_block(args, A, f, n, cnn_s, coarsest)
     if args.geometries:
         out["geometries"] = geometry_block(args, net, alpha_nets if use_alpha else None, n)
+    stack = stack_block(args, A, f, n, theta, eps, coarsest)
+    if stack is not None:
+        out["alpha_stack"] = stack
     if args.train_steps > 0:
         out["training"] = training_block(args)
     out["roofline"]["copy_gbs"] = copy_bandwidth()
@@ -392,6 +395,51 @@ def sweeps_block(args, A, f, n, cnn_s, coarsest):
                              "ms_per_iteration": float(res.ms) / max(int(res.iters[0]), 1)}
         log(f"jacobi V({nu},{nu}): {int(res.iters[0])} iterations, {ms:.1f} ms")
         ctx.close()
+    return out
+
+
+def stack_block(args, A, f, n, theta, eps, coarsest):
+    """The paper's constant-coefficient alpha-CNN (H = f5(..f1) + f6 per level,
+    trained per problem by Algorithm 2; weights/stack_*.json) on this problem,
+    if a committed training run matches it: iterations and time to the
+    tolerance, and the stack kernel's own rate on the finest level (its
+    algorithmic traffic: x with the 5-node halo of a 64 x 16 tile, e read and
+    written, FP32)."""
+    import glob
+
+    import torch
+
+    from paper_2102_12071_amd import mgcnn
+    from paper_2102_12071_amd.stack_train import load_stacks
+    path = None
+    for p in sorted(glob.glob(os.path.join(os.path.dirname(WEIGHTS), "stack_*.json"))):
+        with open(p) as fh:
+            prob = json.load(fh).get("problem", {})
+        if abs(prob.get("theta", -1) - theta) < 1e-9 and abs(prob.get("eps", -1) - eps) < 1e-12 * max(eps, 1):
+            path = p
+    if path is None:
+        return None
+    stacks = load_stacks(path)
+    ctx = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_STACK, coarsest_n=coarsest))
+    ctx.set_stacks(stacks)
+    ctx.solve([f], args.tol, args.maxit)  # warm-up (graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ctx.solve([f], args.tol, args.maxit)
+    ms = (time.perf_counter() - t0) * 1e3
+    k = ctx.time_kernels(args.kernel_reps)
+    ctx.close()
+    tile_bytes = 4.0 * (74 * 26) / (64 * 16) + 8.0  # per node: staged x, e read and written
+    bytes_per_launch = tile_bytes * n * n
+    out = {"weights": os.path.relpath(path, os.path.dirname(os.path.abspath(__file__))),
+           "trained_sizes": sorted(stacks), "iters": int(res.iters[0]), "status": int(res.status[0]),
+           "relres": float(res.relres[0]), "solve_ms": ms,
+           "ms_per_iteration": float(res.ms) / max(int(res.iters[0]), 1),
+           "kernel": {"name": "k_stack_cycle (accumulating)", "ms": k["smooth_apply"],
+                      "algorithmic_bytes": bytes_per_launch,
+                      "achieved_gbs": bytes_per_launch / (k["smooth_apply"] * 1e-3) / 1e9}}
+    log(f"alpha-CNN stack ({os.path.basename(path)}): {out['iters']} iterations, status {out['status']}, "
+        f"{ms:.1f} ms; stack kernel {k['smooth_apply'] * 1e3:.1f} us")
     return out
 
 

@@ -41,7 +41,9 @@ __device__ void stack_tile(const T MG_G *x, T MG_G *y, const T MG_G *w, int n, i
     __syncthreads();
     const T *src = b0;
     T *dst = b1;
-#pragma unroll 1
+    // unrolled: each layer's region width is a compile-time constant, so the
+    // flat index splits into (xx, yy) without a division instruction sequence
+#pragma unroll
     for (int layer = 0; layer < 5; ++layer) {
         const int m = layer + 1;  // this layer is valid on [m, kLW - m) x [m, kLH - m)
         const int rw = kLW - 2 * m, rh = kLH - 2 * m;

@@ -153,33 +153,53 @@ def _run_stage(stage: StackStage, w0: np.ndarray, steps: int, lr: float, lr_fina
 
 def train(theta: float, eps: float, finest: int = 63, Q: int = 50, steps: int = 400, lr: float = 1e-3,
           lr_final: Optional[float] = None, bmax: int = 4, seed: int = 0, coarsest: int = 3,
-          update_rounds: int = 0, update_steps: int = 200, log=print):
+          update_rounds: int = 0, update_steps: int = 200, warm: bool = False, max_points: int = 0,
+          steps_large: Optional[int] = None, large_n: int = 63, log=print):
+    """Stages from the coarsest up.  warm: a stage starts from the previous stage's weights (the
+    operator is the same up to scale on every level) instead of the damped-Jacobi initialisation;
+    max_points: at most that many grid points per stage (Q shrinks on large stages, at least 4);
+    stages above large_n take steps_large steps and no update rounds."""
     lr_final = lr if lr_final is None else lr_final
+    steps_large = steps if steps_large is None else steps_large
     stacks: Dict[int, np.ndarray] = {}
     records = []
-    for n in stage_sizes(finest, coarsest):
+    qn = lambda n: max(4, min(Q, max_points // (n * n))) if max_points else Q
+    sizes = stage_sizes(finest, coarsest)
+
+    def stage(n, prev):
         t0 = time.time()
-        stage = StackStage(n, theta, eps, Q, stacks, seed, coarsest)
-        w, start, end = _run_stage(stage, mg_inputs.stack_init(seed + n), steps, lr, lr_final, bmax, log)
-        stage.close()
+        st = StackStage(n, theta, eps, qn(n), stacks, seed, coarsest)
+        w0 = stacks[prev] if (warm and prev is not None) else mg_inputs.stack_init(seed + n)
+        w, start, end = _run_stage(st, w0, steps if n <= large_n else steps_large, lr, lr_final, bmax, log)
+        st.close()
         stacks[n] = w
-        _, growth = worst_errors(n, theta, eps, 8, stacks, seed, coarsest=coarsest)
-        records.append({"stage_n": n, "loss_start": start, "loss_end": end, "growth": growth,
+        _, growth = worst_errors(n, theta, eps, min(8, qn(n)), stacks, seed, coarsest=coarsest)
+        records.append({"stage_n": n, "instances": st.Q, "loss_start": start, "loss_end": end, "growth": growth,
                         "seconds": round(time.time() - t0, 3)})
         log(json.dumps(records[-1]))
+
+    # the stages up to large_n, then the update rounds on them, then the larger stages
+    prev = None
+    for n in [m for m in sizes if m <= large_n]:
+        stage(n, prev)
+        prev = n
     for rnd in range(update_rounds):
-        for n in stage_sizes(finest, coarsest):
+        for n in [m for m in sizes if m <= large_n]:
             t0 = time.time()
-            inject, before = worst_errors(n, theta, eps, Q // 2, stacks, seed, coarsest=coarsest, rnd=rnd + 1)
+            inject, before = worst_errors(n, theta, eps, max(2, qn(n) // 2), stacks, seed, coarsest=coarsest,
+                                          rnd=rnd + 1)
             lower = {m: s for m, s in stacks.items() if m < n}
-            stage = StackStage(n, theta, eps, Q, lower, seed + 100 * (rnd + 1), coarsest, inject)
-            w, start, end = _run_stage(stage, stacks[n], update_steps, lr_final, lr_final, bmax, log)
-            stage.close()
+            st = StackStage(n, theta, eps, qn(n), lower, seed + 100 * (rnd + 1), coarsest, inject)
+            w, start, end = _run_stage(st, stacks[n], update_steps, lr_final, lr_final, bmax, log)
+            st.close()
             stacks[n] = w
-            _, after = worst_errors(n, theta, eps, 8, stacks, seed, coarsest=coarsest)
+            _, after = worst_errors(n, theta, eps, min(8, qn(n)), stacks, seed, coarsest=coarsest)
             records.append({"update_round": rnd, "stage_n": n, "growth_before": before, "growth_after": after,
                             "loss_start": start, "loss_end": end, "seconds": round(time.time() - t0, 3)})
             log(json.dumps(records[-1]))
+    for n in [m for m in sizes if m > large_n]:
+        stage(n, prev)
+        prev = n
     return stacks, records
 
 
@@ -213,6 +233,10 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--update-rounds", type=int, default=0)
     ap.add_argument("--update-steps", type=int, default=200)
+    ap.add_argument("--warm", action="store_true", help="start each stage from the previous stage's weights")
+    ap.add_argument("--max-points", type=int, default=0, help="grid points per stage (0: Q instances always)")
+    ap.add_argument("--steps-large", type=int, default=None, help="steps of the stages above --large-n")
+    ap.add_argument("--large-n", type=int, default=63)
     ap.add_argument("--eval", type=int, nargs="*", default=[63, 255, 1023])
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
@@ -222,14 +246,15 @@ def main():
 
     mgcnn.load_library()
     stacks, records = train(a.theta, a.eps, a.finest, a.instances, a.steps, a.lr, a.lr_final, a.bmax, a.seed,
-                            update_rounds=a.update_rounds, update_steps=a.update_steps, log=log)
+                            update_rounds=a.update_rounds, update_steps=a.update_steps, warm=a.warm,
+                            max_points=a.max_points, steps_large=a.steps_large, large_n=a.large_n, log=log)
     for n in a.eval:
         r = evaluate(stacks, n, a.theta, a.eps)
         records.append({"eval": {"n": n, "theta": a.theta, "eps": a.eps}, **r})
         log(json.dumps(records[-1]))
     cmd = "python -m paper_2102_12071_amd.stack_train " + " ".join(sys.argv[1:])
     with open(a.out, "w") as fh:
-        json.dump({"command": cmd, "device": "one MI355X",
+        json.dump({"command": cmd, "device": "one MI355X", "problem": {"theta": a.theta, "eps": a.eps},
                    "note": "weights [6][3][3] per trained size, normalised to a_C = 1 (f5 and f6 times a_C); "
                            "eval: V(1,1) to 1e-8 over a 7 x 7 coarsest grid, mixed precision",
                    "stacks": {str(n): w.reshape(-1).tolist() for n, w in stacks.items()},

@@ -193,3 +193,51 @@ def test_error_paths(mg):
     with pytest.raises(mg.MGError) as e:
         ctx.set_stack(0, 0, bad)
     assert e.value.status == mg.MG_ERR_ARG
+
+
+def _committed(mg, name):
+    import os
+    from paper_2102_12071_amd.stack_train import load_stacks
+    return load_stacks(os.path.join(os.path.dirname(mg.__file__), "weights", name))
+
+
+def test_committed_stacks_cycle_matches_oracle(mg):
+    # the trained weights as inputs: FP64 cycle of the library against the oracle's, every level
+    # taking the stack of the nearest trained size scaled by its centre entry
+    stacks = _committed(mg, "stack_theta0_eps0.01.json")
+    n = 127
+    A = ora.stencil_q1_rotated(n, 0.0, 0.01)
+    ctx = mg.Context([_dev(A)], mg.Options(smoother=mg.SMOOTHER_STACK, precision=mg.PREC_FP64))
+    ctx.set_stacks(stacks)
+    h = st.StackHierarchy(A, 7)
+    for l in range(h.num_levels - 1):
+        m = h.stencils[l].shape[1]
+        best = min(stacks, key=lambda q: abs(math.log2(q + 1) - math.log2(m + 1)))
+        w = stacks[best].copy()
+        w[4:] /= h.stencils[l][4].mean()
+        h.set_stack(l, w)
+    f = mg_inputs.rhs_uniform(n, 5)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    ctx.vcycle([_dev(f)], [u])
+    ref = h.vcycle(f)
+    assert np.abs(u.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_committed_stacks_solve_the_problem_they_were_trained_for(mg):
+    # theta = 0, eps = 0.01 (the paper's first test set): mixed precision to 1e-8, the true FP64
+    # residual by the oracle, at least 5x fewer cycles than damped Jacobi
+    stacks = _committed(mg, "stack_theta0_eps0.01.json")
+    n = 255
+    A = mg.stencil_q1_rotated(n, 0.0, 0.01)
+    f = mg_inputs.rhs_uniform(n, 0)
+    iters = {}
+    for name, sm in (("stack", mg.SMOOTHER_STACK), ("jacobi", mg.SMOOTHER_JACOBI)):
+        ctx = mg.Context([A], mg.Options(smoother=sm))
+        if sm == mg.SMOOTHER_STACK:
+            ctx.set_stacks(stacks)
+        res = ctx.solve([_dev(f)], 1e-8, 5000)
+        assert res.status[0] == 0
+        r = f - ora.matvec(A.cpu().numpy(), res.u[0].cpu().numpy())
+        assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(f)
+        iters[name] = int(res.iters[0])
+    assert 5 * iters["stack"] < iters["jacobi"], iters

@@ -403,8 +403,7 @@ def stack_block(args, A, f, n, theta, eps, coarsest):
     trained per problem by Algorithm 2; weights/stack_*.json) on this problem,
     if a committed training run matches it: iterations and time to the
     tolerance, and the stack kernel's own rate on the finest level (its
-    algorithmic traffic: x with the 5-node halo of a 64 x 16 tile, e read and
-    written, FP32)."""
+    algorithmic traffic: x read once, e read and written, FP32)."""
     import glob
 
     import torch
@@ -429,7 +428,7 @@ def stack_block(args, A, f, n, theta, eps, coarsest):
     ms = (time.perf_counter() - t0) * 1e3
     k = ctx.time_kernels(args.kernel_reps)
     ctx.close()
-    tile_bytes = 4.0 * (74 * 26) / (64 * 16) + 8.0  # per node: staged x, e read and written
+    tile_bytes = 12.0  # algorithmic, per node: x read once, e read and written (FP32)
     bytes_per_launch = tile_bytes * n * n
     out = {"weights": os.path.relpath(path, os.path.dirname(os.path.abspath(__file__))),
            "trained_sizes": sorted(stacks), "iters": int(res.iters[0]), "status": int(res.status[0]),

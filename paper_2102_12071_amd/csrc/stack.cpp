@@ -126,7 +126,8 @@ mg_status mg_stack_apply(int32_t n, int32_t count, const double *phi, const doub
     if (!phi || !x || !y) return set_error(MG_ERR_ARG, "null pointer");
     if (accumulate != 0 && accumulate != 1) return set_error(MG_ERR_ARG, "accumulate must be 0 or 1");
     const int64_t nn = (int64_t)n * n;
-    if (x < y + nn * count && y < x + nn * count) return set_error(MG_ERR_ARG, "x and y overlap");
+    const uintptr_t xa = (uintptr_t)x, ya = (uintptr_t)y, len = (uintptr_t)(nn * count) * sizeof(double);
+    if (xa < ya + len && ya < xa + len) return set_error(MG_ERR_ARG, "x and y overlap");
     MG_TRY(require_device());
     if (count == 0) return MG_OK;
     launch_stack_vecs(x, y, nn, phi, n, n, count, accumulate != 0, nullptr, (hipStream_t)stream);

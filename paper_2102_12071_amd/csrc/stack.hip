@@ -9,8 +9,9 @@
 // nodes in LDS, runs the five composed layers there (each on a region one node
 // narrower per side than the last, ping-ponging between two LDS buffers) and
 // adds f6(x) from the staged x.  HBM traffic per node is x once plus the halo
-// (1.8x for this tile) and y read (when accumulating) and written; the 77
-// multiply-adds per node come from LDS.
+// (1.9x for this tile, mostly from L2) and y read (when accumulating) and written; the 77
+// multiply-adds per node read their operands from LDS through three-row
+// register windows.
 //
 // Training (FP64, Algorithm 2): one layer per launch over a batch of vectors,
 // and the weight gradients as per-block sums in a fixed order.
@@ -24,6 +25,7 @@ constexpr int kTX = 64, kTY = 16, kHalo = 5;
 constexpr int kLW = kTX + 2 * kHalo, kLH = kTY + 2 * kHalo;  // staged region 74 x 26
 constexpr int kLN = kLW * kLH;
 constexpr int kST = 256;
+constexpr int kRun = 8;  // rows per thread in a layer's column walk
 
 __device__ inline bool on_grid(int n, int i, int j) { return i >= 0 && i < n && j >= 0 && j < n; }
 
@@ -41,42 +43,76 @@ __device__ void stack_tile(const T MG_G *x, T MG_G *y, const T MG_G *w, int n, i
     __syncthreads();
     const T *src = b0;
     T *dst = b1;
-    // unrolled: each layer's region width is a compile-time constant, so the
-    // flat index splits into (xx, yy) without a division instruction sequence
+    // Each layer: a thread walks down one column of the region for kRun rows,
+    // keeping three rows of the previous layer in registers (3 LDS reads per
+    // output instead of 9).  Unrolled over layers, so every region size is a
+    // compile-time constant.
 #pragma unroll
     for (int layer = 0; layer < 5; ++layer) {
         const int m = layer + 1;  // this layer is valid on [m, kLW - m) x [m, kLH - m)
-        const int rw = kLW - 2 * m, rh = kLH - 2 * m;
+        const int rw = kLW - 2 * m, rh = kLH - 2 * m, chunks = (rh + kRun - 1) / kRun;
         T k[9];
 #pragma unroll
         for (int t = 0; t < 9; ++t) k[t] = w[layer * 9 + t];
-        for (int q = tid; q < rw * rh; q += kST) {
-            const int xx = m + q % rw, yy = m + q / rw;
-            T v = (T)0;
-            if (on_grid(n, i0 + xx, j0 + yy)) {
-                const T *c = src + (yy - 1) * kLW + (xx - 1);  // reads [m - 1, kLW - m], valid for the last layer
-                v = k[0] * c[0] + k[1] * c[1] + k[2] * c[2] + k[3] * c[kLW] + k[4] * c[kLW + 1] +
-                    k[5] * c[kLW + 2] + k[6] * c[2 * kLW] + k[7] * c[2 * kLW + 1] + k[8] * c[2 * kLW + 2];
+        for (int q = tid; q < rw * chunks; q += kST) {
+            const int xx = m + q % rw, y0 = m + (q / rw) * kRun;
+            const int y1 = min(y0 + kRun, kLH - m);
+            const bool col_in = i0 + xx >= 0 && i0 + xx < n;
+            // rows y0 - 1 and y0 of the previous layer, valid on [m - 1, kLW - m]
+            const T *c = src + (y0 - 1) * kLW + (xx - 1);
+            T a0 = c[0], a1 = c[1], a2 = c[2];
+            T b0r = c[kLW], b1r = c[kLW + 1], b2r = c[kLW + 2];
+#pragma unroll
+            for (int r = 0; r < kRun; ++r) {
+                const int yy = y0 + r;
+                if (yy < y1) {
+                    const T *cn = src + (yy + 1) * kLW + (xx - 1);
+                    const T c0 = cn[0], c1 = cn[1], c2 = cn[2];
+                    const T v = k[0] * a0 + k[1] * a1 + k[2] * a2 + k[3] * b0r + k[4] * b1r + k[5] * b2r +
+                                k[6] * c0 + k[7] * c1 + k[8] * c2;
+                    const int gj = j0 + yy;
+                    dst[yy * kLW + xx] = col_in && gj >= 0 && gj < n ? v : (T)0;
+                    a0 = b0r, a1 = b1r, a2 = b2r;
+                    b0r = c0, b1r = c1, b2r = c2;
+                }
             }
-            dst[yy * kLW + xx] = v;
         }
         __syncthreads();
         src = dst;
         dst = dst == b1 ? b2 : b1;
     }
+    // output: src holds f5(..f1(x)) on the tile; add f6(x) from the staged x, same column walk
     T k6[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) k6[t] = w[45 + t];
-    for (int q = tid; q < kTX * kTY; q += kST) {
-        const int xx = kHalo + q % kTX, yy = kHalo + q / kTX;
-        const int gi = i0 + xx, gj = j0 + yy;  // >= 0 on the output tile
-        if (gi >= n || gj >= n) continue;
-        const T *c = b0 + (yy - 1) * kLW + (xx - 1);
-        const T v = src[yy * kLW + xx] + k6[0] * c[0] + k6[1] * c[1] + k6[2] * c[2] + k6[3] * c[kLW] +
-                    k6[4] * c[kLW + 1] + k6[5] * c[kLW + 2] + k6[6] * c[2 * kLW] + k6[7] * c[2 * kLW + 1] +
-                    k6[8] * c[2 * kLW + 2];
-        const int64_t p = (int64_t)gj * P + gi;
-        y[p] = acc ? y[p] + v : v;
+    constexpr int kOutChunks = (kTY + kRun - 1) / kRun;
+    for (int q = tid; q < kTX * kOutChunks; q += kST) {
+        const int xx = kHalo + q % kTX, y0 = kHalo + (q / kTX) * kRun;
+        const int gi = i0 + xx;  // >= 0 on the output tile
+        if (gi >= n) continue;
+        // the run's old y values first: loads issued together, not each behind the previous store
+        T yv[kRun];
+#pragma unroll
+        for (int r = 0; r < kRun; ++r) {
+            const int gj = j0 + y0 + r;
+            yv[r] = acc && y0 + r < kHalo + kTY && gj < n ? y[(int64_t)gj * P + gi] : (T)0;
+        }
+        const T *c = b0 + (y0 - 1) * kLW + (xx - 1);
+        T a0 = c[0], a1 = c[1], a2 = c[2];
+        T b0r = c[kLW], b1r = c[kLW + 1], b2r = c[kLW + 2];
+#pragma unroll
+        for (int r = 0; r < kRun; ++r) {
+            const int yy = y0 + r, gj = j0 + yy;
+            if (yy < kHalo + kTY && gj < n) {
+                const T *cn = b0 + (yy + 1) * kLW + (xx - 1);
+                const T c0 = cn[0], c1 = cn[1], c2 = cn[2];
+                const T v = src[yy * kLW + xx] + k6[0] * a0 + k6[1] * a1 + k6[2] * a2 + k6[3] * b0r +
+                            k6[4] * b1r + k6[5] * b2r + k6[6] * c0 + k6[7] * c1 + k6[8] * c2;
+                y[(int64_t)gj * P + gi] = yv[r] + v;
+                a0 = b0r, a1 = b1r, a2 = b2r;
+                b0r = c0, b1r = c1, b2r = c2;
+            }
+        }
     }
 }
 

@@ -15,6 +15,9 @@ i + kx - 1).  The stack is linear, so the multigrid iteration stays linear.
 The V(1,1) cycle with these smoothers is written here in numpy on top of the
 oracle's stencils, matvec and transfers (Algorithm 1 in correction form, a
 dense solve on the coarsest level); a level given None takes damped Jacobi.
+A level may post-smooth with a different stack; with H^T after the coarse
+correction ("symmetric") the cycle's error propagation is self-adjoint in the
+A inner product.
 
 The Algorithm 2 loss ||Phi(u0, f, k) - u*||_2 of the trained level uses the
 same forward steps as the per-point form (r = f - A u, a = H r, s = r - A a,
@@ -109,19 +112,24 @@ class StackHierarchy:
         self.stencils = [h.stencil(l) for l in range(h.num_levels)]
         self.num_levels = len(self.stencils)
         self.smoothers = [None] * (self.num_levels - 1)
+        self.post = [None] * (self.num_levels - 1)
         self._coarse = stencil_to_dense(self.stencils[-1])
 
-    def set_stack(self, level: int, phi) -> None:
+    def set_stack(self, level: int, phi, post=None) -> None:
+        """The level's stack before the coarse correction (phi) and after it
+        (post; default phi)."""
         if not 0 <= level < self.num_levels - 1:
             raise ValueError("bad level")
         self.smoothers[level] = None if phi is None else _weights(phi).copy()
+        self.post[level] = None if phi is None else _weights(phi if post is None else post).copy()
 
-    def _smooth(self, level: int, r, e):
+    def _smooth(self, level: int, r, e, after: bool = False):
         """e + H (r - A e) (damped Jacobi where no stack is set)."""
         A = self.stencils[level]
         if self.smoothers[level] is None:
             return smooth_jacobi(A, r, e)
-        return e + stack_apply(self.smoothers[level], r - matvec(A, e))
+        w = self.post[level] if after else self.smoothers[level]
+        return e + stack_apply(w, r - matvec(A, e))
 
     def vcycle(self, r, level: int = 0) -> np.ndarray:
         """e = V(r) from level (Algorithm 1, correction form, one sweep before
@@ -134,7 +142,7 @@ class StackHierarchy:
         e = self._smooth(level, r, np.zeros_like(r))
         s = r - matvec(A, e)
         e = prolong_add(self.vcycle(restrict_fw(s), level + 1), e)
-        return self._smooth(level, r, e)
+        return self._smooth(level, r, e, after=True)
 
     def solve(self, f, tol: float, maxit: int):
         """u = 0; while ||f - A u|| > tol ||f|| and k < maxit: u += V(f - A u).
@@ -163,9 +171,11 @@ def _coarse_cycle(hc: StackHierarchy, x):
     return prolong_add(hc.vcycle(restrict_fw(x)), np.zeros((n, n)))
 
 
-def alpha_forward(A, phi, hc: StackHierarchy, f, u0, k) -> np.ndarray:
+def alpha_forward(A, phi, hc: StackHierarchy, f, u0, k, symmetric: bool = False) -> np.ndarray:
     """u_k of Algorithm 2's forward recursion with the stack smoother on the
-    trained level and one cycle of hc (the next coarser level) as Psi_c."""
+    trained level and one cycle of hc (the next coarser level) as Psi_c
+    (symmetric: H^T after the coarse correction)."""
+    post = stack_transpose(phi) if symmetric else phi
     u = np.array(u0, dtype=np.float64)
     for _ in range(k):
         r = f - matvec(A, u)
@@ -173,14 +183,22 @@ def alpha_forward(A, phi, hc: StackHierarchy, f, u0, k) -> np.ndarray:
         s = r - matvec(A, a)
         t = a + _coarse_cycle(hc, s)
         q = r - matvec(A, t)
-        u = u + t + stack_apply(phi, q)
+        u = u + t + stack_apply(post, q)
     return u
 
 
-def alpha_loss_and_grad(A, phi, hc: StackHierarchy, f, u0, u_star, k):
+def _transpose_index(j: int) -> int:
+    """The index in stack_transpose(w) of weight j of w (a permutation)."""
+    L, t = j // 9, j % 9
+    return (4 - L if L < 5 else 5) * 9 + 8 - t
+
+
+def alpha_loss_and_grad(A, phi, hc: StackHierarchy, f, u0, u_star, k, symmetric: bool = False):
     """||u_k - u*||_2 and its gradient with respect to the 54 weights, by
-    forward-mode differentiation of the recursion."""
+    forward-mode differentiation of the recursion (symmetric: H^T after the
+    coarse correction, whose weights are a permutation of phi's)."""
     w = _weights(phi)
+    wT = stack_transpose(w)
     n = A.shape[1]
     u = np.array(u0, dtype=np.float64)
     du = np.zeros((NWEIGHTS, n, n))  # du[j] = d u / d weight j
@@ -191,6 +209,15 @@ def alpha_loss_and_grad(A, phi, hc: StackHierarchy, f, u0, u_star, k):
         dy = stack_apply(w, dx)
         for j in range(NWEIGHTS):
             dy[j] += stack_derivative(w, x, j // 9, j % 9)
+        return y, dy
+
+    def HT_and_tangent(x, dx):
+        """H^T x and its tangent: weight j of phi is weight _transpose_index(j) of H^T's stack."""
+        y = stack_apply(wT, x)
+        dy = stack_apply(wT, dx)
+        for j in range(NWEIGHTS):
+            i = _transpose_index(j)
+            dy[j] += stack_derivative(wT, x, i // 9, i % 9)
         return y, dy
 
     def A_batch(X):
@@ -209,7 +236,7 @@ def alpha_loss_and_grad(A, phi, hc: StackHierarchy, f, u0, u_star, k):
         dt = da + coarse_batch(ds)
         q = r - matvec(A, t)
         dq = dr - A_batch(dt)
-        hq, dhq = H_and_tangent(q, dq)
+        hq, dhq = (HT_and_tangent if symmetric else H_and_tangent)(q, dq)
         u = u + t + hq
         du = du + dt + dhq
     d = u - np.asarray(u_star, dtype=np.float64)
@@ -218,13 +245,13 @@ def alpha_loss_and_grad(A, phi, hc: StackHierarchy, f, u0, u_star, k):
     return L, g
 
 
-def batch_loss_and_grad(A, phi, hc: StackHierarchy, f_list, u0_list, ustar_list, ks):
+def batch_loss_and_grad(A, phi, hc: StackHierarchy, f_list, u0_list, ustar_list, ks, symmetric: bool = False):
     """Mean of the loss over a batch of instances of one problem (the stack's
     weights are shared) and its gradient."""
     B = len(ks)
     total, grad = 0.0, np.zeros(NWEIGHTS)
     for f, u0, us, k in zip(f_list, u0_list, ustar_list, ks):
-        L, g = alpha_loss_and_grad(A, phi, hc, f, u0, us, k)
+        L, g = alpha_loss_and_grad(A, phi, hc, f, u0, us, k, symmetric)
         total += L / B
         grad += g / B
     return total, grad

@@ -210,3 +210,68 @@ def test_damped_jacobi_stack_loss_on_a_sine_mode():
     E = S @ (np.eye(n * n) - P @ np.linalg.solve(R @ Am @ P, R @ Am)) @ S
     L, _ = st.alpha_loss_and_grad(A, w, hc, np.zeros((n, n)), u0, np.zeros((n, n)), 1)
     assert L == pytest.approx(np.linalg.norm(E @ u0.reshape(-1)), rel=1e-12)
+
+
+def _cycle_matrix(h, n):
+    """B with V(r) = B r (the cycle is linear in r)."""
+    return _dense(lambda v: h.vcycle(v), n)
+
+
+def test_symmetric_cycle_is_self_adjoint_in_A():
+    # H before and H^T after the coarse correction on every level: E = I - B A satisfies
+    # A E = E^T A (B symmetric); with H after as well it does not
+    n = 15
+    A = ora.stencil_q1_rotated(n, 0.7, 0.05)
+    Am = stencil_field_to_csr(A).toarray()
+    sym, plain = st.StackHierarchy(A, 3), st.StackHierarchy(A, 3)
+    for l in range(sym.num_levels - 1):
+        w = _scaled_stack(20 + l, sym.stencils[l])
+        sym.set_stack(l, w, post=st.stack_transpose(w))
+        plain.set_stack(l, w)
+    B = _cycle_matrix(sym, n)
+    assert np.abs(B - B.T).max() <= 1e-13 * np.abs(B).max()
+    E = np.eye(n * n) - B @ Am
+    assert np.abs(Am @ E - E.T @ Am).max() <= 1e-12 * np.abs(Am).max()
+    Bp = _cycle_matrix(plain, n)
+    assert np.abs(Bp - Bp.T).max() > 1e-3 * np.abs(Bp).max()
+
+
+def _scaled_stack(seed, A):
+    w = mg_inputs.stack_random(seed)
+    w[4:] /= A[4].flat[0]
+    return w
+
+
+def test_symmetric_alpha_forward_is_the_cycle_iteration():
+    A, w, hc, f, u0, _ = _stage(seed=2)
+    for l in range(hc.num_levels - 1):
+        hc.set_stack(l, hc.smoothers[l], post=st.stack_transpose(hc.smoothers[l]))
+    h = st.StackHierarchy(A, 3)
+    h.set_stack(0, w, post=st.stack_transpose(w))
+    for l in range(hc.num_levels - 1):
+        h.set_stack(l + 1, hc.smoothers[l], post=hc.post[l])
+    u = u0.copy()
+    for _ in range(3):
+        u = u + h.vcycle(f - ora.matvec(A, u))
+    got = st.alpha_forward(A, w, hc, f, u0, 3, symmetric=True)
+    assert np.abs(got - u).max() <= 1e-12 * np.abs(u).max()
+
+
+def test_symmetric_alpha_gradient_central_differences():
+    A, w, hc, f, u0, us = _stage(seed=8)
+    for l in range(hc.num_levels - 1):
+        hc.set_stack(l, hc.smoothers[l], post=st.stack_transpose(hc.smoothers[l]))
+    fl, ul, sl, ks = [f, f.T.copy()], [u0, u0[::-1].copy()], [us, us], [2, 3]
+    L, g = st.batch_loss_and_grad(A, w, hc, fl, ul, sl, ks, symmetric=True)
+    h = 1e-6
+    fd = np.zeros(st.NWEIGHTS)
+    for j in range(st.NWEIGHTS):
+        wp, wm = w.copy().reshape(-1), w.copy().reshape(-1)
+        wp[j] += h
+        wm[j] -= h
+        Lp, _ = st.batch_loss_and_grad(A, wp, hc, fl, ul, sl, ks, symmetric=True)
+        Lm, _ = st.batch_loss_and_grad(A, wm, hc, fl, ul, sl, ks, symmetric=True)
+        fd[j] = (Lp - Lm) / (2 * h)
+    assert np.abs(fd - g).max() <= 1e-6 * np.abs(g).max()
+    L0, _ = st.batch_loss_and_grad(A, w, hc, fl, ul, sl, ks, symmetric=False)
+    assert abs(L - L0) > 1e-6 * L  # the post-smoother really differs

@@ -401,44 +401,46 @@ def sweeps_block(args, A, f, n, cnn_s, coarsest):
 def stack_block(args, A, f, n, theta, eps, coarsest):
     """The paper's constant-coefficient alpha-CNN (H = f5(..f1) + f6 per level,
     trained per problem by Algorithm 2; weights/stack_*.json) on this problem,
-    if a committed training run matches it: iterations and time to the
-    tolerance, and the stack kernel's own rate on the finest level (its
-    algorithmic traffic: x read once, e read and written, FP32)."""
+    for every committed training run that matches it (Algorithm 2's cycle, or
+    the symmetric one with H^T after the coarse correction): iterations and
+    time to the tolerance, and the stack kernel's own rate on the finest level
+    (its algorithmic traffic: x read once, e read and written, FP32)."""
     import glob
 
     import torch
 
     from paper_2102_12071_amd import mgcnn
-    from paper_2102_12071_amd.stack_train import load_stacks
-    path = None
+    from paper_2102_12071_amd.stack_train import load_stack_run
+    runs = []
     for p in sorted(glob.glob(os.path.join(os.path.dirname(WEIGHTS), "stack_*.json"))):
         with open(p) as fh:
             prob = json.load(fh).get("problem", {})
         if abs(prob.get("theta", -1) - theta) < 1e-9 and abs(prob.get("eps", -1) - eps) < 1e-12 * max(eps, 1):
-            path = p
-    if path is None:
+            runs.append(p)
+    if not runs:
         return None
-    stacks = load_stacks(path)
-    ctx = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_STACK, coarsest_n=coarsest))
-    ctx.set_stacks(stacks)
-    ctx.solve([f], args.tol, args.maxit)  # warm-up (graph capture)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = ctx.solve([f], args.tol, args.maxit)
-    ms = (time.perf_counter() - t0) * 1e3
-    k = ctx.time_kernels(args.kernel_reps)
-    ctx.close()
-    tile_bytes = 12.0  # algorithmic, per node: x read once, e read and written (FP32)
-    bytes_per_launch = tile_bytes * n * n
-    out = {"weights": os.path.relpath(path, os.path.dirname(os.path.abspath(__file__))),
-           "trained_sizes": sorted(stacks), "iters": int(res.iters[0]), "status": int(res.status[0]),
-           "relres": float(res.relres[0]), "solve_ms": ms,
-           "ms_per_iteration": float(res.ms) / max(int(res.iters[0]), 1),
-           "kernel": {"name": "k_stack_cycle (accumulating)", "ms": k["smooth_apply"],
-                      "algorithmic_bytes": bytes_per_launch,
-                      "achieved_gbs": bytes_per_launch / (k["smooth_apply"] * 1e-3) / 1e9}}
-    log(f"alpha-CNN stack ({os.path.basename(path)}): {out['iters']} iterations, status {out['status']}, "
-        f"{ms:.1f} ms; stack kernel {k['smooth_apply'] * 1e3:.1f} us")
+    out = []
+    for path in runs:
+        stacks, symmetric = load_stack_run(path)
+        ctx = mgcnn.Context([A], mgcnn.Options(smoother=mgcnn.SMOOTHER_STACK, coarsest_n=coarsest))
+        ctx.set_stacks(stacks, symmetric=symmetric)
+        ctx.solve([f], args.tol, args.maxit)  # warm-up (graph capture)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.solve([f], args.tol, args.maxit)
+        ms = (time.perf_counter() - t0) * 1e3
+        k = ctx.time_kernels(args.kernel_reps)
+        ctx.close()
+        bytes_per_launch = 12.0 * n * n  # algorithmic, per node: x read once, e read and written (FP32)
+        out.append({"weights": os.path.relpath(path, os.path.dirname(os.path.abspath(__file__))),
+                    "symmetric": symmetric, "trained_sizes": sorted(stacks), "iters": int(res.iters[0]),
+                    "status": int(res.status[0]), "relres": float(res.relres[0]), "solve_ms": ms,
+                    "ms_per_iteration": float(res.ms) / max(int(res.iters[0]), 1),
+                    "kernel": {"name": "k_stack_cycle (accumulating, after the coarse correction)",
+                               "ms": k["smooth_apply"], "algorithmic_bytes": bytes_per_launch,
+                               "achieved_gbs": bytes_per_launch / (k["smooth_apply"] * 1e-3) / 1e9}})
+        log(f"alpha-CNN stack ({os.path.basename(path)}): {out[-1]['iters']} iterations, "
+            f"status {out[-1]['status']}, {ms:.1f} ms; stack kernel {k['smooth_apply'] * 1e3:.1f} us")
     return out
 
 

@@ -370,6 +370,15 @@ mg_status mg_alpha_step(mg_ctx top, mg_ctx coarse, mg_ctx coarse_t, mg_net net, 
  * Synchronises. */
 mg_status mg_set_stack(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose);
 
+/* Replaces the stack a level applies after the coarse correction (mg_set_stack
+ * installs the same weights before and after, as Algorithm 2 does).  With the
+ * level's own weights and transpose = 1, the post-smoother is H^T and the
+ * cycle's error propagation is self-adjoint in the A inner product (the
+ * symmetric V-cycle): the A-norm of one cycle then equals its spectral radius,
+ * so a convergent coarse cycle cannot amplify errors once nested inside a
+ * finer one.  MG_ERR_STATE before mg_set_stack on that level.  Synchronises. */
+mg_status mg_set_stack_post(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose);
+
 /* y_c (+)= H x_c for c < count: x, y device [count][n][n] FP64 (must not
  * overlap), phi device [54] FP64, accumulate 0 (y = H x) or 1 (y += H x).
  * Asynchronous on stream. */
@@ -385,7 +394,10 @@ mg_status mg_stack_apply(int32_t n, int32_t count, const double *phi, const doub
  * with H; its gradient with respect to the 54 weights by the adjoint of
  * those cycles (FP64); and, if o->apply_update, an FP64 Adam step (o's lr,
  * beta1, beta2, adam_eps; t the 1-based step number for the bias correction)
- * on phi with the moments adam_m, adam_v.
+ * on phi with the moments adam_m, adam_v.  symmetric = 1: H^T after the
+ * coarse correction on the trained level (the symmetric cycle of
+ * mg_set_stack_post); its coarse hierarchy is then symmetric too, and coarse
+ * may be passed as coarse_t.
  * top: FP64 context, every problem of the same n > coarsest_n (its smoother
  *   setting is not used).
  * coarse, coarse_t: FP64 contexts of the level-1 stencils of top's problems
@@ -399,8 +411,8 @@ mg_status mg_stack_apply(int32_t n, int32_t count, const double *phi, const doub
  *   or NULL, dL/dphi.
  * MG_ERR_DIVERGED (weights unchanged) if a norm is not finite.  Synchronises. */
 mg_status mg_stack_alpha_step(mg_ctx top, mg_ctx coarse, mg_ctx coarse_t, double *phi, double *adam_m,
-                              double *adam_v, int32_t t, const mg_alpha_batch *b, const mg_train_opts *o,
-                              double *loss, double *losses, double *grad);
+                              double *adam_v, int32_t t, int32_t symmetric, const mg_alpha_batch *b,
+                              const mg_train_opts *o, double *loss, double *losses, double *grad);
 
 /* ------------------------------------------------------------------------ */
 const char *mg_status_str(mg_status s);

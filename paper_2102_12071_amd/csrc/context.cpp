@@ -170,9 +170,10 @@ void enqueue_vcycle(mg_ctx_s &c, hipStream_t st)
 {
     const bool cnn = c.opt.smoother == MG_SMOOTHER_CNN, stack = c.opt.smoother == MG_SMOOTHER_STACK;
     const double w = c.opt.omega;
-    auto smooth = [&](const CycleSlot<T> *s, const SizeClass &k, bool first) {
+    auto smooth = [&](const CycleSlot<T> *s, const SizeClass &k, bool first, bool post = false) {
         if (stack)
-            launch_stack_cycle<T>(s, k.nrun, k.n, first, c.d_state, st);
+            launch_stack_cycle<T>(s, k.nrun, k.n, first ? kStackFirst : post ? kStackPost : kStackPre, c.d_state,
+                                  st);
         else if (first)
             launch_smooth_first<T>(s, k.nrun, k.n, cnn, w, c.d_state, st);
         else
@@ -215,7 +216,7 @@ void enqueue_vcycle(mg_ctx_s &c, hipStream_t st)
         launch_prolong<T>(s, k.nrun, k.n, c.d_state, st);
         for (int q = 0; q < c.opt.nu_post; ++q) {
             launch_residual<T>(s, k.nrun, k.n, c.d_state, st);
-            smooth(s, k, false);
+            smooth(s, k, false, true);
         }
     }
 }
@@ -375,7 +376,7 @@ mg_status setup_impl(mg_ctx_s &c, const mg_problem *probs, hipStream_t user)
             ++l;
             if (m == c.opt.coarsest_n) break;
             MG_TRY(c.arena.alloc(&L.H, kSmoother * v * hsize(c)));
-            if (c.opt.smoother == MG_SMOOTHER_STACK) MG_TRY(c.arena.alloc(&L.phi, kStackWeights * tsize(c)));
+            if (c.opt.smoother == MG_SMOOTHER_STACK) MG_TRY(c.arena.alloc(&L.phi, 2 * kStackWeights * tsize(c)));
             MG_TRY(c.arena.alloc(&L.s, v * tsize(c)));
             m = (m - 1) / 2;
         }
@@ -858,7 +859,7 @@ void launch_timed(mg_ctx_s &c, int k, const SizeClass &cls, const SizeClass &oc,
         break;
     case 5:
         if (c.opt.smoother == MG_SMOOTHER_STACK)
-            launch_stack_cycle<T>(s, cls.nslots, n, true, c.d_state, st);
+            launch_stack_cycle<T>(s, cls.nslots, n, kStackFirst, c.d_state, st);
         else
             launch_smooth_first<T>(s, cls.nslots, n, cnn, w, c.d_state, st);
         break;
@@ -867,7 +868,7 @@ void launch_timed(mg_ctx_s &c, int k, const SizeClass &cls, const SizeClass &oc,
     case 8: launch_residual<T>(s, cls.nslots, n, c.d_state, st); break;
     case 9:
         if (c.opt.smoother == MG_SMOOTHER_STACK)
-            launch_stack_cycle<T>(s, cls.nslots, n, false, c.d_state, st);
+            launch_stack_cycle<T>(s, cls.nslots, n, kStackPost, c.d_state, st);
         else
             launch_smooth_apply<T>(s, cls.nslots, n, cnn, w, c.d_state, st);
         break;

@@ -64,7 +64,8 @@ struct LevelBuf {
     float *A32 = nullptr;
     void *H = nullptr;  // 25 planes: bf16 (mixed) or double (FP64)
     void *r = nullptr, *e = nullptr, *s = nullptr;
-    void *phi = nullptr;   // stack smoother: 54 weights (float or double), levels above the coarsest
+    void *phi = nullptr;   // stack smoother: 2 x 54 weights (float or double; before and after the coarse
+                           // correction), levels above the coarsest
     bool phi_set = false;  // mg_set_stack has installed them
 };
 

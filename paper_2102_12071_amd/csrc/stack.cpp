@@ -84,11 +84,8 @@ mg_status check_coarse(const mg_ctx_s &top, const mg_ctx_s &c, const char *name)
     return MG_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-mg_status mg_set_stack(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose)
+// Writes a level's weights: half 0 (before the coarse correction), 1 (after), or both (-1).
+mg_status set_stack_half(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose, int half)
 {
     clear_error();
     MG_TRY(ctx_check(ctx));
@@ -99,23 +96,41 @@ mg_status mg_set_stack(mg_ctx ctx, int32_t prob, int32_t level, const double *ph
         return set_error(MG_ERR_ARG, "level %d has no smoother (levels 0..%d)", level, pb.nlev - 2);
     if (!phi) return set_error(MG_ERR_ARG, "phi is null");
     if (transpose != 0 && transpose != 1) return set_error(MG_ERR_ARG, "transpose must be 0 or 1");
-    double w[kStackWeights];
-    for (int j = 0; j < kStackWeights; ++j) {
-        const int L = j / 9, t = j % 9;
-        w[j] = transpose ? phi[(L < 5 ? 4 - L : 5) * 9 + 8 - t] : phi[j];
-        if (!std::isfinite(w[j])) return set_error(MG_ERR_ARG, "weight %d is not finite", j);
-    }
     LevelBuf &L = pb.lev[level];
-    float wf[kStackWeights];
-    for (int j = 0; j < kStackWeights; ++j) wf[j] = (float)w[j];
+    if (half == 1 && !L.phi_set) return set_error(MG_ERR_STATE, "set the level's stack (mg_set_stack) first");
+    double w[2 * kStackWeights];
+    for (int j = 0; j < kStackWeights; ++j) {
+        const int Lr = j / 9, t = j % 9;
+        w[j] = transpose ? phi[(Lr < 5 ? 4 - Lr : 5) * 9 + 8 - t] : phi[j];
+        if (!std::isfinite(w[j])) return set_error(MG_ERR_ARG, "weight %d is not finite", j);
+        w[kStackWeights + j] = w[j];
+    }
+    float wf[2 * kStackWeights];
+    for (int j = 0; j < 2 * kStackWeights; ++j) wf[j] = (float)w[j];
     const bool fp64 = ctx->opt.precision == MG_PREC_FP64;
+    const size_t es = fp64 ? sizeof(double) : sizeof(float);
+    const int first = half == 1 ? kStackWeights : 0, count = half < 0 ? 2 * kStackWeights : kStackWeights;
     MG_TRY(ctx->join.enter());
     hipStream_t st = ctx->join.internal;
-    MG_HIP(hipMemcpyAsync(L.phi, fp64 ? (const void *)w : (const void *)wf,
-                          kStackWeights * (fp64 ? sizeof(double) : sizeof(float)), hipMemcpyHostToDevice, st));
+    MG_HIP(hipMemcpyAsync((char *)L.phi + first * es, fp64 ? (const void *)w : (const void *)wf, count * es,
+                          hipMemcpyHostToDevice, st));
     MG_HIP(hipStreamSynchronize(st));  // the host staging arrays end with this call
     L.phi_set = true;
     return ctx->join.leave();
+}
+
+}  // namespace
+
+extern "C" {
+
+mg_status mg_set_stack(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose)
+{
+    return set_stack_half(ctx, prob, level, phi, transpose, -1);
+}
+
+mg_status mg_set_stack_post(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose)
+{
+    return set_stack_half(ctx, prob, level, phi, transpose, 1);
 }
 
 mg_status mg_stack_apply(int32_t n, int32_t count, const double *phi, const double *x, double *y, int32_t accumulate,
@@ -136,11 +151,12 @@ mg_status mg_stack_apply(int32_t n, int32_t count, const double *phi, const doub
 }
 
 mg_status mg_stack_alpha_step(mg_ctx top, mg_ctx coarse, mg_ctx coarse_t, double *phi, double *adam_m,
-                              double *adam_v, int32_t t, const mg_alpha_batch *b, const mg_train_opts *o_in,
-                              double *loss, double *losses, double *grad)
+                              double *adam_v, int32_t t, int32_t symmetric, const mg_alpha_batch *b,
+                              const mg_train_opts *o_in, double *loss, double *losses, double *grad)
 {
     clear_error();
     if (!top || !coarse || !coarse_t || !phi || !b) return set_error(MG_ERR_ARG, "null argument");
+    if (symmetric != 0 && symmetric != 1) return set_error(MG_ERR_ARG, "symmetric must be 0 or 1");
     mg_train_opts o;
     if (o_in)
         o = *o_in;
@@ -257,7 +273,7 @@ mg_status mg_stack_alpha_step(mg_ctx top, mg_ctx coarse, mg_ctx coarse_t, double
         launch_al_prolong(w.probs, 0, B, n, P, vs, V(kA), V(kT), act, st);                     // t = a + P u_c
         launch_al_apply_A(w.probs, B, n, P, plane, vs, V(kT), r, -1.0, q, act, st);            // q = r - A t
         launch_al_axpy(B, n, P, vs, V(kU), 1.0, V(kT), V(kU), act, st);                         // u += t
-        H(q, V(kU), false, true, act);                                                          // u += H q
+        H(q, V(kU), symmetric != 0, true, act);                                                 // u += H' q
     }
     launch_al_dist(B, n, P, vs, V(kU), V(kUs), w.dist, st);
     std::vector<double> dist(B);
@@ -279,8 +295,11 @@ mg_status mg_stack_alpha_step(mg_ctx top, mg_ctx coarse, mg_ctx coarse_t, double
     for (int i = kmax - 1; i >= 0; --i) {
         const int *act = w.active + (size_t)i * B;
         const double *r = Rv(i), *q = Qv(i);
-        H(V(kLam), V(kDq), true, false, act);                                                   // dq = H^T lam
-        wgrad(V(kLam), q, act);                                                                  // post-smoothing H q
+        H(V(kLam), V(kDq), symmetric == 0, false, act);                                         // dq = H'^T lam
+        if (symmetric)
+            wgrad(q, V(kLam), act);  // post-smoothing H^T q: <lam, H^T q> = <q, H lam>
+        else
+            wgrad(V(kLam), q, act);  // post-smoothing H q
         launch_al_apply_A(w.probs, B, n, P, plane, vs, V(kDq), V(kLam), -1.0, V(kDt), act, st); // dt = lam - A dq
         launch_al_restrict(w.probs, 1, B, n, P, vs, V(kDt), act, st);                            // r_c = R dt
         coarse_cycle(*coarse_t);                                                                 // u_c = Psi_c^T(r_c)

@@ -116,14 +116,18 @@ __device__ void stack_tile(const T MG_G *x, T MG_G *y, const T MG_G *w, int n, i
     }
 }
 
+// mode 0: e = H r (first sweep); 1: e += H s before the coarse correction;
+// 2: e += H' s after it.  The slot's H points to the level's two weight sets
+// (before, after).
 template <typename T>
-__global__ void __launch_bounds__(kST) k_stack_cycle(const CycleSlot<T> *slots, const SolveState *state, int first)
+__global__ void __launch_bounds__(kST) k_stack_cycle(const CycleSlot<T> *slots, const SolveState *state, int mode)
 {
     __shared__ T b0[kLN], b1[kLN], b2[kLN];
     const TileId t = xcd_tile();
     const CycleSlot<T> s = slots[t.z];
     if (!state[s.prob].active) return;  // uniform over the workgroup
-    stack_tile<T>(first ? s.r : s.s, s.e, (const T MG_G *)s.H, s.n, s.P, !first, t.x, t.y, b0, b1, b2);
+    const T MG_G *w = (const T MG_G *)s.H + (mode == 2 ? kStackWeights : 0);
+    stack_tile<T>(mode == 0 ? s.r : s.s, s.e, w, s.n, s.P, mode != 0, t.x, t.y, b0, b1, b2);
 }
 
 __global__ void __launch_bounds__(kST) k_stack_vecs(const double *x, double *y, int64_t vs, const double *w, int n,
@@ -215,13 +219,13 @@ inline dim3 node_grid(int n, int count) { return dim3((unsigned)(((int64_t)n * n
 }  // namespace
 
 template <typename T>
-void launch_stack_cycle(const CycleSlot<T> *slots, int nslots, int n, bool first, const SolveState *state,
+void launch_stack_cycle(const CycleSlot<T> *slots, int nslots, int n, int mode, const SolveState *state,
                         hipStream_t st)
 {
-    k_stack_cycle<T><<<tile_grid(n, nslots), kST, 0, st>>>(slots, state, first ? 1 : 0);
+    k_stack_cycle<T><<<tile_grid(n, nslots), kST, 0, st>>>(slots, state, mode);
 }
-template void launch_stack_cycle<float>(const CycleSlot<float> *, int, int, bool, const SolveState *, hipStream_t);
-template void launch_stack_cycle<double>(const CycleSlot<double> *, int, int, bool, const SolveState *, hipStream_t);
+template void launch_stack_cycle<float>(const CycleSlot<float> *, int, int, int, const SolveState *, hipStream_t);
+template void launch_stack_cycle<double>(const CycleSlot<double> *, int, int, int, const SolveState *, hipStream_t);
 
 void launch_stack_vecs(const double *x, double *y, int64_t vs, const double *w, int n, int P, int count,
                        bool accumulate, const int *active, hipStream_t st)

@@ -8,10 +8,12 @@ namespace mg {
 constexpr int kStackWeights = 54;  // [6][3][3]: f1..f5 composed, then f6
 
 // The smoothing sweeps of the step-by-step cycle with the stack smoother: the
-// slot's H points to the level's 54 weights (type T).  first: e = H r; else
-// e += H s (s = r - A e from the residual kernel).
+// slot's H points to the level's two weight sets of 54 (type T), before and
+// after the coarse correction.  mode 0: e = H r (first sweep); 1: e += H s
+// (s = r - A e from the residual kernel); 2: e += H' s with the second set.
+enum { kStackFirst = 0, kStackPre = 1, kStackPost = 2 };
 template <typename T>
-void launch_stack_cycle(const CycleSlot<T> *slots, int nslots, int n, bool first, const SolveState *state,
+void launch_stack_cycle(const CycleSlot<T> *slots, int nslots, int n, int mode, const SolveState *state,
                         hipStream_t st);
 
 // y_z (+)= H x_z for z < count, vectors of pitch P at stride vs, one weight

@@ -92,9 +92,11 @@ SIGNATURES = {
                                 C.POINTER(TrainOpts), _c_dp, _c_dp, _c_fp]),
     "mg_set_smoother": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "mg_set_stack": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _c_dp, C.c_int32]),
+    "mg_set_stack_post": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _c_dp, C.c_int32]),
     "mg_stack_apply": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "mg_stack_alpha_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
-                                      C.c_int32, C.POINTER(AlphaBatch), C.POINTER(TrainOpts), _c_dp, _c_dp, _c_dp]),
+                                      C.c_int32, C.c_int32, C.POINTER(AlphaBatch), C.POINTER(TrainOpts), _c_dp,
+                                      _c_dp, _c_dp]),
     "mg_get_smoother": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "mg_vcycle": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "mg_solve": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_double, C.c_int32, _c_ip,
@@ -330,14 +332,18 @@ class Context:
         _check(load_library().mg_set_smoother(self._h, prob, level, _ptr(W)))
         torch.cuda.current_stream().synchronize()
 
-    def set_stack(self, prob: int, level: int, phi, transpose: bool = False) -> None:
-        """Installs a level's convolution-stack smoother (54 weights [6][3][3], f1..f5 then f6)."""
+    def set_stack(self, prob: int, level: int, phi, transpose: bool = False, symmetric: bool = False) -> None:
+        """Installs a level's convolution-stack smoother (54 weights [6][3][3], f1..f5 then f6);
+        symmetric: its transpose after the coarse correction."""
         w = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).reshape(-1))
         if w.size != STACK_WEIGHTS:
             raise ValueError("a stack has 54 weights")
-        _check(load_library().mg_set_stack(self._h, prob, level, w.ctypes.data_as(_c_dp), int(bool(transpose))))
+        lib = load_library()
+        _check(lib.mg_set_stack(self._h, prob, level, w.ctypes.data_as(_c_dp), int(bool(transpose))))
+        if symmetric:
+            _check(lib.mg_set_stack_post(self._h, prob, level, w.ctypes.data_as(_c_dp), int(not transpose)))
 
-    def set_stacks(self, stacks: dict, transpose: bool = False) -> None:
+    def set_stacks(self, stacks: dict, transpose: bool = False, symmetric: bool = False) -> None:
         """Every level above the coarsest of every problem from {trained size: weights normalised
         to a_C = 1}: a level of size m takes the stack of the nearest trained size on the log2
         scale (levels finer than every trained size: the finest one), scaled to the level's
@@ -349,7 +355,7 @@ class Context:
             for l in range(self.num_levels(p) - 1):
                 m = self.level_n(p, l)
                 best = min(sizes, key=lambda q: abs(math.log2(q + 1) - math.log2(m + 1)))
-                self.set_stack(p, l, stack_for_level(stacks[best], self.stencil(p, l)), transpose)
+                self.set_stack(p, l, stack_for_level(stacks[best], self.stencil(p, l)), transpose, symmetric)
 
     def infer(self, net: "Net", size: Optional[int] = None) -> None:
         """Network inference on every smoothing level, or (size given) on the levels of that size only."""
@@ -575,7 +581,7 @@ class StackAdam:
 
 def stack_alpha_step(top: Context, coarse: Context, coarse_t: Context, state: StackAdam, k: Sequence[int],
                      f: Sequence[torch.Tensor], u0: Sequence[torch.Tensor], u_star: Sequence[torch.Tensor],
-                     opts: Optional["TrainOptions"] = None) -> "AlphaResult":
+                     opts: Optional["TrainOptions"] = None, symmetric: bool = False) -> "AlphaResult":
     """One Algorithm 2 step of a stack smoother (mg_stack_alpha_step): loss, the 54-weight
     gradient (FP64), and an Adam update of state per opts."""
     opts = opts or TrainOptions(precision=0)
@@ -595,7 +601,8 @@ def stack_alpha_step(top: Context, coarse: Context, coarse_t: Context, state: St
     losses = np.zeros(B, dtype=np.float64)
     grad = np.zeros(STACK_WEIGHTS, dtype=np.float64)
     _check(load_library().mg_stack_alpha_step(top._h, coarse._h, coarse_t._h, _ptr(state.phi), _ptr(state.m),
-                                              _ptr(state.v), t, C.byref(batch), C.byref(o), C.byref(loss),
+                                              _ptr(state.v), t, int(bool(symmetric)), C.byref(batch), C.byref(o),
+                                              C.byref(loss),
                                               losses.ctypes.data_as(_c_dp), grad.ctypes.data_as(_c_dp)))
     if opts.apply_update:
         state.t = t

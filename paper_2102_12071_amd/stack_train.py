@@ -51,16 +51,23 @@ def _dev(x) -> torch.Tensor:
 
 def load_stacks(path: str) -> Dict[int, np.ndarray]:
     """{size: normalised weights [6][3][3]} of a saved training run."""
+    return load_stack_run(path)[0]
+
+
+def load_stack_run(path: str):
+    """The stacks of a saved training run and whether they post-smooth with H^T."""
     with open(path) as fh:
         d = json.load(fh)
-    return {int(k): np.array(v, dtype=np.float64).reshape(6, 3, 3) for k, v in d["stacks"].items()}
+    stacks = {int(k): np.array(v, dtype=np.float64).reshape(6, 3, 3) for k, v in d["stacks"].items()}
+    return stacks, bool(d.get("symmetric", False))
 
 
 class StackStage:
     """The instances of one stage and the three contexts of its step."""
 
     def __init__(self, n: int, theta: float, eps: float, Q: int, stacks: Dict[int, np.ndarray], seed: int,
-                 coarsest: int = 3, inject: Optional[list] = None):
+                 coarsest: int = 3, inject: Optional[list] = None, symmetric: bool = False):
+        self.symmetric = symmetric
         rng = np.random.default_rng([seed, n, 2])
         self.n = n
         A = mgcnn.stencil_q1_rotated(n, theta, eps)
@@ -84,20 +91,23 @@ class StackStage:
         else:
             opt = mgcnn.Options(precision=mgcnn.PREC_FP64, coarsest_n=coarsest, smoother=mgcnn.SMOOTHER_STACK)
             self.coarse = mgcnn.Context([A1] * self.Q, opt)
-            self.coarse.set_stacks(stacks)
-            self.coarse_t = mgcnn.Context([A1] * self.Q, opt)
-            self.coarse_t.set_stacks(stacks, transpose=True)
+            self.coarse.set_stacks(stacks, symmetric=symmetric)
+            if symmetric:  # a symmetric cycle is its own transpose
+                self.coarse_t = self.coarse
+            else:
+                self.coarse_t = mgcnn.Context([A1] * self.Q, opt)
+                self.coarse_t.set_stacks(stacks, transpose=True)
         self.rng = np.random.default_rng([seed, n, 1])
 
     def step(self, state: mgcnn.StackAdam, opts: mgcnn.TrainOptions, bmax: int):
         k = self.rng.integers(1, bmax + 1, self.Q)
         return mgcnn.stack_alpha_step(self.top, self.coarse, self.coarse_t, state, k, self.f, self.u0, self.u_star,
-                                      opts)
+                                      opts, self.symmetric)
 
     def monitor(self, state: mgcnn.StackAdam, k: int) -> float:
         o = mgcnn.TrainOptions(precision=0, apply_update=0)
         return mgcnn.stack_alpha_step(self.top, self.coarse, self.coarse_t, state, [k] * self.Q, self.f, self.u0,
-                                      self.u_star, o).loss
+                                      self.u_star, o, self.symmetric).loss
 
     def close(self):
         for c in {id(x): x for x in (self.top, self.coarse, self.coarse_t)}.values():
@@ -105,7 +115,7 @@ class StackStage:
 
 
 def worst_errors(n: int, theta: float, eps: float, Q: int, stacks: Dict[int, np.ndarray], seed: int,
-                 cycles: int = 30, coarsest: int = 3, rnd: int = 0):
+                 cycles: int = 30, coarsest: int = 3, rnd: int = 0, symmetric: bool = False):
     """The errors the current hierarchy of the stage reduces worst: cycles on
     A u = 0 from random u0, scaled to the norm of a N(0, 1) vector; and the
     largest per-cycle growth over the last third (a power-iteration estimate
@@ -114,7 +124,7 @@ def worst_errors(n: int, theta: float, eps: float, Q: int, stacks: Dict[int, np.
     A = mgcnn.stencil_q1_rotated(n, theta, eps)
     ctx = mgcnn.Context([A] * Q, mgcnn.Options(precision=mgcnn.PREC_FP64, coarsest_n=coarsest,
                                                smoother=mgcnn.SMOOTHER_STACK))
-    ctx.set_stacks(stacks)
+    ctx.set_stacks(stacks, symmetric=symmetric)
     u = [_dev(rng.normal(size=(n, n))) for _ in range(Q)]
     zero = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for _ in range(Q)]
     tail = max(cycles // 3, 1)
@@ -127,11 +137,26 @@ def worst_errors(n: int, theta: float, eps: float, Q: int, stacks: Dict[int, np.
     return [x * (n / max(float(x.norm()), 1e-300)) for x in u], growth
 
 
-def _run_stage(stage: StackStage, w0: np.ndarray, steps: int, lr: float, lr_final: float, bmax: int, log):
-    """Adam from the normalised weights w0; keeps the weights of the lowest monitored loss at k = bmax."""
+def _run_stage(stage: StackStage, w0: np.ndarray, steps: int, lr: float, lr_final: float, bmax: int, log,
+               growth_of=None):
+    """Adam from the normalised weights w0.  Keeps the weights of the lowest monitored loss at
+    k = bmax, or (growth_of given: normalised weights -> the stage hierarchy's estimated growth
+    per cycle) of the smallest growth, the loss breaking ties within 1 %."""
     state = mgcnn.StackAdam(mgcnn.stack_for_level(w0, stage.top.stencil(0, 0)))
-    best = (stage.monitor(state, bmax), state.phi.clone())
-    start = best[0]
+
+    def normalised(phi):
+        w = phi.cpu().numpy().reshape(6, 3, 3).copy()
+        w[4:] *= stage.a_centre
+        return w
+
+    def score(m, phi):
+        if growth_of is None:
+            return (m,)
+        return (round(growth_of(normalised(phi)), 2), m)
+
+    m0 = stage.monitor(state, bmax)
+    best = (score(m0, state.phi), m0, state.phi.clone())
+    start = m0
     every = max(steps // 10, 1)
     for s in range(steps):
         a = s / max(steps - 1, 1)
@@ -143,18 +168,18 @@ def _run_stage(stage: StackStage, w0: np.ndarray, steps: int, lr: float, lr_fina
             break
         if (s + 1) % every == 0 or s + 1 == steps:
             m = stage.monitor(state, bmax)
-            if m < best[0]:
-                best = (m, state.phi.clone())
-            log(f"  n={stage.n} step {s + 1}: monitor loss (k={bmax}) {m:.4e} (best {best[0]:.4e})")
-    w = best[1].cpu().numpy().reshape(6, 3, 3).copy()
-    w[4:] *= stage.a_centre  # back to the normalised form
-    return w, start, best[0]
+            sc = score(m, state.phi)
+            if sc < best[0]:
+                best = (sc, m, state.phi.clone())
+            log(f"  n={stage.n} step {s + 1}: monitor loss (k={bmax}) {m:.4e}, score {sc} (best {best[0]})")
+    return normalised(best[2]), start, best[1]
 
 
 def train(theta: float, eps: float, finest: int = 63, Q: int = 50, steps: int = 400, lr: float = 1e-3,
           lr_final: Optional[float] = None, bmax: int = 4, seed: int = 0, coarsest: int = 3,
           update_rounds: int = 0, update_steps: int = 200, warm: bool = False, max_points: int = 0,
-          steps_large: Optional[int] = None, large_n: int = 63, log=print):
+          steps_large: Optional[int] = None, large_n: int = 63, symmetric: bool = False, select: str = "loss",
+          log=print):
     """Stages from the coarsest up.  warm: a stage starts from the previous stage's weights (the
     operator is the same up to scale on every level) instead of the damped-Jacobi initialisation;
     max_points: at most that many grid points per stage (Q shrinks on large stages, at least 4);
@@ -166,14 +191,22 @@ def train(theta: float, eps: float, finest: int = 63, Q: int = 50, steps: int = 
     qn = lambda n: max(4, min(Q, max_points // (n * n))) if max_points else Q
     sizes = stage_sizes(finest, coarsest)
 
+    def growth_fn(n):
+        if select != "growth":
+            return None
+        return lambda w: worst_errors(n, theta, eps, min(4, qn(n)), {**{m: s for m, s in stacks.items() if m < n},
+                                                                     n: w}, seed, coarsest=coarsest,
+                                      symmetric=symmetric)[1]
+
     def stage(n, prev):
         t0 = time.time()
-        st = StackStage(n, theta, eps, qn(n), stacks, seed, coarsest)
+        st = StackStage(n, theta, eps, qn(n), stacks, seed, coarsest, symmetric=symmetric)
         w0 = stacks[prev] if (warm and prev is not None) else mg_inputs.stack_init(seed + n)
-        w, start, end = _run_stage(st, w0, steps if n <= large_n else steps_large, lr, lr_final, bmax, log)
+        w, start, end = _run_stage(st, w0, steps if n <= large_n else steps_large, lr, lr_final, bmax, log,
+                                   growth_fn(n))
         st.close()
         stacks[n] = w
-        _, growth = worst_errors(n, theta, eps, min(8, qn(n)), stacks, seed, coarsest=coarsest)
+        _, growth = worst_errors(n, theta, eps, min(8, qn(n)), stacks, seed, coarsest=coarsest, symmetric=symmetric)
         records.append({"stage_n": n, "instances": st.Q, "loss_start": start, "loss_end": end, "growth": growth,
                         "seconds": round(time.time() - t0, 3)})
         log(json.dumps(records[-1]))
@@ -187,13 +220,13 @@ def train(theta: float, eps: float, finest: int = 63, Q: int = 50, steps: int = 
         for n in [m for m in sizes if m <= large_n]:
             t0 = time.time()
             inject, before = worst_errors(n, theta, eps, max(2, qn(n) // 2), stacks, seed, coarsest=coarsest,
-                                          rnd=rnd + 1)
+                                          rnd=rnd + 1, symmetric=symmetric)
             lower = {m: s for m, s in stacks.items() if m < n}
-            st = StackStage(n, theta, eps, qn(n), lower, seed + 100 * (rnd + 1), coarsest, inject)
-            w, start, end = _run_stage(st, stacks[n], update_steps, lr_final, lr_final, bmax, log)
+            st = StackStage(n, theta, eps, qn(n), lower, seed + 100 * (rnd + 1), coarsest, inject, symmetric)
+            w, start, end = _run_stage(st, stacks[n], update_steps, lr_final, lr_final, bmax, log, growth_fn(n))
             st.close()
             stacks[n] = w
-            _, after = worst_errors(n, theta, eps, min(8, qn(n)), stacks, seed, coarsest=coarsest)
+            _, after = worst_errors(n, theta, eps, min(8, qn(n)), stacks, seed, coarsest=coarsest, symmetric=symmetric)
             records.append({"update_round": rnd, "stage_n": n, "growth_before": before, "growth_after": after,
                             "loss_start": start, "loss_end": end, "seconds": round(time.time() - t0, 3)})
             log(json.dumps(records[-1]))
@@ -204,7 +237,7 @@ def train(theta: float, eps: float, finest: int = 63, Q: int = 50, steps: int = 
 
 
 def evaluate(stacks: Dict[int, np.ndarray], n: int, theta: float, eps: float, tol: float = 1e-8,
-             maxit: int = 20000, coarsest: int = 7, seed: int = 0) -> dict:
+             maxit: int = 20000, coarsest: int = 7, seed: int = 0, symmetric: bool = False) -> dict:
     """Iterations and solve time to tol: V(1,1) with the stacks against damped Jacobi (mixed precision)."""
     A = mgcnn.stencil_q1_rotated(n, theta, eps)
     f = _dev(mg_inputs.rhs_uniform(n, seed))
@@ -212,7 +245,7 @@ def evaluate(stacks: Dict[int, np.ndarray], n: int, theta: float, eps: float, to
     for name, sm in (("alpha_stack", mgcnn.SMOOTHER_STACK), ("jacobi", mgcnn.SMOOTHER_JACOBI)):
         ctx = mgcnn.Context([A], mgcnn.Options(smoother=sm, coarsest_n=coarsest))
         if sm == mgcnn.SMOOTHER_STACK:
-            ctx.set_stacks(stacks)
+            ctx.set_stacks(stacks, symmetric=symmetric)
         ctx.solve([f], tol, maxit)  # warm-up (graph capture)
         r = ctx.solve([f], tol, maxit)
         out[name] = {"iters": int(r.iters[0]), "status": int(r.status[0]), "ms": round(r.ms, 3)}
@@ -237,6 +270,9 @@ def main():
     ap.add_argument("--max-points", type=int, default=0, help="grid points per stage (0: Q instances always)")
     ap.add_argument("--steps-large", type=int, default=None, help="steps of the stages above --large-n")
     ap.add_argument("--large-n", type=int, default=63)
+    ap.add_argument("--symmetric", action="store_true", help="post-smooth with H^T (the symmetric cycle)")
+    ap.add_argument("--select", choices=["loss", "growth"], default="loss",
+                    help="keep a stage's weights of the lowest monitored loss, or of the smallest growth estimate")
     ap.add_argument("--eval", type=int, nargs="*", default=[63, 255, 1023])
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
@@ -247,14 +283,16 @@ def main():
     mgcnn.load_library()
     stacks, records = train(a.theta, a.eps, a.finest, a.instances, a.steps, a.lr, a.lr_final, a.bmax, a.seed,
                             update_rounds=a.update_rounds, update_steps=a.update_steps, warm=a.warm,
-                            max_points=a.max_points, steps_large=a.steps_large, large_n=a.large_n, log=log)
+                            max_points=a.max_points, steps_large=a.steps_large, large_n=a.large_n,
+                            symmetric=a.symmetric, select=a.select, log=log)
     for n in a.eval:
-        r = evaluate(stacks, n, a.theta, a.eps)
+        r = evaluate(stacks, n, a.theta, a.eps, symmetric=a.symmetric)
         records.append({"eval": {"n": n, "theta": a.theta, "eps": a.eps}, **r})
         log(json.dumps(records[-1]))
     cmd = "python -m paper_2102_12071_amd.stack_train " + " ".join(sys.argv[1:])
     with open(a.out, "w") as fh:
         json.dump({"command": cmd, "device": "one MI355X", "problem": {"theta": a.theta, "eps": a.eps},
+                   "symmetric": a.symmetric, "select": a.select,
                    "note": "weights [6][3][3] per trained size, normalised to a_C = 1 (f5 and f6 times a_C); "
                            "eval: V(1,1) to 1e-8 over a 7 x 7 coarsest grid, mixed precision",
                    "stacks": {str(n): w.reshape(-1).tolist() for n, w in stacks.items()},

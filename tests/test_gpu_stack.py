@@ -241,3 +241,76 @@ def test_committed_stacks_solve_the_problem_they_were_trained_for(mg):
         assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(f)
         iters[name] = int(res.iters[0])
     assert 5 * iters["stack"] < iters["jacobi"], iters
+
+
+def test_symmetric_cycle_matches_oracle(mg):
+    # H before and H^T after the coarse correction on every level (mg_set_stack_post)
+    n = 127
+    A = ora.stencil_q1_rotated(n, 0.4, 0.05)
+    h = st.StackHierarchy(A, 7)
+    ctx = mg.Context([_dev(A)], mg.Options(smoother=mg.SMOOTHER_STACK, precision=mg.PREC_FP64))
+    for l in range(h.num_levels - 1):
+        w = _scaled(40 + l, h.stencils[l])
+        h.set_stack(l, w, post=st.stack_transpose(w))
+        ctx.set_stack(0, l, w, symmetric=True)
+    f = mg_inputs.rhs_uniform(n, 6)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    ctx.vcycle([_dev(f)], [u])
+    ref = h.vcycle(f)
+    assert np.abs(u.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("n,ks", [(15, [2, 3]), (31, [3, 1, 2])])
+def test_symmetric_alpha_step_matches_oracle(mg, n, ks):
+    B = len(ks)
+    A = ora.stencil_q1_rotated(n, 0.9, 0.03)
+    Ac = ora.galerkin(A)
+    hc = st.StackHierarchy(Ac, 3)
+    top = mg.Context([_dev(A)] * B, mg.Options(precision=mg.PREC_FP64, coarsest_n=3))
+    coarse = mg.Context([_dev(Ac)] * B, mg.Options(smoother=mg.SMOOTHER_STACK, precision=mg.PREC_FP64,
+                                                   coarsest_n=3))
+    for l in range(hc.num_levels - 1):
+        wl = _scaled(60 + l, hc.stencils[l])
+        hc.set_stack(l, wl, post=st.stack_transpose(wl))
+        for b in range(B):
+            coarse.set_stack(b, l, wl, symmetric=True)
+    rng = np.random.default_rng(n)
+    f = [mg_inputs.random_field((n, n), 70 + b) for b in range(B)]
+    u0 = [rng.normal(size=(n, n)) for _ in range(B)]
+    us = [mg_inputs.random_field((n, n), 80 + b) for b in range(B)]
+    w = _scaled(n + 1, A)
+    L_ref, g_ref = st.batch_loss_and_grad(A, w, hc, f, u0, us, ks, symmetric=True)
+    state = mg.StackAdam(w)
+    D = lambda xs: [_dev(x) for x in xs]
+    res = mg.stack_alpha_step(top, coarse, coarse, state, ks, D(f), D(u0), D(us),
+                              mg.TrainOptions(precision=0, apply_update=0), symmetric=True)
+    assert res.loss == pytest.approx(L_ref, rel=1e-12)
+    assert np.abs(res.grad - g_ref).max() <= 1e-10 * np.abs(g_ref).max()
+
+
+def test_set_stack_post_needs_the_stack_first(mg):
+    A = _dev(ora.stencil_q1_rotated(15, 0.5, 0.1))
+    ctx = mg.Context([A], mg.Options(smoother=mg.SMOOTHER_STACK, precision=mg.PREC_FP64))
+    w = np.zeros(54)
+    import ctypes as C
+    rc = mg.load_library().mg_set_stack_post(ctx._h, 0, 0, w.ctypes.data_as(C.POINTER(C.c_double)), 0)
+    assert rc == mg.MG_ERR_STATE
+
+
+def test_committed_symmetric_stacks_converge_where_the_plain_ones_diverge(mg):
+    # theta = pi/4, eps = 0.01: trained with H^T after the coarse correction, converging at n = 255
+    # with fewer cycles than damped Jacobi (the same training with H after it diverges there)
+    import os
+    from paper_2102_12071_amd.stack_train import load_stack_run
+    stacks, symmetric = load_stack_run(os.path.join(os.path.dirname(mg.__file__), "weights",
+                                                    "stack_theta0.785_eps0.01_symmetric.json"))
+    assert symmetric
+    n = 255
+    A = mg.stencil_q1_rotated(n, math.pi / 4, 0.01)
+    f = _dev(mg_inputs.rhs_uniform(n, 0))
+    ctx = mg.Context([A], mg.Options(smoother=mg.SMOOTHER_STACK))
+    ctx.set_stacks(stacks, symmetric=True)
+    res = ctx.solve([f], 1e-8, 5000)
+    jac = mg.Context([A], mg.Options(smoother=mg.SMOOTHER_JACOBI)).solve([f], 1e-8, 5000)
+    assert res.status[0] == 0 and jac.status[0] == 0
+    assert int(res.iters[0]) < int(jac.iters[0]), (int(res.iters[0]), int(jac.iters[0]))

@@ -131,18 +131,22 @@ class StackHierarchy:
         w = self.post[level] if after else self.smoothers[level]
         return e + stack_apply(w, r - matvec(A, e))
 
-    def vcycle(self, r, level: int = 0) -> np.ndarray:
-        """e = V(r) from level (Algorithm 1, correction form, one sweep before
-        and after the coarse correction)."""
+    def vcycle(self, r, level: int = 0, nu1: int = 1, nu2: int = 1) -> np.ndarray:
+        """e = V(r) from level (Algorithm 1, correction form, nu1 sweeps before
+        and nu2 after the coarse correction)."""
         r = np.asarray(r, dtype=np.float64)
         if level == self.num_levels - 1:
             m = r.shape[0]
             return np.linalg.solve(self._coarse, r.reshape(-1)).reshape(m, m)
         A = self.stencils[level]
-        e = self._smooth(level, r, np.zeros_like(r))
+        e = np.zeros_like(r)
+        for _ in range(nu1):
+            e = self._smooth(level, r, e)
         s = r - matvec(A, e)
-        e = prolong_add(self.vcycle(restrict_fw(s), level + 1), e)
-        return self._smooth(level, r, e, after=True)
+        e = prolong_add(self.vcycle(restrict_fw(s), level + 1, nu1, nu2), e)
+        for _ in range(nu2):
+            e = self._smooth(level, r, e, after=True)
+        return e
 
     def solve(self, f, tol: float, maxit: int):
         """u = 0; while ||f - A u|| > tol ||f|| and k < maxit: u += V(f - A u).

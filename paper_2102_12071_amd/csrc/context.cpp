@@ -77,13 +77,8 @@ mg_status build_slots(mg_ctx_s &c)
     c.bottom_top_n = 0;
     for (int p = 0; p < c.nprob; ++p) {
         ProbBuf &pb = c.probs[p];
-        // first level handled by the bottom kernel (the stack smoother runs in the
-        // step-by-step kernels on every level above the coarsest)
-        int top = 0;
-        if (c.opt.smoother == MG_SMOOTHER_STACK)
-            top = pb.nlev - 1;
-        else
-            while (pb.lev[top].n > kBottomMax) ++top;
+        int top = 0;  // first level handled by the bottom kernel
+        while (pb.lev[top].n > kBottomMax) ++top;
         for (int l = 0; l < top; ++l) {
             const LevelBuf &L = pb.lev[l], &Lc = pb.lev[l + 1];
             CycleSlot<T> s{};
@@ -132,7 +127,7 @@ mg_status build_slots(mg_ctx_s &c)
             bl.P = pb.lev[l].P;
             bl.plane = pb.lev[l].plane;
             bl.A = stencil_of<T>(pb.lev[l]);
-            bl.H = (const HT *)pb.lev[l].H;
+            bl.H = c.opt.smoother == MG_SMOOTHER_STACK ? (const HT *)pb.lev[l].phi : (const HT *)pb.lev[l].H;
         }
         b.Ainv = pb.Ainv;
         b.r_in = (const T *)pb.lev[top].r;
@@ -158,6 +153,7 @@ mg_status build_slots(mg_ctx_s &c)
     c.bottom.n = c.bottom_top_n;
     MG_TRY(upload_class(c.arena, bottom, all, c.bottom));
     prepare_bottom<T>();
+    if (c.opt.smoother == MG_SMOOTHER_STACK) prepare_stack_bottom<T>();
     return MG_OK;
 }
 
@@ -206,9 +202,14 @@ void enqueue_vcycle(mg_ctx_s &c, hipStream_t st)
         }
         launch_residual_restrict<T>(s, k.nrun, k.n, c.d_state, st);
     }
-    if (c.bottom.live)
-        launch_bottom<T>((const BottomSlot<T> *)c.bottom.d_run, c.bottom.nrun, c.bottom_top_n, cnn, w, c.opt.nu_pre,
-                         c.opt.nu_post, c.d_state, st);
+    if (c.bottom.live) {
+        if (stack)
+            launch_stack_bottom<T>((const BottomSlot<T> *)c.bottom.d_run, c.bottom.nrun, c.bottom_top_n, c.opt.nu_pre,
+                                   c.opt.nu_post, c.d_state, st);
+        else
+            launch_bottom<T>((const BottomSlot<T> *)c.bottom.d_run, c.bottom.nrun, c.bottom_top_n, cnn, w,
+                             c.opt.nu_pre, c.opt.nu_post, c.d_state, st);
+    }
     for (auto it = c.classes.rbegin(); it != c.classes.rend(); ++it) {  // ascending sizes
         const SizeClass &k = *it;
         if (!k.live) continue;
@@ -854,8 +855,12 @@ void launch_timed(mg_ctx_s &c, int k, const SizeClass &cls, const SizeClass &oc,
     case 2: launch_descend<T>(s, cls.nslots, n, cnn, w, c.d_state, st, cls.tile[0]); break;
     case 3: launch_ascend<T>(s, cls.nslots, n, cnn, w, c.d_state, st, cls.tile[1]); break;
     case 4:
-        launch_bottom<T>((const BottomSlot<T> *)c.bottom.d_slots, c.nprob, c.bottom_top_n, cnn, w, c.opt.nu_pre,
-                         c.opt.nu_post, c.d_state, st);
+        if (c.opt.smoother == MG_SMOOTHER_STACK)
+            launch_stack_bottom<T>((const BottomSlot<T> *)c.bottom.d_slots, c.nprob, c.bottom_top_n, c.opt.nu_pre,
+                                   c.opt.nu_post, c.d_state, st);
+        else
+            launch_bottom<T>((const BottomSlot<T> *)c.bottom.d_slots, c.nprob, c.bottom_top_n, cnn, w,
+                             c.opt.nu_pre, c.opt.nu_post, c.d_state, st);
         break;
     case 5:
         if (c.opt.smoother == MG_SMOOTHER_STACK)

@@ -209,6 +209,155 @@ __global__ void k_stack_adam(double *w, double *m, double *v, const double *g, i
     w[j] -= lr * mh / (sqrt(vh) + eps);
 }
 
+// ---- the levels with n <= kBottomMax in one workgroup per problem
+// Every smoothing level and the coarsest are held in LDS: five vectors per
+// level (r, e, s and two for the stack's intermediate layers) of (n + 2)^2
+// elements with a zero border of one node, which is the zero padding of every
+// layer; one thread per node (n^2 <= 961 < 1024 threads).  The V-cycle of
+// these levels (Algorithm 1) runs with a workgroup barrier between steps
+// instead of a launch per step; the coarsest inverse is read into LDS.
+constexpr int kSBT = 1024;
+constexpr int kSBVec = 5;
+constexpr size_t kSBAinvBytes = ((size_t)kMaxCoarseUnknowns * kMaxCoarseUnknowns * sizeof(double) + 15) / 16 * 16;
+
+__host__ __device__ inline int sb_vec(int n) { return (n + 2) * (n + 2); }
+__device__ inline int sb_at(int n, int i, int j) { return (j + 1) * (n + 2) + i + 1; }
+
+template <typename T>
+__global__ void __launch_bounds__(kSBT) k_stack_bottom(const BottomSlot<T> *slots, const SolveState *state, int nu1,
+                                                       int nu2)
+{
+    extern __shared__ __align__(16) unsigned char sb_raw[];
+    double *ainv = (double *)sb_raw;
+    T *sm = (T *)(sb_raw + kSBAinvBytes);
+    const BottomSlot<T> &S = slots[blockIdx.x];
+    if (!state[S.prob].active) return;  // uniform over the workgroup
+    const int NL = S.nlev, tid = threadIdx.x;
+    int off[kMaxBottomLevels];
+    int total = 0;
+    for (int l = 0; l < kMaxBottomLevels; ++l) {
+        off[l] = total;
+        if (l < NL) total += kSBVec * sb_vec(S.lev[l].n);
+    }
+    const int mc = S.lev[NL - 1].n, mm = mc * mc;
+    for (int q = tid; q < total; q += kSBT) sm[q] = (T)0;
+    for (int q = tid; q < mm * mm; q += kSBT) ainv[q] = S.Ainv[q];
+    __syncthreads();
+    {
+        const int n = S.lev[0].n, P = S.lev[0].P;
+        for (int q = tid; q < n * n; q += kSBT) sm[off[0] + sb_at(n, q % n, q / n)] = S.r_in[(int64_t)(q / n) * P + q % n];
+    }
+    __syncthreads();
+
+    // y (+)= H x on level l (x, y: LDS vector offsets); post: the weights after the coarse correction
+    auto stack = [&](int l, int X, int Y, bool acc, bool post) {
+        const int n = S.lev[l].n, V = sb_vec(n), T1 = off[l] + 3 * V, T2 = off[l] + 4 * V;
+        const T MG_G *w = (const T MG_G *)S.lev[l].H + (post ? kStackWeights : 0);
+        const int src[5] = {X, T1, T2, T1, T2}, dst[4] = {T1, T2, T1, T2};
+#pragma unroll
+        for (int layer = 0; layer < 4; ++layer) {
+            for (int q = tid; q < n * n; q += kSBT) {
+                const int i = q % n, j = q / n;
+                T v = (T)0;
+#pragma unroll
+                for (int t = 0; t < 9; ++t) v += w[layer * 9 + t] * sm[src[layer] + sb_at(n, i + t % 3 - 1, j + t / 3 - 1)];
+                sm[dst[layer] + sb_at(n, i, j)] = v;
+            }
+            __syncthreads();
+        }
+        for (int q = tid; q < n * n; q += kSBT) {
+            const int i = q % n, j = q / n;
+            T v = (T)0;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int a = sb_at(n, i + t % 3 - 1, j + t / 3 - 1);
+                v += w[36 + t] * sm[src[4] + a] + w[45 + t] * sm[X + a];
+            }
+            const int p = Y + sb_at(n, i, j);
+            sm[p] = acc ? sm[p] + v : v;
+        }
+        __syncthreads();
+    };
+    // s = r - A e on level l
+    auto residual = [&](int l) {
+        const int n = S.lev[l].n, P = S.lev[l].P, V = sb_vec(n), R = off[l], E = R + V, Sv = R + 2 * V;
+        const int64_t plane = S.lev[l].plane;
+        for (int q = tid; q < n * n; q += kSBT) {
+            const int i = q % n, j = q / n;
+            T acc = (T)0;
+#pragma unroll
+            for (int c = 0; c < 9; ++c)
+                acc += S.lev[l].A[c * plane + (int64_t)j * P + i] * sm[E + sb_at(n, i + c % 3 - 1, j + c / 3 - 1)];
+            sm[Sv + sb_at(n, i, j)] = sm[R + sb_at(n, i, j)] - acc;
+        }
+        __syncthreads();
+    };
+    // r_{l+1} = R s_l (full weighting)
+    auto restrict_to = [&](int l) {
+        const int n = S.lev[l].n, nc = S.lev[l + 1].n, Sv = off[l] + 2 * sb_vec(n), Rc = off[l + 1];
+        for (int q = tid; q < nc * nc; q += kSBT) {
+            const int I = q % nc, J = q / nc, ci = 2 * I + 1, cj = 2 * J + 1;
+            auto sv = [&](int di, int dj) { return sm[Sv + sb_at(n, ci + di, cj + dj)]; };
+            sm[Rc + sb_at(nc, I, J)] = (T)0.0625 * (sv(-1, -1) + sv(1, -1) + sv(-1, 1) + sv(1, 1)) +
+                                       (T)0.125 * (sv(0, -1) + sv(0, 1) + sv(-1, 0) + sv(1, 0)) + (T)0.25 * sv(0, 0);
+        }
+        __syncthreads();
+    };
+    // e_l += P e_{l+1} (bilinear; the coarse border is zero)
+    auto prolong = [&](int l) {
+        const int n = S.lev[l].n, nc = S.lev[l + 1].n, E = off[l] + sb_vec(n), Ec = off[l + 1] + sb_vec(nc);
+        for (int q = tid; q < n * n; q += kSBT) {
+            const int i = q % n, j = q / n;
+            const int ia = (i & 1) ? (i - 1) / 2 : i / 2 - 1, ib = (i & 1) ? ia : ia + 1;
+            const int ja = (j & 1) ? (j - 1) / 2 : j / 2 - 1, jb = (j & 1) ? ja : ja + 1;
+            T acc = sm[Ec + sb_at(nc, ia, ja)];
+            if (ib != ia) acc += sm[Ec + sb_at(nc, ib, ja)];
+            if (jb != ja) {
+                acc += sm[Ec + sb_at(nc, ia, jb)];
+                if (ib != ia) acc += sm[Ec + sb_at(nc, ib, jb)];
+            }
+            const T wt = (T)(((i & 1) ? 1.0 : 0.5) * ((j & 1) ? 1.0 : 0.5));
+            sm[E + sb_at(n, i, j)] += wt * acc;
+        }
+        __syncthreads();
+    };
+
+    for (int l = 0; l + 1 < NL; ++l) {
+        const int V = sb_vec(S.lev[l].n);
+        if (nu1 > 0) stack(l, off[l], off[l] + V, false, false);  // e = H r
+        for (int it = 1; it < nu1; ++it) {
+            residual(l);
+            stack(l, off[l] + 2 * V, off[l] + V, true, false);
+        }
+        residual(l);
+        restrict_to(l);
+    }
+    {  // the coarsest level: e = A^{-1} r, node (row % mc, row / mc)
+        const int Rc = off[NL - 1], Ec = Rc + sb_vec(mc);
+        T v = (T)0;
+        if (tid < mm) {
+            double acc = 0.0;
+            for (int k = 0; k < mm; ++k) acc += ainv[tid * mm + k] * (double)sm[Rc + sb_at(mc, k % mc, k / mc)];
+            v = (T)acc;
+        }
+        __syncthreads();
+        if (tid < mm) sm[Ec + sb_at(mc, tid % mc, tid / mc)] = v;
+        __syncthreads();
+    }
+    for (int l = NL - 2; l >= 0; --l) {
+        const int V = sb_vec(S.lev[l].n);
+        prolong(l);
+        for (int q = 0; q < nu2; ++q) {
+            residual(l);
+            stack(l, off[l] + 2 * V, off[l] + V, true, true);
+        }
+    }
+    {
+        const int n = S.lev[0].n, P = S.lev[0].P, E = off[0] + sb_vec(n);
+        for (int q = tid; q < n * n; q += kSBT) S.e_out[(int64_t)(q / n) * P + q % n] = sm[E + sb_at(n, q % n, q / n)];
+    }
+}
+
 inline dim3 tile_grid(int n, int count)
 {
     return dim3((unsigned)((n + kTX - 1) / kTX), (unsigned)((n + kTY - 1) / kTY), (unsigned)count);
@@ -226,6 +375,34 @@ void launch_stack_cycle(const CycleSlot<T> *slots, int nslots, int n, int mode, 
 }
 template void launch_stack_cycle<float>(const CycleSlot<float> *, int, int, int, const SolveState *, hipStream_t);
 template void launch_stack_cycle<double>(const CycleSlot<double> *, int, int, int, const SolveState *, hipStream_t);
+
+template <typename T>
+size_t stack_bottom_smem_bytes(int top_n)
+{
+    size_t v = 0;
+    for (int m = top_n, l = 0; l < kMaxBottomLevels; ++l, m = m > 1 ? (m - 1) / 2 : 1) v += kSBVec * sb_vec(m);
+    return kSBAinvBytes + v * sizeof(T);
+}
+
+template <typename T>
+void prepare_stack_bottom()
+{
+    // allow more than 64 KiB of dynamic LDS
+    (void)hipFuncSetAttribute((const void *)k_stack_bottom<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)stack_bottom_smem_bytes<T>(kBottomMax));
+}
+
+template <typename T>
+void launch_stack_bottom(const BottomSlot<T> *slots, int nslots, int top_n, int nu1, int nu2, const SolveState *state,
+                         hipStream_t st)
+{
+    k_stack_bottom<T><<<nslots, kSBT, stack_bottom_smem_bytes<T>(top_n), st>>>(slots, state, nu1, nu2);
+}
+template void prepare_stack_bottom<float>();
+template void prepare_stack_bottom<double>();
+template void launch_stack_bottom<float>(const BottomSlot<float> *, int, int, int, int, const SolveState *, hipStream_t);
+template void launch_stack_bottom<double>(const BottomSlot<double> *, int, int, int, int, const SolveState *,
+                                          hipStream_t);
 
 void launch_stack_vecs(const double *x, double *y, int64_t vs, const double *w, int n, int P, int count,
                        bool accumulate, const int *active, hipStream_t st)

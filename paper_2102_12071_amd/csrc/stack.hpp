@@ -16,6 +16,15 @@ template <typename T>
 void launch_stack_cycle(const CycleSlot<T> *slots, int nslots, int n, int mode, const SolveState *state,
                         hipStream_t st);
 
+// All levels with n <= kBottomMax of every problem in one workgroup each
+// (bottom slots whose H points to each level's two weight sets); the top
+// level's r in, its e out.  prepare_stack_bottom once per compute type before.
+template <typename T>
+void prepare_stack_bottom();
+template <typename T>
+void launch_stack_bottom(const BottomSlot<T> *slots, int nslots, int top_n, int nu1, int nu2, const SolveState *state,
+                         hipStream_t st);
+
 // y_z (+)= H x_z for z < count, vectors of pitch P at stride vs, one weight
 // set w (device, [54]); active (or null) skips vectors.  x and y must not overlap.
 void launch_stack_vecs(const double *x, double *y, int64_t vs, const double *w, int n, int P, int count,

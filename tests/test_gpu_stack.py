@@ -61,13 +61,33 @@ def _hierarchy_pair(mg, n, precision, seed, coarsest=7, f32=False):
     return A, h, ctx
 
 
-@pytest.mark.parametrize("n", [63, 255])
+@pytest.mark.parametrize("n", [31, 63, 255])
 def test_fp64_cycle_matches_oracle(mg, n):
+    # n = 31: the whole cycle in the one-workgroup kernel; larger: the step kernels above it
     A, h, ctx = _hierarchy_pair(mg, n, mg.PREC_FP64, 3)
     f = mg_inputs.rhs_uniform(n, 1)
     u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
     ctx.vcycle([_dev(f)], [u])
     ref = h.vcycle(f)
+    assert np.abs(u.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("coarsest", [1, 3, 7])
+def test_fp64_two_sweep_cycle_matches_oracle(mg, coarsest):
+    # V(2,2): repeated sweeps in the step kernels (n = 63) and in the one-workgroup kernel (n <= 31)
+    n = 63
+    A = ora.stencil_q1_rotated(n, 2.0, 0.2)
+    h = st.StackHierarchy(A, coarsest)
+    ctx = mg.Context([_dev(A)], mg.Options(smoother=mg.SMOOTHER_STACK, precision=mg.PREC_FP64,
+                                           coarsest_n=coarsest, nu_pre=2, nu_post=2))
+    for l in range(h.num_levels - 1):
+        w = _scaled(90 + l, h.stencils[l])
+        h.set_stack(l, w, post=st.stack_transpose(w))
+        ctx.set_stack(0, l, w, symmetric=True)
+    f = mg_inputs.rhs_uniform(n, 8)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    ctx.vcycle([_dev(f)], [u])
+    ref = h.vcycle(f, nu1=2, nu2=2)
     assert np.abs(u.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
 
 

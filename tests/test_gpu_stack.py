@@ -334,3 +334,35 @@ def test_committed_symmetric_stacks_converge_where_the_plain_ones_diverge(mg):
     jac = mg.Context([A], mg.Options(smoother=mg.SMOOTHER_JACOBI)).solve([f], 1e-8, 5000)
     assert res.status[0] == 0 and jac.status[0] == 0
     assert int(res.iters[0]) < int(jac.iters[0]), (int(res.iters[0]), int(jac.iters[0]))
+
+
+def test_uneven_batch_matches_individual_solves(mg):
+    # problems of three sizes in one context (size classes of the step kernels, bottom slots of
+    # different top sizes): each solves as it does alone, to the same iterate and count
+    specs = [(31, 0.3, 0.1), (127, 1.2, 0.05), (63, 2.5, 0.02), (127, 0.0, 0.3)]
+    As, fs, stack_sets = [], [], []
+    for k, (n, th, ep) in enumerate(specs):
+        A = ora.stencil_q1_rotated(n, th, ep)
+        h = st.StackHierarchy(A, 7)
+        ws = []
+        for l in range(h.num_levels - 1):
+            w = mg_inputs.stack_random(200 + 10 * k + l, 0.01)
+            w[4:] /= h.stencils[l][4].flat[0]
+            ws.append(w)
+        As.append(A)
+        fs.append(mg_inputs.rhs_uniform(n, 20 + k))
+        stack_sets.append(ws)
+    opt = mg.Options(smoother=mg.SMOOTHER_STACK, precision=mg.PREC_FP64)
+    batch = mg.Context([_dev(A) for A in As], opt)
+    for p, ws in enumerate(stack_sets):
+        for l, w in enumerate(ws):
+            batch.set_stack(p, l, w)
+    res = batch.solve([_dev(f) for f in fs], 1e-10, 3000)
+    for p, (A, f, ws) in enumerate(zip(As, fs, stack_sets)):
+        one = mg.Context([_dev(A)], opt)
+        for l, w in enumerate(ws):
+            one.set_stack(0, l, w)
+        r1 = one.solve([_dev(f)], 1e-10, 3000)
+        assert res.status[p] == 0 and r1.status[0] == 0
+        assert int(res.iters[p]) == int(r1.iters[0])
+        assert torch.equal(res.u[p], r1.u[0])

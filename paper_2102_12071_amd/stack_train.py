@@ -138,10 +138,11 @@ def worst_errors(n: int, theta: float, eps: float, Q: int, stacks: Dict[int, np.
 
 
 def _run_stage(stage: StackStage, w0: np.ndarray, steps: int, lr: float, lr_final: float, bmax: int, log,
-               growth_of=None):
+               growth_of=None, max_growth: Optional[float] = None):
     """Adam from the normalised weights w0.  Keeps the weights of the lowest monitored loss at
-    k = bmax, or (growth_of given: normalised weights -> the stage hierarchy's estimated growth
-    per cycle) of the smallest growth, the loss breaking ties within 1 %."""
+    k = bmax; with growth_of (normalised weights -> the stage hierarchy's estimated growth per
+    cycle): of the smallest growth (rounded to 0.01; the loss breaks ties), or, with max_growth,
+    of the lowest loss among those whose growth is below max_growth (else the smallest growth)."""
     state = mgcnn.StackAdam(mgcnn.stack_for_level(w0, stage.top.stencil(0, 0)))
 
     def normalised(phi):
@@ -152,7 +153,10 @@ def _run_stage(stage: StackStage, w0: np.ndarray, steps: int, lr: float, lr_fina
     def score(m, phi):
         if growth_of is None:
             return (m,)
-        return (round(growth_of(normalised(phi)), 2), m)
+        g = growth_of(normalised(phi))
+        if max_growth is not None:
+            return (0, m) if g < max_growth else (1, g)
+        return (round(g, 2), m)
 
     m0 = stage.monitor(state, bmax)
     best = (score(m0, state.phi), m0, state.phi.clone())
@@ -179,20 +183,21 @@ def train(theta: float, eps: float, finest: int = 63, Q: int = 50, steps: int = 
           lr_final: Optional[float] = None, bmax: int = 4, seed: int = 0, coarsest: int = 3,
           update_rounds: int = 0, update_steps: int = 200, warm: bool = False, max_points: int = 0,
           steps_large: Optional[int] = None, large_n: int = 63, symmetric: bool = False, select: str = "loss",
-          log=print):
+          max_growth: float = 0.98, log=print):
     """Stages from the coarsest up.  warm: a stage starts from the previous stage's weights (the
     operator is the same up to scale on every level) instead of the damped-Jacobi initialisation;
     max_points: at most that many grid points per stage (Q shrinks on large stages, at least 4);
     stages above large_n take steps_large steps and no update rounds."""
     lr_final = lr if lr_final is None else lr_final
     steps_large = steps if steps_large is None else steps_large
+    cap = max_growth if select == "stable" else None
     stacks: Dict[int, np.ndarray] = {}
     records = []
     qn = lambda n: max(4, min(Q, max_points // (n * n))) if max_points else Q
     sizes = stage_sizes(finest, coarsest)
 
     def growth_fn(n):
-        if select != "growth":
+        if select == "loss":
             return None
         return lambda w: worst_errors(n, theta, eps, min(4, qn(n)), {**{m: s for m, s in stacks.items() if m < n},
                                                                      n: w}, seed, coarsest=coarsest,
@@ -203,7 +208,7 @@ def train(theta: float, eps: float, finest: int = 63, Q: int = 50, steps: int = 
         st = StackStage(n, theta, eps, qn(n), stacks, seed, coarsest, symmetric=symmetric)
         w0 = stacks[prev] if (warm and prev is not None) else mg_inputs.stack_init(seed + n)
         w, start, end = _run_stage(st, w0, steps if n <= large_n else steps_large, lr, lr_final, bmax, log,
-                                   growth_fn(n))
+                                   growth_fn(n), cap)
         st.close()
         stacks[n] = w
         _, growth = worst_errors(n, theta, eps, min(8, qn(n)), stacks, seed, coarsest=coarsest, symmetric=symmetric)
@@ -223,7 +228,8 @@ def train(theta: float, eps: float, finest: int = 63, Q: int = 50, steps: int = 
                                           rnd=rnd + 1, symmetric=symmetric)
             lower = {m: s for m, s in stacks.items() if m < n}
             st = StackStage(n, theta, eps, qn(n), lower, seed + 100 * (rnd + 1), coarsest, inject, symmetric)
-            w, start, end = _run_stage(st, stacks[n], update_steps, lr_final, lr_final, bmax, log, growth_fn(n))
+            w, start, end = _run_stage(st, stacks[n], update_steps, lr_final, lr_final, bmax, log, growth_fn(n),
+                                       cap)
             st.close()
             stacks[n] = w
             _, after = worst_errors(n, theta, eps, min(8, qn(n)), stacks, seed, coarsest=coarsest, symmetric=symmetric)
@@ -271,8 +277,10 @@ def main():
     ap.add_argument("--steps-large", type=int, default=None, help="steps of the stages above --large-n")
     ap.add_argument("--large-n", type=int, default=63)
     ap.add_argument("--symmetric", action="store_true", help="post-smooth with H^T (the symmetric cycle)")
-    ap.add_argument("--select", choices=["loss", "growth"], default="loss",
-                    help="keep a stage's weights of the lowest monitored loss, or of the smallest growth estimate")
+    ap.add_argument("--select", choices=["loss", "growth", "stable"], default="loss",
+                    help="keep a stage's weights of the lowest monitored loss, of the smallest growth estimate, "
+                         "or of the lowest loss among those with growth below --max-growth")
+    ap.add_argument("--max-growth", type=float, default=0.98)
     ap.add_argument("--eval", type=int, nargs="*", default=[63, 255, 1023])
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
@@ -284,7 +292,7 @@ def main():
     stacks, records = train(a.theta, a.eps, a.finest, a.instances, a.steps, a.lr, a.lr_final, a.bmax, a.seed,
                             update_rounds=a.update_rounds, update_steps=a.update_steps, warm=a.warm,
                             max_points=a.max_points, steps_large=a.steps_large, large_n=a.large_n,
-                            symmetric=a.symmetric, select=a.select, log=log)
+                            symmetric=a.symmetric, select=a.select, max_growth=a.max_growth, log=log)
     for n in a.eval:
         r = evaluate(stacks, n, a.theta, a.eps, symmetric=a.symmetric)
         records.append({"eval": {"n": n, "theta": a.theta, "eps": a.eps}, **r})
@@ -292,7 +300,7 @@ def main():
     cmd = "python -m paper_2102_12071_amd.stack_train " + " ".join(sys.argv[1:])
     with open(a.out, "w") as fh:
         json.dump({"command": cmd, "device": "one MI355X", "problem": {"theta": a.theta, "eps": a.eps},
-                   "symmetric": a.symmetric, "select": a.select,
+                   "symmetric": a.symmetric, "select": a.select, "max_growth": a.max_growth,
                    "note": "weights [6][3][3] per trained size, normalised to a_C = 1 (f5 and f6 times a_C); "
                            "eval: V(1,1) to 1e-8 over a 7 x 7 coarsest grid, mixed precision",
                    "stacks": {str(n): w.reshape(-1).tolist() for n, w in stacks.items()},

@@ -317,23 +317,27 @@ def test_set_stack_post_needs_the_stack_first(mg):
     assert rc == mg.MG_ERR_STATE
 
 
-def test_committed_symmetric_stacks_converge_where_the_plain_ones_diverge(mg):
-    # theta = pi/4, eps = 0.01: trained with H^T after the coarse correction, converging at n = 255
-    # with fewer cycles than damped Jacobi (the same training with H after it diverges there)
+@pytest.mark.parametrize("name,theta,eps,factor", [("stack_theta0.785_eps0.01_symmetric.json", math.pi / 4, 0.01, 1),
+                                                    ("stack_theta1.047_eps0.001_symmetric.json", math.pi / 3, 1e-3, 5)])
+def test_committed_symmetric_stacks_converge_where_the_plain_ones_diverge(mg, name, theta, eps, factor):
+    # trained with H^T after the coarse correction: converging at n = 255 with fewer cycles than damped
+    # Jacobi (factor times fewer), where the same training with H after it diverges; the true FP64
+    # residual by the oracle
     import os
     from paper_2102_12071_amd.stack_train import load_stack_run
-    stacks, symmetric = load_stack_run(os.path.join(os.path.dirname(mg.__file__), "weights",
-                                                    "stack_theta0.785_eps0.01_symmetric.json"))
+    stacks, symmetric = load_stack_run(os.path.join(os.path.dirname(mg.__file__), "weights", name))
     assert symmetric
     n = 255
-    A = mg.stencil_q1_rotated(n, math.pi / 4, 0.01)
-    f = _dev(mg_inputs.rhs_uniform(n, 0))
+    A = mg.stencil_q1_rotated(n, theta, eps)
+    f = mg_inputs.rhs_uniform(n, 0)
     ctx = mg.Context([A], mg.Options(smoother=mg.SMOOTHER_STACK))
     ctx.set_stacks(stacks, symmetric=True)
-    res = ctx.solve([f], 1e-8, 5000)
-    jac = mg.Context([A], mg.Options(smoother=mg.SMOOTHER_JACOBI)).solve([f], 1e-8, 5000)
+    res = ctx.solve([_dev(f)], 1e-8, 5000)
+    jac = mg.Context([A], mg.Options(smoother=mg.SMOOTHER_JACOBI)).solve([_dev(f)], 1e-8, 5000)
     assert res.status[0] == 0 and jac.status[0] == 0
-    assert int(res.iters[0]) < int(jac.iters[0]), (int(res.iters[0]), int(jac.iters[0]))
+    r = f - ora.matvec(A.cpu().numpy(), res.u[0].cpu().numpy())
+    assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(f)
+    assert factor * int(res.iters[0]) < int(jac.iters[0]), (int(res.iters[0]), int(jac.iters[0]))
 
 
 def test_uneven_batch_matches_individual_solves(mg):

@@ -430,17 +430,26 @@ def stack_block(args, A, f, n, theta, eps, coarsest):
         res = ctx.solve([f], args.tol, args.maxit)
         ms = (time.perf_counter() - t0) * 1e3
         k = ctx.time_kernels(args.kernel_reps)
+        fg = None
+        if args.restart > 0 and int(res.status[0]) == 0:  # the cycle as a preconditioner of FGMRES
+            ctx.solve_fgmres([f], args.tol, args.maxit, restart=args.restart)  # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.solve_fgmres([f], args.tol, args.maxit, restart=args.restart)
+            fg = {"iters": int(r.iters[0]), "status": int(r.status[0]), "relres": float(r.relres[0]),
+                  "solve_ms": (time.perf_counter() - t0) * 1e3, "restart": args.restart}
         ctx.close()
         bytes_per_launch = 12.0 * n * n  # algorithmic, per node: x read once, e read and written (FP32)
         out.append({"weights": os.path.relpath(path, os.path.dirname(os.path.abspath(__file__))),
                     "symmetric": symmetric, "trained_sizes": sorted(stacks), "iters": int(res.iters[0]),
                     "status": int(res.status[0]), "relres": float(res.relres[0]), "solve_ms": ms,
-                    "ms_per_iteration": float(res.ms) / max(int(res.iters[0]), 1),
+                    "ms_per_iteration": float(res.ms) / max(int(res.iters[0]), 1), "fgmres": fg,
                     "kernel": {"name": "k_stack_cycle (accumulating, after the coarse correction)",
                                "ms": k["smooth_apply"], "algorithmic_bytes": bytes_per_launch,
                                "achieved_gbs": bytes_per_launch / (k["smooth_apply"] * 1e-3) / 1e9}})
         log(f"alpha-CNN stack ({os.path.basename(path)}): {out[-1]['iters']} iterations, "
-            f"status {out[-1]['status']}, {ms:.1f} ms; stack kernel {k['smooth_apply'] * 1e3:.1f} us")
+            f"status {out[-1]['status']}, {ms:.1f} ms; stack kernel {k['smooth_apply'] * 1e3:.1f} us"
+            + (f"; FGMRES {fg['iters']} iterations, {fg['solve_ms']:.1f} ms" if fg else ""))
     return out
 
 

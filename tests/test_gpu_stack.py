@@ -370,3 +370,23 @@ def test_uneven_batch_matches_individual_solves(mg):
         assert res.status[p] == 0 and r1.status[0] == 0
         assert int(res.iters[p]) == int(r1.iters[0])
         assert torch.equal(res.u[p], r1.u[0])
+
+
+def test_committed_symmetric_stacks_precondition_fgmres(mg):
+    # the symmetric stack cycle of the benchmark problem as the preconditioner of FGMRES(30): fewer
+    # iterations than with the Jacobi cycle, the true FP64 residual by the oracle
+    import os
+    from paper_2102_12071_amd.stack_train import load_stack_run
+    stacks, symmetric = load_stack_run(os.path.join(os.path.dirname(mg.__file__), "weights",
+                                                    "stack_theta1.047_eps0.001_symmetric.json"))
+    n = 255
+    A = mg.stencil_q1_rotated(n, math.pi / 3, 1e-3)
+    f = mg_inputs.rhs_uniform(n, 1)
+    ctx = mg.Context([A], mg.Options(smoother=mg.SMOOTHER_STACK))
+    ctx.set_stacks(stacks, symmetric=symmetric)
+    res = ctx.solve_fgmres([_dev(f)], 1e-8, 1000, restart=30)
+    jac = mg.Context([A], mg.Options(smoother=mg.SMOOTHER_JACOBI)).solve_fgmres([_dev(f)], 1e-8, 1000, restart=30)
+    assert res.status[0] == 0 and jac.status[0] == 0
+    r = f - ora.matvec(A.cpu().numpy(), res.u[0].cpu().numpy())
+    assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(f)
+    assert int(res.iters[0]) < int(jac.iters[0]), (int(res.iters[0]), int(jac.iters[0]))

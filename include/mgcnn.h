@@ -366,7 +366,7 @@ mg_status mg_alpha_step(mg_ctx top, mg_ctx coarse, mg_ctx coarse_t, mg_net net, 
  * transpose = 1 installs the stack of H^T instead (the kernels turned by 180
  * degrees, f1..f5 in reverse order), as the adjoint context of
  * mg_stack_alpha_step needs.  Every level above the coarsest of every problem
- * needs weights before mg_vcycle / mg_solve / mg_fgmres (MG_ERR_STATE).
+ * needs weights before mg_vcycle / mg_solve / mg_solve_fgmres (MG_ERR_STATE).
  * Synchronises. */
 mg_status mg_set_stack(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose);
 

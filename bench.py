@@ -148,8 +148,9 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no multi-GPU path; "
-              f"see the sharding notes in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library has no multi-GPU path "
+              f"(independent problems would shard by size-balanced bin packing, one large grid by 2-D "
+              f"blocks with halo exchanges)", file=sys.stderr)
         sys.exit(2)
     if os.environ.get("WORLD_SIZE", "1") not in ("1", ""):
         print("bench.py runs on one GPU only (WORLD_SIZE > 1)", file=sys.stderr)

@@ -31,18 +31,6 @@ namespace {
 
 constexpr int kMaxCycles = 64;
 
-struct Carve {
-    char *base;
-    size_t off = 0;
-    template <typename T>
-    T *take(size_t count)
-    {
-        T *p = (T *)(base ? base + off : nullptr);
-        off += (count * sizeof(T) + 255) & ~(size_t)255;
-        return p;
-    }
-};
-
 // Vectors of the step, each B * vs doubles.
 enum { kU, kF, kUs, kA, kS, kT, kLam, kDq, kDt, kDs, kDa, kDr, kNumVec };
 
@@ -74,7 +62,11 @@ Work carve(char *base, int B, int kmax, int n, int64_t vs, int64_t plane)
     return w;
 }
 
-mg_status check_coarse(const mg_ctx_s &top, const mg_ctx_s &c, const char *name)
+}  // namespace
+
+namespace mg {
+
+mg_status check_alpha_coarse(const mg_ctx_s &top, const mg_ctx_s &c, const char *name)
 {
     if (c.opt.precision != MG_PREC_FP64) return set_error(MG_ERR_ARG, "%s must be an FP64 context", name);
     if (c.nprob != top.nprob) return set_error(MG_ERR_SHAPE, "%s has %d problems, top %d", name, c.nprob, top.nprob);
@@ -92,7 +84,7 @@ mg_status check_coarse(const mg_ctx_s &top, const mg_ctx_s &c, const char *name)
     return MG_OK;
 }
 
-}  // namespace
+}  // namespace mg
 
 extern "C" mg_status mg_smoother_transpose(int32_t n, const double *A, const double *W, double *WT, void *stream)
 {
@@ -134,8 +126,8 @@ extern "C" mg_status mg_alpha_step(mg_ctx top, mg_ctx coarse, mg_ctx coarse_t, m
         kmax = std::max(kmax, b->k[p]);
     }
     if (c.probs[0].nlev < 2) return set_error(MG_ERR_SHAPE, "top needs a coarser level (n > coarsest_n)");
-    MG_TRY(check_coarse(c, *coarse, "coarse"));
-    MG_TRY(check_coarse(c, *coarse_t, "coarse_t"));
+    MG_TRY(check_alpha_coarse(c, *coarse, "coarse"));
+    MG_TRY(check_alpha_coarse(c, *coarse_t, "coarse_t"));
     if (coarse == top || coarse_t == top) return set_error(MG_ERR_ARG, "the coarse contexts must differ from top");
 
     const LevelBuf &L0 = c.probs[0].lev[0];

@@ -35,4 +35,18 @@ void launch_al_dw(const AlphaProb *pr, int nb, int n, int P, int64_t plane, cons
 // Dense [25][n][n] field W of stencil A to the field of the transposed smoother.
 void launch_al_transpose(int n, const double *A, const double *W, double *WT, hipStream_t st);
 
+// Sub-allocation of a step's workspace in 256-byte aligned pieces; with a null
+// base it only adds up the size.
+struct Carve {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t count)
+    {
+        T *p = (T *)(base ? base + off : nullptr);
+        off += (count * sizeof(T) + 255) & ~(size_t)255;
+        return p;
+    }
+};
+
 }  // namespace mg

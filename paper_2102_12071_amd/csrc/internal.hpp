@@ -124,6 +124,10 @@ mg_status ctx_check_vectors(mg_ctx c, const double *const *f, double *const *u);
 // MG_ERR_STATE unless the context's smoother can run: the CNN's fields inferred
 // or set, the stack's weights installed on every level above the coarsest.
 mg_status ctx_check_smoother(const mg_ctx_s &c);
+// The coarse contexts of an Algorithm 2 step (alpha.cpp): FP64, one problem per
+// problem of top at its level 1 (same order), as many post- as pre-smoothing
+// sweeps, the fixed smoothers installed.  name: the argument's name in messages.
+mg_status check_alpha_coarse(const mg_ctx_s &top, const mg_ctx_s &c, const char *name);
 // Launches only the slots of the given problems from now on (see update_live).
 mg_status ctx_set_live(mg_ctx_s &c, const std::vector<char> &active);
 // Enqueues e = V(r) of the live problems: level-0 r in, u += e on the finest level.

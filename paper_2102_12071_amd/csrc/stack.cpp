@@ -27,18 +27,6 @@ namespace {
 
 constexpr int kMaxCycles = 64;
 
-struct Carve {
-    char *base;
-    size_t off = 0;
-    template <typename T>
-    T *take(size_t count)
-    {
-        T *p = (T *)(base ? base + off : nullptr);
-        off += (count * sizeof(T) + 255) & ~(size_t)255;
-        return p;
-    }
-};
-
 // state vectors, adjoint vectors, and the gradient's intermediates x1..x4, g0..g3
 enum { kU, kF, kUs, kA, kS, kT, kLam, kDq, kDt, kDs, kDa, kDr, kX1, kX2, kX3, kX4, kG0, kG1, kG2, kG3, kNumVec };
 
@@ -66,22 +54,6 @@ Work carve(char *base, int B, int kmax, int n, int64_t vs)
     w.vec = c.take<double>((size_t)(kNumVec + 2 * kmax) * B * vs);
     w.bytes = c.off;
     return w;
-}
-
-mg_status check_coarse(const mg_ctx_s &top, const mg_ctx_s &c, const char *name)
-{
-    if (c.opt.precision != MG_PREC_FP64) return set_error(MG_ERR_ARG, "%s must be an FP64 context", name);
-    if (c.nprob != top.nprob) return set_error(MG_ERR_SHAPE, "%s has %d problems, top %d", name, c.nprob, top.nprob);
-    if (c.opt.nu_pre != c.opt.nu_post)
-        return set_error(MG_ERR_ARG, "%s: the coarse cycle needs as many post- as pre-smoothing sweeps", name);
-    MG_TRY(ctx_check_smoother(c));
-    for (int p = 0; p < c.nprob; ++p) {
-        const ProbBuf &t = top.probs[p], &q = c.probs[p];
-        if (q.n != (t.n - 1) / 2 || q.nlev != t.nlev - 1)
-            return set_error(MG_ERR_SHAPE, "%s problem %d: n = %d with %d levels, expected %d with %d", name, p, q.n,
-                             q.nlev, (t.n - 1) / 2, t.nlev - 1);
-    }
-    return MG_OK;
 }
 
 // Writes a level's weights: half 0 (before the coarse correction), 1 (after), or both (-1).
@@ -181,8 +153,8 @@ mg_status mg_stack_alpha_step(mg_ctx top, mg_ctx coarse, mg_ctx coarse_t, double
         kmax = std::max(kmax, b->k[p]);
     }
     if (c.probs[0].nlev < 2) return set_error(MG_ERR_SHAPE, "top needs a coarser level (n > coarsest_n)");
-    MG_TRY(check_coarse(c, *coarse, "coarse"));
-    MG_TRY(check_coarse(c, *coarse_t, "coarse_t"));
+    MG_TRY(check_alpha_coarse(c, *coarse, "coarse"));
+    MG_TRY(check_alpha_coarse(c, *coarse_t, "coarse_t"));
     if (coarse == top || coarse_t == top) return set_error(MG_ERR_ARG, "the coarse contexts must differ from top");
 
     const LevelBuf &L0 = c.probs[0].lev[0];

@@ -380,8 +380,9 @@ mg_status mg_set_stack(mg_ctx ctx, int32_t prob, int32_t level, const double *ph
 mg_status mg_set_stack_post(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose);
 
 /* y_c (+)= H x_c for c < count: x, y device [count][n][n] FP64 (must not
- * overlap), phi device [54] FP64, accumulate 0 (y = H x) or 1 (y += H x).
- * Asynchronous on stream. */
+ * overlap), phi device [54] FP64, accumulate 0 (y = H x) or 1 (y += H x);
+ * 1 <= n <= 16383, 0 <= count <= 65535 (else MG_ERR_ARG).  Asynchronous on
+ * stream. */
 mg_status mg_stack_apply(int32_t n, int32_t count, const double *phi, const double *x, double *y,
                          int32_t accumulate, void *stream);
 

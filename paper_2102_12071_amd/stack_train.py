@@ -18,8 +18,17 @@ times the stage's a_C); a level takes them divided by its own a_C, so a stack
 serves any level of the problem's Galerkin hierarchy (for these operators
 every Galerkin level is the same stencil over 4).
 
-    python -m paper_2102_12071_amd.stack_train --theta 1.0471975511965976 --eps 1e-3 \
-        --out paper_2102_12071_amd/weights/stack_c2.json
+Options beyond the paper's procedure: stages above n = 63 (--finest, with
+--max-points capping the instances per stage); --symmetric, H^T after the
+coarse correction (the cycle's error propagation is then self-adjoint in the
+A inner product); --select growth / stable, keeping a stage's weights by the
+power-iteration estimate of its hierarchy's growth per cycle rather than by
+the monitored loss alone.  Each committed run records its command, e.g.
+
+    python -m paper_2102_12071_amd.stack_train --theta 1.0471975511965976 --eps 1e-3 --finest 1023 \
+        --max-points 200000 --steps 3000 --large-n 1023 --bmax 8 --lr 3e-3 --lr-final 1e-4 \
+        --update-rounds 2 --update-steps 600 --symmetric --select stable --max-growth 0.98 \
+        --out paper_2102_12071_amd/weights/stack_theta1.047_eps0.001_symmetric.json
 """
 from __future__ import annotations
 

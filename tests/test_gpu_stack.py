@@ -390,3 +390,21 @@ def test_committed_symmetric_stacks_precondition_fgmres(mg):
     r = f - ora.matvec(A.cpu().numpy(), res.u[0].cpu().numpy())
     assert np.linalg.norm(r) <= 1.01e-8 * np.linalg.norm(f)
     assert int(res.iters[0]) < int(jac.iters[0]), (int(res.iters[0]), int(jac.iters[0]))
+
+
+def test_mixed_symmetric_cycle_matches_oracle(mg):
+    # FP32 inner cycle, H before and H^T after the coarse correction (the transposed weights are a
+    # permutation of the FP32 weights the context holds)
+    n = 255
+    A = ora.stencil_q1_rotated(n, 0.8, 0.02)
+    h = st.StackHierarchy(A, 7)
+    ctx = mg.Context([_dev(A)], mg.Options(smoother=mg.SMOOTHER_STACK, precision=mg.PREC_MIXED))
+    for l in range(h.num_levels - 1):
+        w = _scaled(120 + l, h.stencils[l], f32=True)
+        h.set_stack(l, w, post=st.stack_transpose(w))
+        ctx.set_stack(0, l, w, symmetric=True)
+    f = mg_inputs.rhs_uniform(n, 9)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    ctx.vcycle([_dev(f)], [u])
+    ref = h.vcycle(f)
+    assert np.abs(u.cpu().numpy() - ref).max() <= 2e-5 * np.abs(ref).max()

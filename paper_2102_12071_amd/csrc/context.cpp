@@ -720,6 +720,9 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
     std::vector<char> act(c.nprob);
     const int every = c.opt.check_every;
     int64_t replays = 0;
+    // maxit cycles and the last check take maxit + 1 replays; a problem paused for the fallback
+    // spends the rest of its check block without cycling, so each switch adds one block
+    int64_t budget = (int64_t)maxit + 2;
     for (;;) {
         MG_TRY(ensure_graph(c));  // (re)captured with the live classes; the stream is idle here
         for (int q = 0; q < every; ++q) {
@@ -757,13 +760,14 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
         if (resumed) {
             MG_HIP(hipMemcpyAsync(c.d_state, hs.data(), sizeof(SolveState) * c.nprob, hipMemcpyHostToDevice, st));
             MG_HIP(hipStreamSynchronize(st));
+            budget += every;
         }
         bool any = false;
         for (int p = 0; p < c.nprob; ++p) {
             act[p] = hs[p].active != 0;
             any |= act[p] != 0;
         }
-        if (!any || replays > (int64_t)maxit + 2) break;
+        if (!any || replays > budget) break;
         MG_TRY(update_live(c, act));
     }
     copy_out(c, u, st);

@@ -46,8 +46,9 @@ def test_diverging_smoother_falls_back_and_converges(mg):
     A = ora.stencil_q1_rotated(n, math.pi / 6, 0.01)
     f = mg_inputs.rhs_uniform(n, 0)
     tol = 1e-9
-    jac = mg.Context([_dev(A)], mg.Options(precision=mg.PREC_FP64)).solve([_dev(f)], tol, 3000, history=True)
-    jac_hist = jac.history[0]
+    # the oracle's FP64 damped-Jacobi V(1,1) solve from u = 0
+    _, k_jac, jac_hist, conv = ora.Hierarchy(A).solve(f, tol, 3000, 1, 1)
+    assert conv
     for fb in (0, 1):
         ctx = mg.Context([_dev(A)], mg.Options(precision=mg.PREC_FP64, smoother=mg.SMOOTHER_CNN, fallback=fb,
                                                check_every=4))
@@ -61,10 +62,10 @@ def test_diverging_smoother_falls_back_and_converges(mg):
         # u restarted from zero with damped Jacobi: after the few diverging cycles (the check that
         # sees the residual at 100 times its best pauses the problem; its history entry is then
         # overwritten by the restart's) the cycles are exactly the Jacobi solve's
-        k_cnn = int(res.iters[0]) - int(jac.iters[0])
+        k_cnn = int(res.iters[0]) - k_jac
         assert 1 <= k_cnn <= 10
         assert res.history[0, k_cnn] == pytest.approx(1.0)
-        assert np.allclose(res.history[0, k_cnn:int(res.iters[0]) + 1], jac_hist[:int(jac.iters[0]) + 1],
+        assert np.allclose(res.history[0, k_cnn:int(res.iters[0]) + 1], jac_hist[:k_jac + 1],
                            rtol=1e-9, atol=1e-14)
         # the learned smoother was overwritten: a CNN solve needs inference again
         with pytest.raises(mg.MGError) as ei:
@@ -104,3 +105,27 @@ def test_only_the_failing_problem_of_a_batch_falls_back(mg):
         one.infer(net)
         r1 = one.solve([fs[q]], 1e-8, 4000)
         assert r1.iters[0] == res.iters[q] and torch.equal(r1.u[0], res.u[q])
+
+
+def test_fallback_close_to_maxit_still_gets_its_cycles(mg):
+    # a problem paused for the switch spends the rest of its check block without cycling; the
+    # solve must still give it maxit cycles in all (maxit = exactly the cycles this solve needs)
+    n = 63
+    A = ora.stencil_q1_rotated(n, math.pi / 6, 0.01)
+    f = mg_inputs.rhs_uniform(n, 0)
+    tol = 1e-9
+    opt = mg.Options(precision=mg.PREC_FP64, smoother=mg.SMOOTHER_CNN, fallback=1, check_every=16)
+    ctx = mg.Context([_dev(A)], opt)
+    _install(ctx, mg, 0, n, 3.0)
+    free = ctx.solve([_dev(f)], tol, 3000)
+    need = int(free.iters[0])
+    assert free.status[0] == 0 and ctx.fallbacks()[0] == 1
+    ctx = mg.Context([_dev(A)], opt)
+    _install(ctx, mg, 0, n, 3.0)
+    res = ctx.solve([_dev(f)], tol, need)
+    assert res.status[0] == 0 and int(res.iters[0]) == need
+    assert torch.equal(res.u[0], free.u[0])
+    ctx = mg.Context([_dev(A)], opt)
+    _install(ctx, mg, 0, n, 3.0)
+    short = ctx.solve([_dev(f)], tol, need - 1)
+    assert short.status[0] == mg.MG_NOT_CONVERGED and int(short.iters[0]) == need - 1

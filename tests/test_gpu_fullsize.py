@@ -54,11 +54,12 @@ def test_c2_cycle_matches_oracle_with_the_same_smoother(mg):
         h.set_smoother(l, ctx.smoother(0, l).cpu().numpy())
     e = h.vcycle(f, 1, 1)
     got = u.cpu().numpy()
-    assert np.abs(got - e).max() <= 1e-4 * np.abs(e).max()
+    # mixed-mode iterates: relative gap <= 1e-5 per cycle
+    assert np.linalg.norm(got - e) <= 1e-5 * np.linalg.norm(e)
     # sampled nodes: the tile corners and edges of the fused kernels, one by one
     rng = np.random.default_rng(0)
     for j, i in list(zip(rng.integers(0, n, 64), rng.integers(0, n, 64))) + [(0, 0), (n - 1, n - 1), (63, 64)]:
-        assert abs(got[j, i] - e[j, i]) <= 1e-4 * np.abs(e).max()
+        assert abs(got[j, i] - e[j, i]) <= 1e-5 * np.abs(e).max()
 
 
 def test_c2_headline_solve_true_residual(mg):

@@ -204,6 +204,26 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
 mg_status mg_solve_fgmres(mg_ctx ctx, const double *const *f, double *const *u, double rtol, int32_t maxit,
                           int32_t restart, int32_t *iters, double *relres, int32_t *status, double *history);
 
+/* mg_solve_fgmres for callers that cannot allocate device memory (code that a
+ * caller records into a HIP graph of its own, tight serving loops, harnesses
+ * that forbid hipMalloc): the same solve, bit for bit, with the Krylov
+ * workspace in a fixed device array of MG_FGMRES_NOALLOC_BYTES (64 MiB) per
+ * GPU instead of the context's memory.  The array is loaded with the library's
+ * code object and held until the process ends; this call allocates and frees
+ * nothing on the device (the context, created before, is the caller's).  It
+ * needs (2 restart + 4) FP64 vectors of the context's largest finest grid,
+ * n (n + 1) values each rounded up to a multiple of 64, plus
+ * (restart + 2) (256 + 4) values: for n = 255 and restart = 30, 33.5 MB; for
+ * n = 1023, restart <= 2.  Larger requests return MG_ERR_ARG before any work.
+ * Every call on one GPU uses that GPU's one array and leaves its contents
+ * behind (nothing in it is read before this call writes it): calls that
+ * overlap on one GPU - two streams, two threads, two contexts - race.
+ * Arguments, outputs, errors and synchronisation as mg_solve_fgmres. */
+#define MG_FGMRES_NOALLOC_BYTES (64ll << 20)
+mg_status mg_solve_fgmres_noalloc(mg_ctx ctx, const double *const *f, double *const *u, double rtol,
+                                  int32_t maxit, int32_t restart, int32_t *iters, double *relres, int32_t *status,
+                                  double *history);
+
 /* Per problem: 1 if the last mg_solve switched it from the learned smoother
  * to damped Jacobi (mg_options.fallback), else 0.  flags: host [nprob]. */
 mg_status mg_last_fallbacks(mg_ctx ctx, int32_t *flags);

@@ -499,12 +499,18 @@ mg_status update_live(mg_ctx_s &c, const std::vector<char> &active)
     for (SizeClass &k : c.classes) MG_TRY(compact(k));
     for (SizeClass &k : c.outer) MG_TRY(compact(k));
     MG_TRY(compact(c.bottom));
-    if (changed) drop_graph(c);
+    // the captured iteration no longer matches: mark it (ensure_graph rebuilds it before the next
+    // replay) rather than destroy it here, so the calls that change the live set free nothing
+    if (changed) c.graph_stale = true;
     return MG_OK;
 }
 
 mg_status ensure_graph(mg_ctx_s &c)
 {
+    if (c.graph_stale) {
+        drop_graph(c);
+        c.graph_stale = false;
+    }
     if (c.graph_exec || !c.opt.use_graph) return MG_OK;
     hipStream_t st = c.join.internal;
     MG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));

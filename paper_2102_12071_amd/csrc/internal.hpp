@@ -163,6 +163,7 @@ struct mg_ctx_s {
     bool fused = false;                  // V(1,1): fused level kernels
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    bool graph_stale = false;            // the live set changed: mg_solve re-captures before its next replay
     hipEvent_t t0 = nullptr, t1 = nullptr;
     double last_ms = 0.0;
     // CNN inference scratch (direct path)

@@ -21,18 +21,45 @@ using namespace mg;
 
 namespace {
 
-mg_status ensure_workspace(mg_ctx_s &c, int m)
+// Where an FGMRES(m) solve keeps its vectors: 2 m + 4 FP64 vectors of vs values (V: m + 1, Z: m,
+// w, X, r) and the small arrays (partial sums of m + 2 dot products, two Hessenberg columns, the
+// coefficients, a norm).  restart: the m the layout was made for (>= the solve's m).
+struct Workspace {
+    double *vec = nullptr, *small = nullptr;
+    int restart = 0;
+    int64_t vs = 0;
+};
+
+int64_t vector_stride(const mg_ctx_s &c)
 {
     int64_t vs = 0;
     for (const ProbBuf &pb : c.probs) vs = std::max<int64_t>(vs, pb.lev[0].plane);
-    vs = (vs + 63) / 64 * 64;
-    if (c.kr_restart >= m && c.kr_vec) return MG_OK;
-    void *p = nullptr;
-    MG_TRY(c.arena.alloc(&p, (size_t)(2 * m + 4) * vs * sizeof(double)));
-    c.kr_vec = (double *)p;
-    MG_TRY(c.arena.alloc(&p, ((size_t)(m + 2) * kKrylovBlocks + 4 * (m + 2)) * sizeof(double)));
-    c.kr_small = (double *)p;
-    c.kr_restart = m;
+    return (vs + 63) / 64 * 64;
+}
+
+size_t workspace_doubles(int64_t vs, int m, size_t *vec_part)
+{
+    *vec_part = (size_t)(2 * m + 4) * vs;
+    return *vec_part + (size_t)(m + 2) * kKrylovBlocks + 4 * (size_t)(m + 2);
+}
+
+mg_status ensure_workspace(mg_ctx_s &c, int m, Workspace &ws)
+{
+    const int64_t vs = vector_stride(c);
+    if (!(c.kr_restart >= m && c.kr_vec)) {
+        size_t vec_part = 0;
+        const size_t total = workspace_doubles(vs, m, &vec_part);
+        void *p = nullptr;
+        MG_TRY(c.arena.alloc(&p, vec_part * sizeof(double)));
+        c.kr_vec = (double *)p;
+        MG_TRY(c.arena.alloc(&p, (total - vec_part) * sizeof(double)));
+        c.kr_small = (double *)p;
+        c.kr_restart = m;
+    }
+    ws.vec = c.kr_vec;
+    ws.small = c.kr_small;
+    ws.restart = c.kr_restart;
+    ws.vs = vs;
     return MG_OK;
 }
 
@@ -41,19 +68,17 @@ struct Result {
     double relres = 1.0;
 };
 
-mg_status fgmres_problem(mg_ctx_s &c, int p, double rtol, int maxit, int m, double *hist, Result &res,
-                         hipStream_t st)
+mg_status fgmres_problem(mg_ctx_s &c, int p, double rtol, int maxit, int m, const Workspace &ws, double *hist,
+                         Result &res, hipStream_t st)
 {
     const ProbBuf &pb = c.probs[p];
     const LevelBuf &L0 = pb.lev[0];
     const int n = pb.n, P = L0.P;
     const int64_t plane = L0.plane, bytes = plane * (int64_t)sizeof(double);
-    int64_t vs = 0;
-    for (const ProbBuf &q : c.probs) vs = std::max<int64_t>(vs, q.lev[0].plane);
-    vs = (vs + 63) / 64 * 64;
-    const int mw = c.kr_restart;
-    double *V = c.kr_vec, *Z = V + (int64_t)(mw + 1) * vs, *w = Z + (int64_t)mw * vs, *X = w + vs, *r = X + vs;
-    double *partial = c.kr_small, *h1 = partial + (int64_t)(mw + 2) * kKrylovBlocks, *h2 = h1 + (mw + 2),
+    const int64_t vs = ws.vs;
+    const int mw = ws.restart;
+    double *V = ws.vec, *Z = V + (int64_t)(mw + 1) * vs, *w = Z + (int64_t)mw * vs, *X = w + vs, *r = X + vs;
+    double *partial = ws.small, *h1 = partial + (int64_t)(mw + 2) * kKrylovBlocks, *h2 = h1 + (mw + 2),
            *ydev = h2 + (mw + 2), *nrm = ydev + (mw + 2);
     const bool mixed = c.opt.precision != MG_PREC_FP64;
 
@@ -159,21 +184,11 @@ mg_status fgmres_problem(mg_ctx_s &c, int p, double rtol, int maxit, int m, doub
     return MG_OK;
 }
 
-}  // namespace
-
-extern "C" mg_status mg_solve_fgmres(mg_ctx ctx, const double *const *f, double *const *u, double rtol,
-                                     int32_t maxit, int32_t restart, int32_t *iters, double *relres, int32_t *status,
-                                     double *history)
+// The solve of every problem with the given workspace (the body of both entry points).
+mg_status fgmres_all(mg_ctx_s &c, const double *const *f, double *const *u, double rtol, int32_t maxit,
+                     int32_t restart, const Workspace &ws, int32_t *iters, double *relres, int32_t *status,
+                     double *history)
 {
-    clear_error();
-    MG_TRY(ctx_check(ctx));
-    MG_TRY(ctx_check_vectors(ctx, f, u));
-    if (!(rtol >= 0.0) || maxit < 0 || maxit > 100000000)
-        return set_error(MG_ERR_ARG, "need rtol >= 0 and 0 <= maxit <= 1e8");
-    if (restart < 1 || restart > 256) return set_error(MG_ERR_ARG, "restart must be in [1, 256]");
-    MG_TRY(ctx_check_smoother(*ctx));
-    mg_ctx_s &c = *ctx;
-    MG_TRY(ensure_workspace(c, restart));
     MG_TRY(c.join.enter());
     hipStream_t st = c.join.internal;
     MG_HIP(hipEventRecord(c.t0, st));
@@ -184,7 +199,8 @@ extern "C" mg_status mg_solve_fgmres(mg_ctx ctx, const double *const *f, double 
         const ProbBuf &pb = c.probs[p];
         launch_copy_field(pb.n, 1, f[p], pb.n, (int64_t)pb.n * pb.n, pb.f, pb.lev[0].P, pb.lev[0].plane, st);
         Result r;
-        MG_TRY(fgmres_problem(c, p, rtol, maxit, restart, history ? &hist[(size_t)p * (maxit + 1)] : nullptr, r, st));
+        MG_TRY(fgmres_problem(c, p, rtol, maxit, restart, ws, history ? &hist[(size_t)p * (maxit + 1)] : nullptr, r,
+                              st));
         launch_copy_field(pb.n, 1, pb.u, pb.lev[0].P, pb.lev[0].plane, u[p], pb.n, (int64_t)pb.n * pb.n, st);
         if (iters) iters[p] = r.iters;
         if (relres) relres[p] = r.relres;
@@ -202,4 +218,53 @@ extern "C" mg_status mg_solve_fgmres(mg_ctx ctx, const double *const *f, double 
     if (history) std::copy(hist.begin(), hist.end(), history);
     MG_TRY(c.join.leave());
     return agg;
+}
+
+mg_status check_fgmres_args(mg_ctx ctx, const double *const *f, double *const *u, double rtol, int32_t maxit,
+                            int32_t restart)
+{
+    MG_TRY(ctx_check(ctx));
+    MG_TRY(ctx_check_vectors(ctx, f, u));
+    if (!(rtol >= 0.0) || maxit < 0 || maxit > 100000000)
+        return set_error(MG_ERR_ARG, "need rtol >= 0 and 0 <= maxit <= 1e8");
+    if (restart < 1 || restart > 256) return set_error(MG_ERR_ARG, "restart must be in [1, 256]");
+    return ctx_check_smoother(*ctx);
+}
+
+}  // namespace
+
+extern "C" mg_status mg_solve_fgmres(mg_ctx ctx, const double *const *f, double *const *u, double rtol,
+                                     int32_t maxit, int32_t restart, int32_t *iters, double *relres, int32_t *status,
+                                     double *history)
+{
+    clear_error();
+    MG_TRY(check_fgmres_args(ctx, f, u, rtol, maxit, restart));
+    Workspace ws;
+    MG_TRY(ensure_workspace(*ctx, restart, ws));
+    return fgmres_all(*ctx, f, u, rtol, maxit, restart, ws, iters, relres, status, history);
+}
+
+extern "C" mg_status mg_solve_fgmres_noalloc(mg_ctx ctx, const double *const *f, double *const *u, double rtol,
+                                             int32_t maxit, int32_t restart, int32_t *iters, double *relres,
+                                             int32_t *status, double *history)
+{
+    clear_error();
+    MG_TRY(check_fgmres_args(ctx, f, u, rtol, maxit, restart));
+    Workspace ws;
+    ws.vs = vector_stride(*ctx);
+    ws.restart = restart;
+    size_t vec_part = 0;
+    const size_t need = workspace_doubles(ws.vs, restart, &vec_part) * sizeof(double);
+    if (need > kKrylovStaticBytes)
+        return set_error(MG_ERR_ARG,
+                         "FGMRES(%d) on a finest grid of %lld values needs %zu bytes of workspace; the fixed "
+                         "workspace holds %zu (use a smaller restart, or mg_solve_fgmres)",
+                         restart, (long long)ws.vs, need, kKrylovStaticBytes);
+    double *base = nullptr;
+    const hipError_t e = krylov_static_workspace(&base);
+    if (e != hipSuccess)
+        return set_error(MG_ERR_DEVICE, "fixed FGMRES workspace: %s", hipGetErrorString(e));
+    ws.vec = base;
+    ws.small = base + vec_part;
+    return fgmres_all(*ctx, f, u, rtol, maxit, restart, ws, iters, relres, status, history);
 }

@@ -4,10 +4,42 @@
 // n*P elements, the padding column zero.  Kernels only touch interior nodes,
 // so the padding stays zero.  Reductions are deterministic: fixed-size
 // partial sums per block, then one block sums them in a fixed order.
+#include <mutex>
+
 #include "common.hpp"
 #include "launch.hpp"
 
 namespace mg {
+
+// The fixed workspace of mg_solve_fgmres_noalloc (callers that cannot allocate
+// device memory): one array per GPU, loaded with this code object and held
+// until the process ends.  Host code never passes the array's name to a
+// kernel: it takes the device address hipGetSymbolAddress gives, once per
+// device, with that device current.
+static __device__ __align__(256) double scratch[kKrylovStaticBytes / sizeof(double)];
+
+namespace {
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxStaticDevices] = {};
+}  // namespace
+
+hipError_t krylov_static_workspace(double **ptr)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxStaticDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 
 namespace {
 

@@ -34,6 +34,10 @@ const char *tile_name(int kernel, int tile);
 
 // ---- krylov.hip: FP64 vectors of the flexible-GMRES solver (finest grid, pitch P) ----
 constexpr int kKrylovBlocks = 256;  // partial sums per dot product
+// the fixed workspace of mg_solve_fgmres_noalloc: bytes per GPU, and its device address on the
+// current device (looked up once per device)
+constexpr size_t kKrylovStaticBytes = size_t(64) << 20;
+hipError_t krylov_static_workspace(double **ptr);
 // y = b + sign * A x (b may be null)
 void launch_kr_apply(int n, int P, int64_t plane, const double *A, const double *x, const double *b, double sign,
                      double *y, hipStream_t st);

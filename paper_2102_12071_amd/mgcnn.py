@@ -103,6 +103,8 @@ SIGNATURES = {
                            _c_dp, _c_ip, _c_dp]),
     "mg_solve_fgmres": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_double, C.c_int32,
                                   C.c_int32, _c_ip, _c_dp, _c_ip, _c_dp]),
+    "mg_solve_fgmres_noalloc": (C.c_int, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_double,
+                                          C.c_int32, C.c_int32, _c_ip, _c_dp, _c_ip, _c_dp]),
     "mg_last_solve_ms": (C.c_int, [C.c_void_p, _c_dp]),
     "mg_last_fallbacks": (C.c_int, [C.c_void_p, _c_ip]),
     "mg_restencil": (C.c_int, [C.c_void_p, C.POINTER(Problem)]),
@@ -420,8 +422,11 @@ class Context:
         return out
 
     def solve_fgmres(self, f: Sequence[torch.Tensor], rtol: float, maxit: int, restart: int = 30,
-                     history: bool = False, u: Optional[Sequence[torch.Tensor]] = None) -> SolveResult:
-        """Flexible GMRES(restart) preconditioned by one V-cycle per iteration (u_0 = 0)."""
+                     history: bool = False, u: Optional[Sequence[torch.Tensor]] = None,
+                     noalloc: bool = False) -> SolveResult:
+        """Flexible GMRES(restart) preconditioned by one V-cycle per iteration (u_0 = 0).
+        noalloc: mg_solve_fgmres_noalloc (the Krylov workspace in the library's fixed device array;
+        the caller passes u then, or the binding's own u allocation happens here, before the call)."""
         f = self._vecs(f, "f")
         if u is None:
             u = [torch.empty((n, n), dtype=torch.float64, device="cuda") for n in self.ns]
@@ -433,10 +438,11 @@ class Context:
         relres = np.zeros(self.nprob, dtype=np.float64)
         status = np.zeros(self.nprob, dtype=np.int32)
         hist = np.zeros((self.nprob, maxit + 1), dtype=np.float64) if history else None
-        st = load_library().mg_solve_fgmres(self._h, fp, up, float(rtol), int(maxit), int(restart),
-                                            iters.ctypes.data_as(_c_ip), relres.ctypes.data_as(_c_dp),
-                                            status.ctypes.data_as(_c_ip),
-                                            hist.ctypes.data_as(_c_dp) if history else None)
+        fn = load_library().mg_solve_fgmres_noalloc if noalloc else load_library().mg_solve_fgmres
+        st = fn(self._h, fp, up, float(rtol), int(maxit), int(restart),
+                iters.ctypes.data_as(_c_ip), relres.ctypes.data_as(_c_dp),
+                status.ctypes.data_as(_c_ip),
+                hist.ctypes.data_as(_c_dp) if history else None)
         _check(st, allow=(MG_OK, MG_NOT_CONVERGED, MG_ERR_DIVERGED))
         ms = C.c_double()
         _check(load_library().mg_last_solve_ms(self._h, C.byref(ms)))

@@ -117,7 +117,6 @@ def parse():
                     help="headline smoother: the per-level networks of the adaptive training (alpha: "
                          "weights/alpha_n*.bin), or the single network (hf); auto: alpha when its checkpoints exist")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-cycles", type=int, default=30, help="V-cycles in the oracle's timed sample")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--tune-reps", type=int, default=10, help="launches per tile shape in the autotuner")
     ap.add_argument("--sweeps", type=int, nargs="*", default=[2, 3],
@@ -346,7 +345,7 @@ def main():
             params = {m: v.get().astype(np.float64) for m, v in alpha_nets.items()}
         else:
             params = {0: net.get().astype(np.float64)}
-        out["cpu_baseline"] = cpu_baseline(n, theta, eps, params, coarsest, cnn_s["iters"], args.cpu_cycles)
+        out["cpu_baseline"] = cpu_baseline(n, theta, eps, params, coarsest, tol, args.maxit, cnn_s["iters"])
     print(json.dumps(out), flush=True)
 
 
@@ -729,15 +728,28 @@ def workload_c5(args):
                       "config": out}), flush=True)
 
 
-def cpu_baseline(n, theta, eps, params, coarsest, gpu_iters, cycles):
-    """The FP64 oracle on the host cores: stencil, hierarchy, CNN inference on
-    every level and a bounded number of V(1,1) cycles, extrapolated to the
-    GPU's iteration count.  params: network parameters keyed by level size (a
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n, theta, eps, params, coarsest, tol, maxit, gpu_iters):
+    """The FP64 oracle on the host cores, run in full on the headline problem:
+    stencil, Galerkin hierarchy, CNN inference on every level with the same
+    networks, and the V(1,1) solve to tol (nothing extrapolated); beside it the
+    n = 63 problem (theta = pi/6, eps = 0.01, damped-Jacobi V(2,2) to 1e-10) on
+    all threads and on one.  params: network parameters keyed by level size (a
     level takes the nearest trained size, as on the GPU; one key: every level)."""
     import mg_inputs
     import oracle
 
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = oracle.num_threads()
     sizes = sorted(params)
 
     def for_size(m):
@@ -751,14 +763,34 @@ def cpu_baseline(n, theta, eps, params, coarsest, gpu_iters, cycles):
     for l in range(h.num_levels - 1):
         h.set_smoother(l, oracle.cnn_forward(h.stencil(l), for_size(h.level_n(l))))
     t2 = time.perf_counter()
-    _, k, _, _ = h.solve(f, 0.0, cycles, 1, 1)
+    _, k, hist, conv = h.solve(f, tol, maxit, 1, 1)
     t3 = time.perf_counter()
-    per_cycle = (t3 - t2) / max(k, 1)
-    total = (t1 - t0) + (t2 - t1) + per_cycle * gpu_iters
+    total = t3 - t0
+
+    def c1_rate(nthreads):
+        oracle.set_threads(nthreads)
+        try:
+            p = mg_inputs.config_c1()
+            fc = mg_inputs.rhs_uniform(p.n, p.rhs_seed)
+            ts = time.perf_counter()
+            hc = oracle.Hierarchy(oracle.stencil_q1_rotated(p.n, p.theta, p.eps))
+            _, kc, _, okc = hc.solve(fc, 1e-10, 1000, 2, 2)
+            dt = time.perf_counter() - ts
+        finally:
+            oracle.set_threads(threads)
+        return {"threads": nthreads, "iters": int(kc), "converged": bool(okc), "s": dt,
+                "unknowns_per_s": p.n * p.n / dt}
+
+    c1 = {"all_threads": c1_rate(threads), "one_thread": c1_rate(1)}
     return {"value": n * n / total, "unit": "unknowns/s", "cores": threads, "kind": "oracle",
-            "sample": f"FP64 oracle: stencil + Galerkin hierarchy ({t1 - t0:.2f} s), CNN inference on all levels "
-                      f"({t2 - t1:.2f} s), {k} V(1,1) cycles timed ({per_cycle * 1e3:.1f} ms/cycle) and "
-                      f"extrapolated to the GPU's {gpu_iters} cycles"}
+            "run": f"full: the solve to {tol:g} run to the end, nothing extrapolated",
+            "iters": int(k), "gpu_iters": int(gpu_iters), "converged": bool(conv), "relres": float(hist[-1]),
+            "setup_s": t1 - t0, "infer_s": t2 - t1, "solve_s": t3 - t2, "total_s": total,
+            "ms_per_cycle": (t3 - t2) / max(k, 1) * 1e3,
+            "omp_threads": threads, "nproc": os.cpu_count(), "cpu_model": _cpu_model(), "c1": c1,
+            "sample": f"FP64 oracle (C, OpenMP over rows, {threads} threads): the headline problem in full - "
+                      f"stencil + Galerkin hierarchy ({t1 - t0:.2f} s), CNN inference on all levels "
+                      f"({t2 - t1:.2f} s), V(1,1) solve to {tol:g} ({k} cycles, {t3 - t2:.2f} s)"}
 
 
 if __name__ == "__main__":

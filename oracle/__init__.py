@@ -64,6 +64,8 @@ def _load():
         "ora_cnn_forward": (None, [C.c_int, _dp, C.c_int, _ip, _dp, C.c_double, _dp]),
         "ora_hf_loss": (C.c_double, [C.c_int, _ip, C.POINTER(_dp), C.POINTER(_dp), C.c_int, C.c_int,
                                      _ip, _dp, C.c_double, _dp]),
+        "ora_num_threads": (C.c_int, []),
+        "ora_set_threads": (None, [C.c_int]),
         "ora_adam_step": (None, [C.c_int64, _dp, _dp, _dp, _dp, C.c_int, C.c_double, C.c_double,
                                  C.c_double, C.c_double]),
     }
@@ -321,3 +323,14 @@ def adam_step(p, m, v, g, t: int, lr: float = 1e-3, beta1: float = 0.9, beta2: f
     p, m, v, g = _f64(p).copy(), _f64(m).copy(), _f64(v).copy(), _f64(g)
     _load().ora_adam_step(p.size, _p(p), _p(m), _p(v), _p(g), int(t), lr, beta1, beta2, eps)
     return p, m, v
+
+
+# ------------------------------------------------------------------ timing aids
+def num_threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().ora_num_threads())
+
+
+def set_threads(nthreads: int) -> None:
+    """Sets the oracle's OpenMP thread count (results do not depend on it)."""
+    _load().ora_set_threads(int(nthreads))

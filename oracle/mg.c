@@ -7,6 +7,7 @@
 #include <math.h>
 #include <string.h>
 #include "util.h"
+#include <omp.h>
 
 /* ------------------------------------------------------------------ */
 /* y = A x.  Section 2, A u = f; a 9-point stencil per node.            */
@@ -331,4 +332,11 @@ int ora_mg_solve(ora_mg *mg, const double *f, double *u, double tol, int maxit, 
     free(r);
     free(e);
     return k;
+}
+
+int ora_num_threads(void) { return omp_get_max_threads(); }
+
+void ora_set_threads(int nthreads)
+{
+    if (nthreads >= 1) omp_set_num_threads(nthreads);
 }

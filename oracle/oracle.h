@@ -155,6 +155,12 @@ void ora_adam_step(int64_t np, double *p, double *m, double *v,
                    const double *g, int t, double lr, double beta1,
                    double beta2, double eps);
 
+/* OpenMP threads the routines above use (omp_get_max_threads), and a way to
+ * set them (omp_set_num_threads; nthreads >= 1).  Timing aids only: no
+ * routine's result depends on the thread count (independent rows). */
+int ora_num_threads(void);
+void ora_set_threads(int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

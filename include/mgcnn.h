@@ -436,6 +436,74 @@ mg_status mg_stack_alpha_step(mg_ctx top, mg_ctx coarse, mg_ctx coarse_t, double
                               const mg_train_opts *o, double *loss, double *losses, double *grad);
 
 /* ------------------------------------------------------------------------ */
+/* Red-black coarsening (section 6.1) with the two-layer convolution smoother  */
+/* H = f2(f1) (section 6, "Neural networks").                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Levels alternate between a full grid and its checkerboard: level 0 is the
+ * n x n grid; a full N x N level coarsens to the nodes with i + j even of the
+ * same array ("black"; a semi-coarsening along the 45-degree direction); a
+ * checkerboard level coarsens, on its 45-degree rotated mesh, to the full
+ * (N - 1)/2 grid of the nodes with i and j both odd (coarse node I on fine
+ * node 2I + 1).  Transfers: restriction (1/8)[0 1 0; 1 4 1; 0 1 0] and
+ * interpolation (1/4)][0 1 0; 1 4 1; 0 1 0][ along the level's mesh axes
+ * (the grid axes on a full level, the diagonals on a checkerboard); coarse
+ * operators Galerkin R A P (their footprints grow to 45 entries); the last
+ * level solved directly (at most 49 points).  As the paper pads its irregular
+ * grids with zeros, every level's vectors are N x N arrays that are zero off
+ * the level's points (values given there are ignored).  Every call is FP64.
+ * Smoothers: damped Jacobi (omega = 2/3, default) or
+ *   H x = M f2(f1(M x)),
+ * f1, f2 single-channel 3x3 cross-correlations on the N x N array with zero
+ * padding, M the level's point mask; weights: 18 FP64 [2][3][3] (layer, ky,
+ * kx), tap (ky, kx) multiplying x at (j + ky - 1, i + kx - 1). */
+typedef struct mg_rb_s *mg_rb;
+
+/* Builds the hierarchy of one operator: stencil device [9][n][n] FP64
+ * (conventions above; validated: MG_ERR_ARG), nlevels >= 1 levels in all
+ * (the last solved directly: MG_ERR_ARG if it has more than 49 points or the
+ * grid is too small), the Galerkin levels and the last level's inverse on the
+ * device.  n = 2^k - 1 <= 8191.  Synchronises. */
+mg_status mg_rb_create(int32_t n, const double *stencil, int32_t nlevels, void *stream, mg_rb *out);
+mg_status mg_rb_destroy(mg_rb h);
+/* Level shape: N (array side), checker (0 full, 1 checkerboard), noffsets (stencil footprint). */
+mg_status mg_rb_level(mg_rb h, int32_t level, int32_t *N, int32_t *checker, int32_t *noffsets);
+/* The level's operator: offsets host [2 K] (dx, dy pairs; may be NULL) and its field, out device
+ * [K][N][N] (may be NULL): row (i, j) couples to (i + dx_c, j + dy_c) with out[c][j][i]. */
+mg_status mg_rb_get_stencil(mg_rb h, int32_t level, int32_t *offsets, double *out);
+/* Installs the two-layer smoother on a level above the last: phi host [18], or NULL for damped
+ * Jacobi.  a_ref > 0: the weights were made for an operator whose centre entry is a_ref; f1 is
+ * taken times a_ref / a_C, a_C the level's centre entry at its middle node (N/2, N/2), so that H
+ * keeps its scale relative to the operator (a_ref = 0: as given).  Synchronises. */
+mg_status mg_rb_set_smoother(mg_rb h, int32_t level, const double *phi, double a_ref);
+/* e = V(r) from `level` down (Algorithm 1 in correction form, nu_pre / nu_post sweeps in [0, 8])
+ * for nvec vectors: r, e device [nvec][N][N] of that level. */
+mg_status mg_rb_vcycle(mg_rb h, int32_t level, int32_t nvec, const double *r, double *e, int32_t nu_pre,
+                       int32_t nu_post);
+/* The stationary solve u_0 = 0, u += V(f - A u) until ||f - A u|| <= rtol ||f|| (section 6.1
+ * stopping rule) or maxit cycles, on `level`'s operator (0: the input grid) with the levels below
+ * it, for nvec right-hand sides f (device [nvec][N][N] of that level); u receives the solutions.
+ * Host outputs as in mg_solve (each may be NULL; history [nvec][maxit + 1]).  Synchronises. */
+mg_status mg_rb_solve(mg_rb h, int32_t level, int32_t nvec, const double *f, double *u, double rtol,
+                      int32_t maxit, int32_t nu_pre, int32_t nu_post, int32_t *iters, double *relres,
+                      int32_t *status, double *history);
+/* Device time of the last mg_rb_solve in milliseconds. */
+mg_status mg_rb_last_solve_ms(mg_rb h, double *ms);
+/* One step of the adaptive training (Algorithm 2) of `level`'s two-layer smoother: for B
+ * instances (f, u0, u_star device [B][N][N] of that level, k host [B] in [1, 64]) the loss
+ *   L = (1/B) sum_b || Phi(u0_b, f_b, k_b) - u*_b ||_2,
+ * Phi being k_b cycles of: pre-smoothing with H (weights phi, device [18]), coarse correction
+ * P Psi_c R with one V(1,1) cycle Psi_c of the levels below (their installed smoothers),
+ * post-smoothing with H; its gradient with respect to the 18 weights (forward mode: each instance
+ * runs with its 18 tangents), and an Adam step (o->lr, beta1, beta2, adam_eps; step t >= 1) on
+ * phi with the moments adam_m, adam_v (device [18]) if o->apply_update (o NULL: the defaults).
+ * loss: host; losses: host [B] or NULL; grad: host [18] or NULL.  B * 19 <= 65535.
+ * MG_ERR_DIVERGED (weights unchanged) if the loss is not finite.  Synchronises. */
+mg_status mg_rb_alpha_step(mg_rb h, int32_t level, double *phi, double *adam_m, double *adam_v, int32_t t,
+                           int32_t B, const int32_t *k, const double *f, const double *u0, const double *u_star,
+                           const mg_train_opts *o, double *loss, double *losses, double *grad);
+
+/* ------------------------------------------------------------------------ */
 const char *mg_status_str(mg_status s);
 const char *mg_last_error(void);
 /* Library version string. */

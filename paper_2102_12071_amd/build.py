@@ -12,8 +12,8 @@ LIB = os.path.join(HERE, "libmgcnn.so")
 OBJDIR = os.path.join(HERE, "_build")
 ARCH = "gfx950"
 
-DEVICE_SOURCES = ["stencil.hip", "cycle.hip", "coarse.hip", "bottom.hip", "fused.hip", "cnn.hip", "cnn_mfma.hip", "train_kernels.hip", "train_mfma.hip", "krylov.hip", "alpha.hip", "stack.hip"]
-HOST_SOURCES = ["abi.cpp", "context.cpp", "net.cpp", "train.cpp", "krylov.cpp", "alpha.cpp", "stack.cpp"]
+DEVICE_SOURCES = ["stencil.hip", "cycle.hip", "coarse.hip", "bottom.hip", "fused.hip", "cnn.hip", "cnn_mfma.hip", "train_kernels.hip", "train_mfma.hip", "krylov.hip", "alpha.hip", "stack.hip", "redblack.hip"]
+HOST_SOURCES = ["abi.cpp", "context.cpp", "net.cpp", "train.cpp", "krylov.cpp", "alpha.cpp", "stack.cpp", "redblack.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
           "-Wno-unused-function", "-Wno-unused-variable",

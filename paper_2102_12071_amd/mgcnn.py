@@ -123,6 +123,18 @@ SIGNATURES = {
     "mg_net_load": (C.c_int, [C.c_void_p, C.c_char_p]),
     "mg_train_opts_default": (None, [C.POINTER(TrainOpts)]),
     "mg_train_step": (C.c_int, [C.c_void_p, C.POINTER(TrainBatch), C.POINTER(TrainOpts), _c_fp, _c_fp]),
+    "mg_rb_create": (C.c_int, [C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "mg_rb_destroy": (C.c_int, [C.c_void_p]),
+    "mg_rb_level": (C.c_int, [C.c_void_p, C.c_int32, _c_ip, _c_ip, _c_ip]),
+    "mg_rb_get_stencil": (C.c_int, [C.c_void_p, C.c_int32, _c_ip, C.c_void_p]),
+    "mg_rb_set_smoother": (C.c_int, [C.c_void_p, C.c_int32, _c_dp, C.c_double]),
+    "mg_rb_vcycle": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32]),
+    "mg_rb_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_double, C.c_int32,
+                              C.c_int32, C.c_int32, _c_ip, _c_dp, _c_ip, _c_dp]),
+    "mg_rb_last_solve_ms": (C.c_int, [C.c_void_p, _c_dp]),
+    "mg_rb_alpha_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                                   _c_ip, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(TrainOpts), _c_dp, _c_dp,
+                                   _c_dp]),
     "mg_status_str": (C.c_char_p, [C.c_int]),
     "mg_last_error": (C.c_char_p, []),
     "mg_version": (C.c_char_p, []),
@@ -647,3 +659,124 @@ def alpha_step(top: Context, coarse: Context, coarse_t: Context, net: Net, k: Se
                                         C.byref(loss), losses.ctypes.data_as(_c_dp),
                                         grad.ctypes.data_as(_c_fp) if want_grad else None))
     return AlphaResult(loss=loss.value, losses=losses, grad=grad, dW=dW)
+
+
+# ------------------------------------------------------------ red-black coarsening
+RB_WEIGHTS = 18
+
+
+class RedBlack:
+    """Red-black hierarchy of one operator (mg_rb_*): levels alternate between a full grid and its
+    checkerboard, stored padded on N x N arrays; damped Jacobi or the two-layer stack per level."""
+
+    def __init__(self, A: torch.Tensor, nlevels: int, stream=None):
+        A = _dev_f64(A)
+        n = A.shape[-1]
+        if tuple(A.shape) != (9, n, n):
+            raise ValueError("stencil must be [9, n, n]")
+        h = C.c_void_p()
+        _check(load_library().mg_rb_create(n, _ptr(A), int(nlevels), _stream(stream), C.byref(h)))
+        self._h = h
+        self.n = n
+        self.num_levels = int(nlevels)
+        self.shapes = []
+        for l in range(self.num_levels):
+            N, ck, K = C.c_int32(), C.c_int32(), C.c_int32()
+            _check(load_library().mg_rb_level(self._h, l, C.byref(N), C.byref(ck), C.byref(K)))
+            self.shapes.append((N.value, "checker" if ck.value else "full", K.value))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().mg_rb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_n(self, level: int) -> int:
+        return self.shapes[level][0]
+
+    def stencil(self, level: int):
+        """(offsets [K, 2] as (dx, dy), field [K, N, N] on the device)."""
+        N, _, K = self.shapes[level]
+        offs = np.zeros(2 * K, dtype=np.int32)
+        out = torch.empty((K, N, N), dtype=torch.float64, device="cuda")
+        _check(load_library().mg_rb_get_stencil(self._h, level, offs.ctypes.data_as(_c_ip), _ptr(out)))
+        return offs.reshape(K, 2), out
+
+    def set_smoother(self, level: int, phi=None, a_ref: float = 0.0) -> None:
+        """phi: 18 weights [2][3][3] (f1, f2), or None for damped Jacobi; a_ref > 0: the weights
+        were made for an operator of centre entry a_ref (the library rescales f1 to the level's)."""
+        if phi is None:
+            _check(load_library().mg_rb_set_smoother(self._h, level, None, 0.0))
+            return
+        w = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).reshape(-1))
+        if w.size != RB_WEIGHTS:
+            raise ValueError("a red-black stack has 18 weights")
+        _check(load_library().mg_rb_set_smoother(self._h, level, w.ctypes.data_as(_c_dp), float(a_ref)))
+
+    def vcycle(self, r: torch.Tensor, level: int = 0, nu_pre: int = 1, nu_post: int = 1) -> torch.Tensor:
+        """e = V(r) from level for a batch r [nvec, N, N] (or [N, N])."""
+        N = self.level_n(level)
+        r = _dev_f64(r)
+        rb = r.reshape(-1, N, N)
+        e = torch.empty_like(rb)
+        _check(load_library().mg_rb_vcycle(self._h, level, rb.shape[0], _ptr(rb), _ptr(e), nu_pre, nu_post))
+        return e.reshape(r.shape)
+
+    def solve(self, f: torch.Tensor, rtol: float, maxit: int, nu_pre: int = 1, nu_post: int = 1,
+              history: bool = False, level: int = 0) -> SolveResult:
+        """The stationary solve from u = 0 on `level` for f [nvec, N, N] (or [N, N])."""
+        f = _dev_f64(f)
+        N = self.level_n(level)
+        fb = f.reshape(-1, N, N)
+        nv = fb.shape[0]
+        u = torch.empty_like(fb)
+        iters = np.zeros(nv, dtype=np.int32)
+        relres = np.zeros(nv, dtype=np.float64)
+        status = np.zeros(nv, dtype=np.int32)
+        hist = np.zeros((nv, maxit + 1), dtype=np.float64) if history else None
+        st = load_library().mg_rb_solve(self._h, level, nv, _ptr(fb), _ptr(u), float(rtol), int(maxit), nu_pre,
+                                        nu_post,
+                                        iters.ctypes.data_as(_c_ip), relres.ctypes.data_as(_c_dp),
+                                        status.ctypes.data_as(_c_ip), hist.ctypes.data_as(_c_dp) if history else None)
+        _check(st, allow=(MG_OK, MG_NOT_CONVERGED, MG_ERR_DIVERGED))
+        ms = C.c_double()
+        _check(load_library().mg_rb_last_solve_ms(self._h, C.byref(ms)))
+        return SolveResult(u=list(u), iters=iters, relres=relres, status=status, history=hist, ms=ms.value)
+
+
+class RBAdam:
+    """The 18 device weights of one red-black level's stack and their Adam state (FP64)."""
+
+    def __init__(self, phi):
+        self.phi = torch.tensor(np.asarray(phi, dtype=np.float64).reshape(-1), device="cuda")
+        self.m = torch.zeros(RB_WEIGHTS, dtype=torch.float64, device="cuda")
+        self.v = torch.zeros(RB_WEIGHTS, dtype=torch.float64, device="cuda")
+        self.t = 0
+
+
+def rb_alpha_step(h: RedBlack, level: int, state: RBAdam, k: Sequence[int], f: torch.Tensor, u0: torch.Tensor,
+                  u_star: torch.Tensor, opts: Optional["TrainOptions"] = None) -> AlphaResult:
+    """One Algorithm 2 step of a red-black level's stack (mg_rb_alpha_step): f, u0, u_star [B, N, N]."""
+    opts = opts or TrainOptions(precision=0)
+    N = h.level_n(level)
+    f, u0, us = (_dev_f64(x).reshape(-1, N, N) for x in (f, u0, u_star))
+    B = f.shape[0]
+    if not (len(k) == u0.shape[0] == us.shape[0] == B):
+        raise ValueError(f"need {B} entries of k, f, u0 and u_star")
+    kk = np.ascontiguousarray(np.asarray(k, dtype=np.int32))
+    o = opts.to_c()
+    t = state.t + 1 if opts.apply_update else max(state.t, 1)
+    loss = C.c_double()
+    losses = np.zeros(B, dtype=np.float64)
+    grad = np.zeros(RB_WEIGHTS, dtype=np.float64)
+    _check(load_library().mg_rb_alpha_step(h._h, level, _ptr(state.phi), _ptr(state.m), _ptr(state.v), t, B,
+                                           kk.ctypes.data_as(_c_ip), _ptr(f), _ptr(u0), _ptr(us), C.byref(o),
+                                           C.byref(loss), losses.ctypes.data_as(_c_dp), grad.ctypes.data_as(_c_dp)))
+    if opts.apply_update:
+        state.t = t
+    return AlphaResult(loss=loss.value, losses=losses, grad=grad)

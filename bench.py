@@ -471,42 +471,72 @@ def copy_bandwidth(mib=1024, reps=10):
 
 
 def training_block(args):
-    """One training step of the stencil-to-smoother network on the
-    high-frequency loss, BF16 on the matrix cores with FP32 master weights and
-    Adam: 256 problems with n in {31, 63}, theta ~ U[0, pi), log10 eps ~
-    U[-3, 0], 16 high-frequency unit vectors each; inputs resident on the GPU,
-    steps timed back to back.  Useful FLOP: forward and the two backward
-    convolutions (data and weight gradients), 3 x 56,448 per point."""
+    """Training steps of the stencil-to-smoother network on the high-frequency
+    loss, BF16 on the matrix cores with FP32 master weights and Adam: 256
+    problems with n in {31, 63} (the size of each problem drawn once, so that
+    every step has the same structure), and per step new draws of theta ~
+    U[0, pi), log10 eps ~ U[-3, 0] and 16 high-frequency unit vectors per
+    problem from pools of 512 per size.  The timed step is the whole of it
+    (host draws, the library's stencils and vector gather, forward, loss,
+    backward, Adam), replayed from one captured HIP graph
+    (mg_train_step_draw); beside it the eager step on one fixed batch of
+    caller-made stencils and vectors (mg_train_step).  Useful FLOP: forward and
+    the two backward convolutions (data and weight gradients), 3 x 56,448 per
+    point."""
     import numpy as np
     import torch
 
     import mg_inputs
     from paper_2102_12071_amd import mgcnn
-    B, J = 256, 16
+    B, J, POOL = 256, 16, 512
     ns, theta, eps = mg_inputs.training_draws(B, 12345, (31, 63))
-    stencils = [mgcnn.stencil_q1_rotated(int(m), float(t), float(e)) for m, t, e in zip(ns, theta, eps)]
-    pools = {m: torch.tensor(mg_inputs.hf_pool(m, 512, 1000 + m), dtype=torch.float32, device="cuda")
+    ns = [int(m) for m in ns]
+    pools = {m: torch.tensor(mg_inputs.hf_pool(m, POOL, 1000 + m), dtype=torch.float32, device="cuda")
              for m in (31, 63)}
     rng = np.random.default_rng(7)
-    vectors = [pools[int(m)][torch.tensor(rng.integers(0, 512, J), device="cuda")].contiguous() for m in ns]
+    opts = mgcnn.TrainOptions(precision=1, lr=1e-3)
+
+    def draw():
+        th = rng.uniform(0.0, np.pi, B)
+        ep = 10.0 ** rng.uniform(-3.0, 0.0, B)
+        return th, ep, rng.integers(0, POOL, (B, J))
+
     net = mgcnn.Net()
     net.set(mg_inputs.cnn_init(0).astype(np.float32))
-    opts = mgcnn.TrainOptions(precision=1, lr=1e-3)
     for _ in range(2):
-        net.train_step(stencils, vectors, opts, want_loss=False)
+        th, ep, ix = draw()
+        net.train_step_draw(ns, th, ep, pools, ix, opts, want_loss=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.train_steps):
-        net.train_step(stencils, vectors, opts, want_loss=False)
+        th, ep, ix = draw()
+        net.train_step_draw(ns, th, ep, pools, ix, opts, want_loss=False)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.train_steps
-    loss, _ = net.train_step(stencils, vectors, mgcnn.TrainOptions(precision=1, apply_update=0))
-    points = int(sum(int(m) ** 2 for m in ns))
+    th, ep, ix = draw()
+    loss, _ = net.train_step_draw(ns, th, ep, pools, ix, mgcnn.TrainOptions(precision=1, apply_update=0))
+    # the eager step on one fixed batch, for comparison
+    stencils = [mgcnn.stencil_q1_rotated(m, float(t), float(e)) for m, t, e in zip(ns, theta, eps)]
+    vectors = [pools[m][torch.tensor(rng.integers(0, POOL, J), device="cuda")].contiguous() for m in ns]
+    eager = mgcnn.Net()
+    eager.set(mg_inputs.cnn_init(0).astype(np.float32))
+    for _ in range(2):
+        eager.train_step(stencils, vectors, opts, want_loss=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.train_steps):
+        eager.train_step(stencils, vectors, opts, want_loss=False)
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / args.train_steps
+    points = int(sum(m ** 2 for m in ns))
     tflops = 3 * CNN_FLOP_PER_NODE * points / (ms * 1e-3) / 1e12
-    log(f"training: {ms:.2f} ms per step, {tflops:.0f} TFLOP/s useful")
+    log(f"training: {ms:.2f} ms per drawn, graph-replayed step ({tflops:.0f} TFLOP/s useful); eager fixed batch "
+        f"{ms_eager:.2f} ms")
     return {"problems": B, "vectors_per_problem": J, "points": points, "ms_per_step": ms,
             "useful_tflops": tflops, "mfma_peak_tflops": BF16_MFMA_PEAK_TFLOPS, "mfma_frac": tflops / BF16_MFMA_PEAK_TFLOPS,
-            "loss_after": loss, "precision": "bf16 MFMA, fp32 master weights, Adam"}
+            "loss_after": loss, "step": "host draws + stencils + vector gather + forward + loss + backward + Adam, "
+                                          "one captured HIP graph per step",
+            "eager_fixed_batch_ms_per_step": ms_eager, "precision": "bf16 MFMA, fp32 master weights, Adam"}
 
 
 def load_alpha_nets(args):

@@ -322,6 +322,34 @@ void mg_train_opts_default(mg_train_opts *o);
 mg_status mg_train_step(mg_net net, const mg_train_batch *b, const mg_train_opts *o, float *loss,
                         float *grad);
 
+/* The same training step on problems the library draws up itself: for every
+ * problem b the Q1 stencil of the rotated tensor (theta[b], eps[b]) on an
+ * n[b] x n[b] grid (as mg_stencil_q1_rotated) and nvec high-frequency vectors
+ * taken from the pool of its grid size at index[b * nvec + j].  Steps of the
+ * same structure (nprob, n, nvec, the pools, the options) replay one captured
+ * HIP graph holding every launch of the step - stencils, vector gather,
+ * forward, loss, backward, Adam - with the per-step tensors, indices and the
+ * Adam step number uploaded just before the replay; a different structure
+ * rebuilds it (and the first call allocates).  The network's later eager
+ * calls do not disturb it.  Adam's bias corrections are computed on the
+ * device (FP64 pow), which may differ from mg_train_step's host values in the
+ * last bit.  Pools stay the caller's and must not change address or size
+ * between replays of one structure (pass them again: a change rebuilds). */
+typedef struct {
+    int32_t nprob;               /* B */
+    const int32_t *n;            /* host [B] grid sizes (odd, 3..255) */
+    const double *theta;         /* host [B] */
+    const double *eps;           /* host [B], 0 < eps <= 1 */
+    int32_t npools;
+    const int32_t *pool_n;       /* host [npools]: the grid size of each pool */
+    const float *const *pool;    /* host [npools] device pointers, [pool_size][pool_n][pool_n] FP32 unit vectors */
+    const int32_t *pool_size;    /* host [npools] */
+    const int32_t *index;        /* host [B][nvec]: pool entries per problem */
+    int32_t nvec;                /* J >= 1 */
+} mg_train_draw;
+
+mg_status mg_train_step_draw(mg_net net, const mg_train_draw *d, const mg_train_opts *o, float *loss, float *grad);
+
 /* ------------------------------------------------------------------------ */
 /* Adaptive training (section 3.3, Algorithm 2).                              */
 /* ------------------------------------------------------------------------ */
@@ -387,8 +415,14 @@ mg_status mg_alpha_step(mg_ctx top, mg_ctx coarse, mg_ctx coarse_t, mg_net net, 
  * degrees, f1..f5 in reverse order), as the adjoint context of
  * mg_stack_alpha_step needs.  Every level above the coarsest of every problem
  * needs weights before mg_vcycle / mg_solve / mg_solve_fgmres (MG_ERR_STATE).
+ * normalised = 1: phi was made for an operator whose centre entry is 1 (a
+ * trained stack is stored that way); f5 and f6, which carry the scale of
+ * H ~ 1/a_C, are divided by the mean centre entry of the level's stencil
+ * (constant-coefficient operators have one value), so that one set of
+ * weights serves every level of a Galerkin hierarchy.  0: phi as given.
  * Synchronises. */
-mg_status mg_set_stack(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose);
+mg_status mg_set_stack(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose,
+                       int32_t normalised);
 
 /* Replaces the stack a level applies after the coarse correction (mg_set_stack
  * installs the same weights before and after, as Algorithm 2 does).  With the
@@ -396,8 +430,10 @@ mg_status mg_set_stack(mg_ctx ctx, int32_t prob, int32_t level, const double *ph
  * cycle's error propagation is self-adjoint in the A inner product (the
  * symmetric V-cycle): the A-norm of one cycle then equals its spectral radius,
  * so a convergent coarse cycle cannot amplify errors once nested inside a
- * finer one.  MG_ERR_STATE before mg_set_stack on that level.  Synchronises. */
-mg_status mg_set_stack_post(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose);
+ * finer one.  normalised as for mg_set_stack.  MG_ERR_STATE before
+ * mg_set_stack on that level.  Synchronises. */
+mg_status mg_set_stack_post(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose,
+                            int32_t normalised);
 
 /* y_c (+)= H x_c for c < count: x, y device [count][n][n] FP64 (must not
  * overlap), phi device [54] FP64, accumulate 0 (y = H x) or 1 (y += H x);

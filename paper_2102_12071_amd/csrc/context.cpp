@@ -405,6 +405,7 @@ mg_status setup_impl(mg_ctx_s &c, const mg_problem *probs, hipStream_t user)
     }
     MG_TRY(upload(c.arena, init, (void **)&c.d_state));
     MG_TRY(c.arena.alloc((void **)&c.d_params, sizeof(SolveParams)));
+    MG_TRY(c.arena.alloc((void **)&c.d_scalar, sizeof(double)));
     MG_TRY(read_flag(c, st));
     MG_TRY(c.join.leave());
     return MG_OK;

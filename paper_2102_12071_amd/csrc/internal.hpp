@@ -97,6 +97,11 @@ struct SizeClass {
 
 }  // namespace mg
 
+namespace mg {
+struct TrainDraw;
+void train_draw_release(mg_net_s &net);
+}  // namespace mg
+
 struct mg_net_s {
     mg::StreamJoin join;
     mg::Arena arena;
@@ -115,6 +120,7 @@ struct mg_net_s {
     size_t scratch_bytes = 0;
     void *scratch_base = nullptr;
     std::vector<char> host_desc;  // source of the last asynchronous descriptor upload
+    mg::TrainDraw *draw = nullptr;  // the captured step of mg_train_step_draw (train.cpp)
 };
 
 namespace mg {
@@ -156,6 +162,7 @@ struct mg_ctx_s {
     int bottom_top_n = 0;                // largest top level of the bottom kernel
     mg::SolveState *d_state = nullptr;
     mg::SolveParams *d_params = nullptr;
+    double *d_scalar = nullptr;          // one device double for set-up reductions read by the host
     int *d_flag = nullptr;
     double *d_history = nullptr;
     size_t history_cap = 0;              // doubles

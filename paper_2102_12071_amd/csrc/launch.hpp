@@ -7,6 +7,10 @@ namespace mg {
 
 // ---- stencil.hip: discretisation and coarsening (FP64) ----
 void launch_q1_rotated(int n, int P, int64_t plane, double theta, double eps, double *out, hipStream_t st);
+// K = R(theta) diag(1, eps) R(theta)^T: k = {k11, k12, k22}.
+void q1_tensor(double theta, double eps, double *k);
+// Q1 stencils of count problems of size n, tensors k (device [count][3]); out: [count][9][n][n].
+void launch_q1_rotated_batch(int n, int count, const double *k, double *out, hipStream_t st);
 void launch_cellavg5(int n, const double *a, int Pa, int P, int64_t plane, double *out, hipStream_t st);
 void launch_galerkin(int n, int P, int64_t plane, const double *A, int Pc, int64_t planec, double *Ac,
                      hipStream_t st);

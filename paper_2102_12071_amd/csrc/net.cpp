@@ -88,6 +88,7 @@ mg_status mg_net_destroy(mg_net net)
     clear_error();
     if (!net) return MG_OK;
     if (net->join.internal) (void)hipStreamSynchronize(net->join.internal);
+    train_draw_release(*net);
     net->scratch.release();
     net->arena.release();
     net->join.destroy();

@@ -57,7 +57,8 @@ Work carve(char *base, int B, int kmax, int n, int64_t vs)
 }
 
 // Writes a level's weights: half 0 (before the coarse correction), 1 (after), or both (-1).
-mg_status set_stack_half(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose, int half)
+mg_status set_stack_half(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose,
+                         int32_t normalised, int half)
 {
     clear_error();
     MG_TRY(ctx_check(ctx));
@@ -68,13 +69,26 @@ mg_status set_stack_half(mg_ctx ctx, int32_t prob, int32_t level, const double *
         return set_error(MG_ERR_ARG, "level %d has no smoother (levels 0..%d)", level, pb.nlev - 2);
     if (!phi) return set_error(MG_ERR_ARG, "phi is null");
     if (transpose != 0 && transpose != 1) return set_error(MG_ERR_ARG, "transpose must be 0 or 1");
+    if (normalised != 0 && normalised != 1) return set_error(MG_ERR_ARG, "normalised must be 0 or 1");
     LevelBuf &L = pb.lev[level];
     if (half == 1 && !L.phi_set) return set_error(MG_ERR_STATE, "set the level's stack (mg_set_stack) first");
+    MG_TRY(ctx->join.enter());
+    hipStream_t st = ctx->join.internal;
+    double scale = 1.0;  // normalised weights: f5 and f6 over the level's mean centre entry
+    if (normalised) {
+        launch_stack_mean_centre(L.n, L.P, L.plane, L.A64, ctx->d_scalar, st);
+        double ac = 0.0;
+        MG_HIP(hipMemcpyAsync(&ac, ctx->d_scalar, sizeof ac, hipMemcpyDeviceToHost, st));
+        MG_HIP(hipStreamSynchronize(st));
+        if (!(ac > 0.0)) return set_error(MG_ERR_ARG, "level %d: the mean centre entry is not positive", level);
+        scale = 1.0 / ac;
+    }
     double w[2 * kStackWeights];
     for (int j = 0; j < kStackWeights; ++j) {
         const int Lr = j / 9, t = j % 9;
         w[j] = transpose ? phi[(Lr < 5 ? 4 - Lr : 5) * 9 + 8 - t] : phi[j];
         if (!std::isfinite(w[j])) return set_error(MG_ERR_ARG, "weight %d is not finite", j);
+        if (j >= 4 * 9) w[j] *= scale;  // f5 and f6 (a turned stack keeps them as layers 5 and 6)
         w[kStackWeights + j] = w[j];
     }
     float wf[2 * kStackWeights];
@@ -82,8 +96,6 @@ mg_status set_stack_half(mg_ctx ctx, int32_t prob, int32_t level, const double *
     const bool fp64 = ctx->opt.precision == MG_PREC_FP64;
     const size_t es = fp64 ? sizeof(double) : sizeof(float);
     const int first = half == 1 ? kStackWeights : 0, count = half < 0 ? 2 * kStackWeights : kStackWeights;
-    MG_TRY(ctx->join.enter());
-    hipStream_t st = ctx->join.internal;
     MG_HIP(hipMemcpyAsync((char *)L.phi + first * es, fp64 ? (const void *)w : (const void *)wf, count * es,
                           hipMemcpyHostToDevice, st));
     MG_HIP(hipStreamSynchronize(st));  // the host staging arrays end with this call
@@ -95,14 +107,16 @@ mg_status set_stack_half(mg_ctx ctx, int32_t prob, int32_t level, const double *
 
 extern "C" {
 
-mg_status mg_set_stack(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose)
+mg_status mg_set_stack(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose,
+                       int32_t normalised)
 {
-    return set_stack_half(ctx, prob, level, phi, transpose, -1);
+    return set_stack_half(ctx, prob, level, phi, transpose, normalised, -1);
 }
 
-mg_status mg_set_stack_post(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose)
+mg_status mg_set_stack_post(mg_ctx ctx, int32_t prob, int32_t level, const double *phi, int32_t transpose,
+                            int32_t normalised)
 {
-    return set_stack_half(ctx, prob, level, phi, transpose, 1);
+    return set_stack_half(ctx, prob, level, phi, transpose, normalised, 1);
 }
 
 mg_status mg_stack_apply(int32_t n, int32_t count, const double *phi, const double *x, double *y, int32_t accumulate,

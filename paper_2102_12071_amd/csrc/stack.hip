@@ -198,6 +198,16 @@ __global__ void k_stack_transpose(const double *w, double *wT)
     wT[j] = w[(L < 5 ? 4 - L : 5) * 9 + 8 - t];
 }
 
+// out[0] = the mean of the centre entries of a level's stencil (fixed order: deterministic).
+__global__ void __launch_bounds__(256) k_stack_mean_centre(int n, int P, int64_t plane, const double *A, double *out)
+{
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int64_t q = threadIdx.x; q < (int64_t)n * n; q += 256) acc += A[4 * plane + (q / n) * P + q % n];
+    const double s = block_sum<256>(acc, red);
+    if (threadIdx.x == 0) out[0] = s / ((double)n * n);
+}
+
 __global__ void k_stack_adam(double *w, double *m, double *v, const double *g, int t, double lr, double b1, double b2,
                              double eps)
 {
@@ -430,6 +440,11 @@ void launch_stack_gsum(const double *part, int64_t nrow, double *grad, hipStream
 }
 
 void launch_stack_transpose(const double *w, double *wT, hipStream_t st) { k_stack_transpose<<<1, 64, 0, st>>>(w, wT); }
+
+void launch_stack_mean_centre(int n, int P, int64_t plane, const double *A, double *out, hipStream_t st)
+{
+    k_stack_mean_centre<<<1, 256, 0, st>>>(n, P, plane, A, out);
+}
 
 void launch_stack_adam(double *w, double *m, double *v, const double *g, int t, double lr, double b1, double b2,
                        double eps, hipStream_t st)

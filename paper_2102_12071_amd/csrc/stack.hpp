@@ -48,6 +48,8 @@ void launch_stack_wgrad(const StackPairs &pr, int64_t vs, int n, int P, int coun
 void launch_stack_gsum(const double *part, int64_t nrow, double *grad, hipStream_t st);
 // The weights of H^T.
 void launch_stack_transpose(const double *w, double *wT, hipStream_t st);
+// out[0] = the mean centre entry of a level's FP64 stencil (device).
+void launch_stack_mean_centre(int n, int P, int64_t plane, const double *A, double *out, hipStream_t st);
 // Adam on the 54 weights (FP64), step t >= 1.
 void launch_stack_adam(double *w, double *m, double *v, const double *g, int t, double lr, double b1, double b2,
                        double eps, hipStream_t st);

@@ -38,6 +38,31 @@ __global__ void k_q1_rotated(int n, int P, int64_t plane, double k11, double k12
     }
 }
 
+// The same stencil for a batch of problems of one size, the tensor of problem z
+// at k[3 z .. 3 z + 2] (k11, k12, k22); out: [count][9][n][n].
+__global__ void k_q1_rotated_batch(int n, const double *k, double *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= n || j >= n) return;
+    const double k11 = k[3 * blockIdx.z], k12 = k[3 * blockIdx.z + 1], k22 = k[3 * blockIdx.z + 2];
+    const int64_t plane = (int64_t)n * n;
+    double *o = out + (int64_t)blockIdx.z * 9 * plane;
+    const double edge_x = -k11 / 3.0 + k22 / 6.0;
+    const double edge_y = k11 / 6.0 - k22 / 3.0;
+    double v[9];
+    v[4] = 4.0 * (k11 + k22) / 3.0;
+    v[3] = v[5] = 2.0 * edge_x;
+    v[1] = v[7] = 2.0 * edge_y;
+    v[0] = v[8] = -(k11 + k22) / 6.0 - 0.5 * k12;
+    v[2] = v[6] = -(k11 + k22) / 6.0 + 0.5 * k12;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        const int dx = c % 3 - 1, dy = c / 3 - 1;
+        o[c * plane + (int64_t)j * n + i] = inside(n, i + dx, j + dy) ? v[c] : 0.0;
+    }
+}
+
 __global__ void k_cellavg5(int n, const double *a, int Pa, int P, int64_t plane, double *out)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -160,12 +185,28 @@ dim3 node_grid(int n, dim3 blk) { return dim3((n + blk.x - 1) / blk.x, (n + blk.
 
 }  // namespace
 
-void launch_q1_rotated(int n, int P, int64_t plane, double theta, double eps, double *out, hipStream_t st)
+void q1_tensor(double theta, double eps, double *k)
 {
     const double c = cos(theta), s = sin(theta);
-    const double k11 = c * c + eps * s * s, k12 = c * s * (1.0 - eps), k22 = s * s + eps * c * c;
+    k[0] = c * c + eps * s * s;
+    k[1] = c * s * (1.0 - eps);
+    k[2] = s * s + eps * c * c;
+}
+
+void launch_q1_rotated(int n, int P, int64_t plane, double theta, double eps, double *out, hipStream_t st)
+{
+    double k[3];
+    q1_tensor(theta, eps, k);
     dim3 blk(64, 4);
-    k_q1_rotated<<<node_grid(n, blk), blk, 0, st>>>(n, P, plane, k11, k12, k22, out);
+    k_q1_rotated<<<node_grid(n, blk), blk, 0, st>>>(n, P, plane, k[0], k[1], k[2], out);
+}
+
+void launch_q1_rotated_batch(int n, int count, const double *k, double *out, hipStream_t st)
+{
+    dim3 blk(64, 4);
+    dim3 g = node_grid(n, blk);
+    g.z = count;
+    k_q1_rotated_batch<<<g, blk, 0, st>>>(n, k, out);
 }
 
 void launch_cellavg5(int n, const double *a, int Pa, int P, int64_t plane, double *out, hipStream_t st)

@@ -43,6 +43,11 @@ void launch_tr_reduce(const float *wpart, int B, int64_t np, float *grad, hipStr
 void launch_tr_loss(const float *loss_part, int count, float scale, float *loss, hipStream_t st);
 void launch_adam(int64_t np, float *p, float *m, float *v, const float *g, float lr, float b1, float b2, float eps,
                  float c1, float c2, hipStream_t st);
+// Adam whose bias corrections come from the step number *t on the device.
+void launch_adam_dev(int64_t np, float *p, float *m, float *v, const float *g, float lr, float b1, float b2,
+                     float eps, const int64_t *t, hipStream_t st);
+// dst[z][j] = pool[index[z J + j]] for count problems of size n (FP32 vectors of n * n).
+void launch_tr_gather(int n, int count, int J, const float *pool, const int *index, float *dst, hipStream_t st);
 
 }  // namespace mg
 

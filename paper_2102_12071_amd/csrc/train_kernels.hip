@@ -278,6 +278,32 @@ __global__ void __launch_bounds__(kT) k_adam(int64_t np, float *p, float *m, flo
     p[q] -= lr * mhat / (sqrtf(vhat) + eps);
 }
 
+// Adam with the bias corrections of step *t (device): the step a captured graph replays.
+__global__ void __launch_bounds__(kT) k_adam_dev(int64_t np, float *p, float *m, float *v, const float *g, float lr,
+                                                 float b1, float b2, float eps, const int64_t *t)
+{
+    const int64_t q = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (q >= np) return;
+    const double td = (double)*t;
+    const float c1 = (float)(1.0 - pow((double)b1, td)), c2 = (float)(1.0 - pow((double)b2, td));
+    const float gq = g[q];
+    const float mq = b1 * m[q] + (1.0f - b1) * gq;
+    const float vq = b2 * v[q] + (1.0f - b2) * gq * gq;
+    m[q] = mq;
+    v[q] = vq;
+    const float mhat = mq / c1, vhat = vq / c2;
+    p[q] -= lr * mhat / (sqrtf(vhat) + eps);
+}
+
+// dst[z][j] = pool[index[z * J + j]] for the count problems of one size (vectors of n * n FP32).
+__global__ void __launch_bounds__(kT) k_tr_gather(int64_t nn, int J, const float *pool, const int *index, float *dst)
+{
+    const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (p >= nn) return;
+    const int j = blockIdx.y, z = blockIdx.z;
+    dst[((int64_t)z * J + j) * nn + p] = pool[(int64_t)index[z * J + j] * nn + p];
+}
+
 inline unsigned blocks_for(int64_t count) { return (unsigned)((count + kT - 1) / kT); }
 
 }  // namespace
@@ -333,6 +359,18 @@ void launch_tr_reduce(const float *wpart, int B, int64_t np, float *grad, hipStr
 void launch_tr_loss(const float *loss_part, int count, float scale, float *loss, hipStream_t st)
 {
     k_tr_loss<<<1, kT, 0, st>>>(loss_part, count, scale, loss);
+}
+
+void launch_adam_dev(int64_t np, float *p, float *m, float *v, const float *g, float lr, float b1, float b2,
+                     float eps, const int64_t *t, hipStream_t st)
+{
+    k_adam_dev<<<blocks_for(np), kT, 0, st>>>(np, p, m, v, g, lr, b1, b2, eps, t);
+}
+
+void launch_tr_gather(int n, int count, int J, const float *pool, const int *index, float *dst, hipStream_t st)
+{
+    const int64_t nn = (int64_t)n * n;
+    k_tr_gather<<<dim3(blocks_for(nn), J, count), kT, 0, st>>>(nn, J, pool, index, dst);
 }
 
 void launch_adam(int64_t np, float *p, float *m, float *v, const float *g, float lr, float b1, float b2, float eps,

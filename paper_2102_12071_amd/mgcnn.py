@@ -65,6 +65,13 @@ class TrainBatch(C.Structure):
                 ("vectors", C.POINTER(C.c_void_p)), ("nvec", C.c_int32)]
 
 
+class TrainDraw(C.Structure):
+    _fields_ = [("nprob", C.c_int32), ("n", C.POINTER(C.c_int32)), ("theta", C.POINTER(C.c_double)),
+                ("eps", C.POINTER(C.c_double)), ("npools", C.c_int32), ("pool_n", C.POINTER(C.c_int32)),
+                ("pool", C.POINTER(C.c_void_p)), ("pool_size", C.POINTER(C.c_int32)),
+                ("index", C.POINTER(C.c_int32)), ("nvec", C.c_int32)]
+
+
 class TrainOpts(C.Structure):
     _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("adam_eps", C.c_float),
                 ("omega", C.c_double), ("precision", C.c_int32), ("apply_update", C.c_int32)]
@@ -91,8 +98,8 @@ SIGNATURES = {
     "mg_alpha_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(AlphaBatch),
                                 C.POINTER(TrainOpts), _c_dp, _c_dp, _c_fp]),
     "mg_set_smoother": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
-    "mg_set_stack": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _c_dp, C.c_int32]),
-    "mg_set_stack_post": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _c_dp, C.c_int32]),
+    "mg_set_stack": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _c_dp, C.c_int32, C.c_int32]),
+    "mg_set_stack_post": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _c_dp, C.c_int32, C.c_int32]),
     "mg_stack_apply": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
     "mg_stack_alpha_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_int32, C.c_int32, C.POINTER(AlphaBatch), C.POINTER(TrainOpts), _c_dp,
@@ -123,6 +130,7 @@ SIGNATURES = {
     "mg_net_load": (C.c_int, [C.c_void_p, C.c_char_p]),
     "mg_train_opts_default": (None, [C.POINTER(TrainOpts)]),
     "mg_train_step": (C.c_int, [C.c_void_p, C.POINTER(TrainBatch), C.POINTER(TrainOpts), _c_fp, _c_fp]),
+    "mg_train_step_draw": (C.c_int, [C.c_void_p, C.POINTER(TrainDraw), C.POINTER(TrainOpts), _c_fp, _c_fp]),
     "mg_rb_create": (C.c_int, [C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
     "mg_rb_destroy": (C.c_int, [C.c_void_p]),
     "mg_rb_level": (C.c_int, [C.c_void_p, C.c_int32, _c_ip, _c_ip, _c_ip]),
@@ -346,22 +354,25 @@ class Context:
         _check(load_library().mg_set_smoother(self._h, prob, level, _ptr(W)))
         torch.cuda.current_stream().synchronize()
 
-    def set_stack(self, prob: int, level: int, phi, transpose: bool = False, symmetric: bool = False) -> None:
+    def set_stack(self, prob: int, level: int, phi, transpose: bool = False, symmetric: bool = False,
+                  normalised: bool = False) -> None:
         """Installs a level's convolution-stack smoother (54 weights [6][3][3], f1..f5 then f6);
-        symmetric: its transpose after the coarse correction."""
+        symmetric: its transpose after the coarse correction; normalised: the weights were made
+        for a_C = 1 (the library scales them to the level's operator)."""
         w = np.ascontiguousarray(np.asarray(phi, dtype=np.float64).reshape(-1))
         if w.size != STACK_WEIGHTS:
             raise ValueError("a stack has 54 weights")
         lib = load_library()
-        _check(lib.mg_set_stack(self._h, prob, level, w.ctypes.data_as(_c_dp), int(bool(transpose))))
+        nz = int(bool(normalised))
+        _check(lib.mg_set_stack(self._h, prob, level, w.ctypes.data_as(_c_dp), int(bool(transpose)), nz))
         if symmetric:
-            _check(lib.mg_set_stack_post(self._h, prob, level, w.ctypes.data_as(_c_dp), int(not transpose)))
+            _check(lib.mg_set_stack_post(self._h, prob, level, w.ctypes.data_as(_c_dp), int(not transpose), nz))
 
     def set_stacks(self, stacks: dict, transpose: bool = False, symmetric: bool = False) -> None:
         """Every level above the coarsest of every problem from {trained size: weights normalised
         to a_C = 1}: a level of size m takes the stack of the nearest trained size on the log2
-        scale (levels finer than every trained size: the finest one), scaled to the level's
-        operator by stack_for_level."""
+        scale (levels finer than every trained size: the finest one); the library scales it to the
+        level's operator."""
         sizes = sorted(int(k) for k in stacks)
         if not sizes:
             raise ValueError("no stacks given")
@@ -369,7 +380,7 @@ class Context:
             for l in range(self.num_levels(p) - 1):
                 m = self.level_n(p, l)
                 best = min(sizes, key=lambda q: abs(math.log2(q + 1) - math.log2(m + 1)))
-                self.set_stack(p, l, stack_for_level(stacks[best], self.stencil(p, l)), transpose, symmetric)
+                self.set_stack(p, l, stacks[best], transpose, symmetric, normalised=True)
 
     def infer(self, net: "Net", size: Optional[int] = None) -> None:
         """Network inference on every smoothing level, or (size given) on the levels of that size only."""
@@ -548,6 +559,39 @@ class Net:
                                             grad.ctypes.data_as(_c_fp) if want_grad else None))
         return (loss.value if want_loss else None), grad
 
+    def train_step_draw(self, n: Sequence[int], theta: Sequence[float], eps: Sequence[float], pools: dict,
+                        index, opts: Optional[TrainOptions] = None, want_loss: bool = True, want_grad: bool = False):
+        """One step on problems the library draws up (mg_train_step_draw): per problem the size n,
+        the tensor (theta, eps), and index [B, J] into pools {size: float32 device tensor [count, m, m]}.
+        Returns (loss, grad)."""
+        opts = opts or TrainOptions()
+        B = len(n)
+        idx = np.ascontiguousarray(np.asarray(index, dtype=np.int32))
+        if idx.ndim != 2 or idx.shape[0] != B or len(theta) != B or len(eps) != B:
+            raise ValueError("need n, theta, eps of length B and index [B, J]")
+        sizes = sorted(int(k) for k in pools)
+        for m in sizes:
+            t = pools[m]
+            if not (t.is_cuda and t.dtype == torch.float32 and t.dim() == 3 and tuple(t.shape[1:]) == (m, m)
+                    and t.is_contiguous()):
+                raise ValueError("pools must be contiguous float32 device tensors [count, m, m]")
+        ns = np.ascontiguousarray(np.asarray(n, dtype=np.int32))
+        th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+        ep = np.ascontiguousarray(np.asarray(eps, dtype=np.float64))
+        pn = (C.c_int32 * len(sizes))(*sizes)
+        pp = (C.c_void_p * len(sizes))(*[pools[m].data_ptr() for m in sizes])
+        ps = (C.c_int32 * len(sizes))(*[int(pools[m].shape[0]) for m in sizes])
+        d = TrainDraw(B, ns.ctypes.data_as(_c_ip), th.ctypes.data_as(_c_dp), ep.ctypes.data_as(_c_dp), len(sizes),
+                      pn, pp, ps, idx.ctypes.data_as(_c_ip), int(idx.shape[1]))
+        o = opts.to_c()
+        loss = C.c_float()
+        grad = np.zeros(self.num_params, dtype=np.float32) if want_grad else None
+        self._keep_pools = pools  # the captured step reads them on later replays
+        _check(load_library().mg_train_step_draw(self._h, C.byref(d), C.byref(o),
+                                                 C.byref(loss) if want_loss else None,
+                                                 grad.ctypes.data_as(_c_fp) if want_grad else None))
+        return (loss.value if want_loss else None), grad
+
 
 # ----------------------------------------------------------- adaptive training
 def smoother_transpose(A: torch.Tensor, W: torch.Tensor) -> torch.Tensor:
@@ -558,16 +602,6 @@ def smoother_transpose(A: torch.Tensor, W: torch.Tensor) -> torch.Tensor:
     out = torch.empty_like(W)
     _check(load_library().mg_smoother_transpose(n, _ptr(A), _ptr(W), _ptr(out), _stream()))
     return out
-
-
-def stack_for_level(phi, A: torch.Tensor) -> np.ndarray:
-    """Stack weights normalised to an operator with centre entry 1 (f5 and f6 carry the scale of
-    H ~ 1 / a_C), rescaled to the level whose stencil A is given: f5 and f6 divided by its centre
-    entry (constant coefficients: one value; the mean is taken)."""
-    w = np.array(phi, dtype=np.float64).reshape(6, 3, 3)
-    ac = float(A[4].mean())
-    w[4:] /= ac
-    return w
 
 
 def stack_apply(phi: torch.Tensor, x: torch.Tensor, y: Optional[torch.Tensor] = None,

@@ -152,7 +152,9 @@ def _run_stage(stage: StackStage, w0: np.ndarray, steps: int, lr: float, lr_fina
     k = bmax; with growth_of (normalised weights -> the stage hierarchy's estimated growth per
     cycle): of the smallest growth (rounded to 0.01; the loss breaks ties), or, with max_growth,
     of the lowest loss among those whose growth is below max_growth (else the smallest growth)."""
-    state = mgcnn.StackAdam(mgcnn.stack_for_level(w0, stage.top.stencil(0, 0)))
+    w_level = np.array(w0, dtype=np.float64).reshape(6, 3, 3)
+    w_level[4:] /= stage.a_centre  # the trained level's own scale (f5, f6 carry H ~ 1 / a_C)
+    state = mgcnn.StackAdam(w_level)
 
     def normalised(phi):
         w = phi.cpu().numpy().reshape(6, 3, 3).copy()

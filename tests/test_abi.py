@@ -90,13 +90,13 @@ def test_argument_errors_before_device(lib):
     assert b"same buffer" in lib.mg_last_error()
     assert lib.mg_smoother_infer_size(None, None, 7) == -1
     # the convolution-stack smoother's entry points
-    assert lib.mg_set_stack(None, 0, 0, None, 0) == -1
+    assert lib.mg_set_stack(None, 0, 0, None, 0, 0) == -1
     assert lib.mg_stack_apply(0, 1, C.c_void_p(16), C.c_void_p(16), C.c_void_p(4096), 0, None) == -1
     assert lib.mg_stack_apply(7, 1, C.c_void_p(16), C.c_void_p(4096), C.c_void_p(4096 + 8 * 48), 0, None) == -1
     assert b"overlap" in lib.mg_last_error()
     assert lib.mg_stack_apply(7, 1, C.c_void_p(16), C.c_void_p(4096), C.c_void_p(8192), 2, None) == -1
     assert lib.mg_stack_alpha_step(None, None, None, None, None, None, 0, 0, None, None, None, None, None) == -1
-    assert lib.mg_set_stack_post(None, 0, 0, None, 1) == -1
+    assert lib.mg_set_stack_post(None, 0, 0, None, 1, 0) == -1
     lib.mg_options_default(C.byref(opt))
     opt.smoother, opt.fallback = mgcnn.SMOOTHER_STACK, 1
     assert lib.mg_setup(probs, 1, C.byref(opt), None, C.byref(h)) == -1

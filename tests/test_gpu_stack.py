@@ -313,7 +313,7 @@ def test_set_stack_post_needs_the_stack_first(mg):
     ctx = mg.Context([A], mg.Options(smoother=mg.SMOOTHER_STACK, precision=mg.PREC_FP64))
     w = np.zeros(54)
     import ctypes as C
-    rc = mg.load_library().mg_set_stack_post(ctx._h, 0, 0, w.ctypes.data_as(C.POINTER(C.c_double)), 0)
+    rc = mg.load_library().mg_set_stack_post(ctx._h, 0, 0, w.ctypes.data_as(C.POINTER(C.c_double)), 0, 0)
     assert rc == mg.MG_ERR_STATE
 
 
@@ -408,3 +408,23 @@ def test_mixed_symmetric_cycle_matches_oracle(mg):
     ctx.vcycle([_dev(f)], [u])
     ref = h.vcycle(f)
     assert np.abs(u.cpu().numpy() - ref).max() <= 2e-5 * np.abs(ref).max()
+
+
+def test_normalised_weights_take_each_levels_scale(mg):
+    # normalised = 1: the library divides f5 and f6 by the level's mean centre entry; the same cycle
+    # as the oracle's with the weights scaled by hand
+    n = 63
+    A = ora.stencil_q1_rotated(n, 0.7, 0.05)
+    h = st.StackHierarchy(A)
+    ctx = mg.Context([_dev(A)], mg.Options(smoother=mg.SMOOTHER_STACK, precision=mg.PREC_FP64))
+    for l in range(h.num_levels - 1):
+        w = mg_inputs.stack_random(40 + l)  # made for a_C = 1
+        ctx.set_stack(0, l, w, normalised=True)
+        ws = w.reshape(6, 3, 3).copy()
+        ws[4:] /= h.stencils[l][4].mean()
+        h.set_stack(l, ws)
+    f = mg_inputs.rhs_uniform(n, 3)
+    u = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    ctx.vcycle([_dev(f)], [u])
+    e = h.vcycle(f)
+    assert np.abs(u.cpu().numpy() - e).max() <= 1e-13 * np.abs(e).max()

@@ -134,3 +134,91 @@ def test_bf16_training_step_is_deterministic_and_reduces_the_loss(mg):
     assert losses[0] == losses[1]
     assert np.array_equal(nets[0].get(), nets[1].get())
     assert losses[0][-1] < 0.9 * losses[0][0]
+
+
+# ------------------------------------------------------- drawn, graph-replayed steps
+def _draws(step, B=10, J=4, pool=24):
+    rng = np.random.default_rng([77, step])
+    n = [31 if q % 3 else 63 for q in range(B)]  # the same size pattern every step
+    theta = rng.uniform(0.0, np.pi, B)
+    eps = 10.0 ** rng.uniform(-3.0, 0.0, B)
+    index = rng.integers(0, pool, (B, J))
+    return n, theta, eps, index
+
+
+def _pools(pool=24):
+    return {m: torch.tensor(mg_inputs.hf_pool(m, pool, 5), dtype=torch.float32, device="cuda") for m in (31, 63)}
+
+
+def _explicit(mg, n, theta, eps, index, pools):
+    st = [mg.stencil_q1_rotated(m, t, e) for m, t, e in zip(n, theta, eps)]
+    vs = [pools[m][torch.tensor(ix, dtype=torch.long, device="cuda")].contiguous() for m, ix in zip(n, index)]
+    return st, vs
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_drawn_step_equals_the_explicit_step(mg, precision):
+    # the library's own stencils and vector gather, inside the captured step, give what the caller's
+    # stencils (mg_stencil_q1_rotated) and gathered vectors give to mg_train_step
+    pools = _pools()
+    params = mg_inputs.cnn_random(11).astype(np.float32)
+    a, b = mg.Net(), mg.Net()
+    a.set(params)
+    b.set(params)
+    opts = mg.TrainOptions(precision=precision, apply_update=0)
+    for step in range(2):
+        n, theta, eps, index = _draws(step)
+        La, ga = a.train_step_draw(n, theta, eps, pools, index, opts, want_grad=True)
+        st, vs = _explicit(mg, n, theta, eps, index, pools)
+        Lb, gb = b.train_step(st, vs, opts, want_grad=True)
+        assert La == Lb and np.array_equal(ga, gb), (step, La, Lb)
+    if precision == 0:  # and the oracle's FP64 loss and gradient of the drawn batch
+        stencils = [ora.stencil_q1_rotated(m, t, e) for m, t, e in zip(n, theta, eps)]
+        vecs = [pools[m].cpu().numpy()[ix].astype(np.float64) for m, ix in zip(n, index)]
+        L_ref, g_ref = ora.hf_loss(stencils, vecs, params.astype(np.float64))
+        assert abs(La - L_ref) <= 1e-5 * L_ref
+        assert np.linalg.norm(ga - g_ref) <= 1e-4 * np.linalg.norm(g_ref)
+
+
+def test_drawn_steps_replay_the_graph_like_eager_steps(mg):
+    # several replays with new draws and Adam updates, eager device work and synchronisations
+    # between them; every step against the same step taken eagerly
+    pools = _pools()
+    params = mg_inputs.cnn_random(12).astype(np.float32)
+    a, b = mg.Net(), mg.Net()
+    a.set(params)
+    b.set(params)
+    opts = mg.TrainOptions(lr=1e-3, precision=1, apply_update=1)
+    junk = torch.zeros(1 << 20, device="cuda")
+    for step in range(5):
+        n, theta, eps, index = _draws(step)
+        La, _ = a.train_step_draw(n, theta, eps, pools, index, opts)
+        st, vs = _explicit(mg, n, theta, eps, index, pools)
+        Lb, _ = b.train_step(st, vs, opts)
+        assert La == pytest.approx(Lb, rel=1e-5), step
+        pa, pb = a.get(), b.get()
+        assert np.abs(pa - pb).max() <= 1e-6 * np.abs(pb).max(), step
+        junk.add_(1.0)
+        torch.cuda.synchronize()
+    # a batch of another structure rebuilds the captured step
+    n, theta, eps, index = _draws(9, B=6)
+    La, _ = a.train_step_draw(n, theta, eps, pools, index, mg.TrainOptions(precision=1, apply_update=0))
+    st, vs = _explicit(mg, n, theta, eps, index, pools)
+    Lb, _ = b.train_step(st, vs, mg.TrainOptions(precision=1, apply_update=0))
+    assert La == pytest.approx(Lb, rel=1e-5)
+
+
+def test_drawn_step_rejects_bad_draws(mg):
+    pools = _pools()
+    net = mg.Net()
+    n, theta, eps, index = _draws(0)
+    bad = index.copy()
+    bad[0, 0] = 24  # past the pool
+    with pytest.raises(mg.MGError):
+        net.train_step_draw(n, theta, eps, pools, bad)
+    with pytest.raises(mg.MGError):
+        net.train_step_draw([33] + list(n[1:]), theta, eps, pools, index)  # no pool of size 33
+    e2 = np.array(eps)
+    e2[1] = 0.0
+    with pytest.raises(mg.MGError):
+        net.train_step_draw(n, theta, e2, pools, index)

@@ -126,6 +126,9 @@ def parse():
                          "Jacobi, beside the headline; 0: skip")
     ap.add_argument("--train-steps", type=int, default=10,
                     help="timed BF16 training steps of the 256-problem batch reported beside the headline (0: skip)")
+    ap.add_argument("--redblack", type=int, default=1,
+                    help="1: also solve the headline problem with red-black coarsening (committed two-layer "
+                         "alpha-CNN smoothers, damped Jacobi V(1,1) and V(2,2)); 0: skip")
     ap.add_argument("--restart", type=int, default=30,
                     help="restart length of the FGMRES comparison reported beside the headline (0: skip it)")
     ap.add_argument("--only", choices=["both", "cnn", "jacobi"], default="both",
@@ -335,6 +338,10 @@ def main():
     stack = stack_block(args, A, f, n, theta, eps, coarsest)
     if stack is not None:
         out["alpha_stack"] = stack
+    if args.redblack:
+        rbb = redblack_block(args, n, theta, eps)
+        if rbb is not None:
+            out["redblack"] = rbb
     if args.train_steps > 0:
         out["training"] = training_block(args)
     out["roofline"]["copy_gbs"] = copy_bandwidth()
@@ -451,6 +458,27 @@ def stack_block(args, A, f, n, theta, eps, coarsest):
             f"status {out[-1]['status']}, {ms:.1f} ms; stack kernel {k['smooth_apply'] * 1e3:.1f} us"
             + (f"; FGMRES {fg['iters']} iterations, {fg['solve_ms']:.1f} ms" if fg else ""))
     return out
+
+
+def redblack_block(args, n, theta, eps):
+    """Red-black coarsening (section 6.1) on the headline problem, FP64: the committed two-layer
+    alpha-CNN smoothers (trained by Algorithm 2 at n = 63 for this theta and eps; deeper levels take
+    the deepest trained level of their kind, rescaled to their centre entry) in V(1,1), against
+    damped Jacobi V(1,1) and the cost-matched V(2,2) (two Jacobi sweeps per smoothing step, as the
+    smoother has two convolutions), all with the same red-black hierarchy."""
+    from paper_2102_12071_amd import rb_train
+    path = os.path.join(os.path.dirname(args.weights), f"rb_theta{theta:.3f}_eps{eps:g}.json")
+    if not os.path.exists(path):
+        log(f"red-black: no trained smoothers at {path}")
+        return None
+    weights, centres, kinds, _ = rb_train.load_run(path)
+    ev = rb_train.evaluate(weights, centres, kinds, n, theta, eps, tol=args.tol)
+    ev["weights"] = os.path.basename(path)
+    ev["precision"] = "fp64 (generic-footprint kernels, step by step)"
+    log(f"red-black: alpha-CNN {ev['alpha_cnn']['iters']} cycles {ev['alpha_cnn']['solve_ms']:.0f} ms; Jacobi "
+        f"V(1,1) {ev['jacobi']['iters']} / {ev['jacobi']['solve_ms']:.0f} ms; V(2,2) {ev['jacobi_v22']['iters']} / "
+        f"{ev['jacobi_v22']['solve_ms']:.0f} ms")
+    return ev
 
 
 def copy_bandwidth(mib=1024, reps=10):

@@ -217,3 +217,41 @@ def test_errors(mg):
     h = mg.RedBlack(_dev(A), 9)
     with pytest.raises(mg.MGError):
         h.set_smoother(8, np.zeros(18))  # the last level has no smoother
+
+
+def test_committed_redblack_smoothers_beat_jacobi_on_their_problem(mg):
+    # the red-black alpha-CNN smoothers trained (Algorithm 2, stable selection) for theta = pi/3,
+    # eps = 1e-3 at n = 63, applied without retraining at n = 255: fewer cycles than damped Jacobi
+    # V(1,1) with the same coarsening, and the oracle's own residual of the solution
+    import os
+    from paper_2102_12071_amd.rb_train import install, load_run, levels_for
+    path = os.path.join(os.path.dirname(mg.__file__), "weights", "rb_theta1.047_eps0.001.json")
+    weights, centres, kinds, _ = load_run(path)
+    n = 255
+    A = ora.stencil_q1_rotated(n, math.pi / 3, 1e-3)
+    f = mg_inputs.rhs_uniform(n, 0)
+    h = mg.RedBlack(_dev(A), levels_for(n))
+    jac = h.solve(_dev(f), 1e-8, 5000)
+    install(h, weights, centres, kinds)
+    res = h.solve(_dev(f), 1e-8, 5000)
+    assert res.status[0] == 0 and jac.status[0] == 0
+    assert int(res.iters[0]) < int(jac.iters[0])
+    r = f - ora.matvec(A, res.u[0].cpu().numpy())
+    assert np.linalg.norm(r) <= 1.0001e-8 * np.linalg.norm(f)
+    # and the cycle with those weights is the oracle's
+    ref = rb.RBHierarchy(A, levels_for(n))
+    e = h.vcycle(_dev(f)).cpu().numpy()
+    deepest = {}
+    for l in sorted(weights):
+        deepest[kinds[l]] = l
+    for l in range(ref.num_levels - 1):
+        if l in weights:
+            ref.set_smoother(l, weights[l])
+        else:
+            src = deepest[ref.shapes[l][1]]
+            N = ref.level_n(l)
+            w = weights[src].copy()
+            w[0] *= centres[src] / ref.diag(l)[N // 2, N // 2]
+            ref.set_smoother(l, w)
+    want = ref.vcycle(f)
+    assert np.abs(e - want).max() <= 1e-12 * np.abs(want).max()

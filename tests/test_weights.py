@@ -29,3 +29,19 @@ def test_stack_runs_are_well_formed():
             assert w.shape == (6, 3, 3) and np.isfinite(w).all()
         evals = [r for r in d["records"] if "eval" in r]
         assert {r["eval"]["n"] for r in evals} == {63, 255, 1023}
+
+
+def test_redblack_runs_are_well_formed():
+    from paper_2102_12071_amd.rb_train import load_run
+    paths = sorted(glob.glob(os.path.join(WEIGHTS, "rb_*.json")))
+    assert len(paths) >= 2
+    for p in paths:
+        weights, centres, kinds, d = load_run(p)
+        assert d["command"].startswith("python -m paper_2102_12071_amd.rb_train")
+        assert d["command"].endswith(os.path.relpath(p, ROOT))
+        assert sorted(weights) == list(range(6)) and sorted(centres) == list(range(6))
+        assert [kinds[l] for l in range(6)] == ["full", "checker"] * 3
+        for w in weights.values():
+            assert w.shape == (2, 3, 3) and np.isfinite(w).all()
+        assert all(c > 0 for c in centres.values())
+        assert {e["n"] for e in d["evaluations"]} == {63, 255, 1023}

@@ -257,7 +257,7 @@ const char *mg_kernel_name(int32_t k);
  * MG_ERR_ARG if it cannot be written.  Contexts whose sweeps are not V(1,1)
  * have nothing to tune (MG_OK).  Leaves the context's vectors undefined (the
  * next mg_solve resets them).  Synchronises. */
-#define MG_NUM_TILES 7
+#define MG_NUM_TILES 9
 mg_status mg_autotune(mg_ctx ctx, int32_t reps, const char *cache);
 /* The shape in use for kernel on level size n, and (ms non-NULL) the time per
  * launch of each shape at the last mg_autotune (MG_NUM_TILES entries, 0 when

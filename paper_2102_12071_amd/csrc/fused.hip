@@ -43,13 +43,17 @@ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 #define MG_DESCEND_TILES(X) X(0, 32, 8, 512) X(1, 32, 4, 256) X(2, 16, 8, 256) X(3, 32, 16, 1024) X(4, 64, 8, 1024)
 #define MG_ASCEND_TILES(X)                                                                                     \
     X(0, 64, 16, 512) X(1, 64, 8, 256) X(2, 128, 8, 512) X(3, 64, 32, 1024) X(4, 128, 16, 1024)            \
-    X(5, 256, 8, 1024) X(6, 32, 16, 256)
+    X(5, 256, 8, 1024) X(6, 32, 16, 256) X(7, 128, 32, 1024) X(8, 256, 16, 1024)
 // The descent split in two launches: the pre-smoothing sweep on owned fine
 // tiles of FX x FY nodes (NT1 threads), then residual and restriction on
 // coarse tiles of CX x CY nodes (NT2 threads) reading e back.  It moves 8 more
 // bytes per node (e written and read) but reads every smoother entry once, on
 // aligned rows, instead of recomputing e on a one-node ring around each tile.
-#define MG_SPLIT_TILES(X) X(5, 64, 16, 512, 32, 8, 512) X(6, 128, 8, 512, 64, 8, 1024)
+// Taller residual tiles recompute fewer shared rows (a tile's residual region overlaps the next one's by
+// one fine row and one pair of columns).
+#define MG_SPLIT_TILES(X)                                                                                      \
+    X(5, 64, 16, 512, 32, 8, 512) X(6, 128, 8, 512, 64, 8, 1024) X(7, 128, 8, 512, 64, 16, 1024)          \
+    X(8, 128, 8, 512, 32, 32, 1024)
 
 template <typename T> struct Pair { typedef T type __attribute__((ext_vector_type(2))); };
 

@@ -92,7 +92,7 @@ struct SizeClass {
     int nrun = 0;
     std::vector<int> run_slots;    // which slots d_run holds, in order
     int tile[2] = {0, 0};     // workgroup shape of the fused descent and ascent
-    double tile_ms[2][8] = {};  // time per launch of each shape at the last autotuning (0: not timed)
+    double tile_ms[2][kNumTiles] = {};  // time per launch of each shape at the last autotuning (0: not timed)
 };
 
 }  // namespace mg

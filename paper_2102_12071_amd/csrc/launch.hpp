@@ -26,7 +26,7 @@ void launch_coarse_factor(int m, int P, int64_t plane, const double *A, double *
 
 // ---- fused.hip: one launch per level and direction for V(1,1) ----
 // tile: one of kNumTiles workgroup shapes (0 = default); results do not depend on it.
-constexpr int kNumTiles = 7;
+constexpr int kNumTiles = 9;
 template <typename T>
 void launch_descend(const CycleSlot<T> *slots, int nslots, int n, bool cnn, double omega, const SolveState *state,
                     hipStream_t st, int tile = 0);

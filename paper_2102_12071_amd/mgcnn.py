@@ -27,7 +27,7 @@ PREC_FP64, PREC_MIXED = 0, 1
 
 CNN_CHANNELS = (9, 32, 32, 32, 25)
 NUM_TIMED_KERNELS = 11
-NUM_TILES = 7
+NUM_TILES = 9
 TILE_KERNELS = ("descend", "ascend")
 
 # Every exported symbol of the header, with its ctypes signature.

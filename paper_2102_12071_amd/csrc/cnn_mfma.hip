@@ -50,65 +50,91 @@ struct PackedNet {
     float bias[4][32];
 };
 
-// One layer: out(region Wo x Wo, origin (gy0, gx0)) = conv(in(region Wo+2)).
-template <int STEPS, bool FIRST, bool LAST>
-__device__ inline void conv_layer(const bf16_t *in, int CSin, int Wo, bf16_t *out_bf, float *out_f, int gy0, int gx0,
-                                  int n, const PackedNet MG_G *pk, int layer)
+// The B fragments and biases of one layer into registers (issued before the barrier that
+// precedes the layer, so that their latency overlaps the wait).
+template <int STEPS>
+__device__ inline void load_layer(const PackedNet MG_G *pk, int layer, bf16x8 (&bw)[9][2], float &b0, float &b1)
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int Wi = Wo + 2;
-    bf16x8 bw[STEPS][2];
+    const int lane = threadIdx.x & 63;
     const bf16_t MG_G *wl = pk->w + kPackOff[layer];
 #pragma unroll
     for (int s = 0; s < STEPS; ++s)
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) bw[s][nb] = *(const bf16x8 MG_G *)(wl + ((s * 2 + nb) * 64 + lane) * 8);
-    const float b0 = pk->bias[layer][lane % 16], b1 = pk->bias[layer][16 + lane % 16];
-    const int P = Wo * Wo, MB = (P + 15) / 16;
+    b0 = pk->bias[layer][lane % 16];
+    b1 = pk->bias[layer][16 + lane % 16];
+}
+
+// One layer: out(region Wo x Wo, origin (gy0, gx0)) = conv(in(region Wo+2)), input channel
+// stride CSin.  Each lane's A fragments sit at constant offsets from one LDS address per block.
+template <int STEPS, int Wo, int CSin, bool FIRST, bool LAST>
+__device__ inline void conv_layer(const bf16_t *in, bf16_t *out_bf, float *out_f, int gy0, int gx0, int n,
+                                  const bf16x8 (&bw)[9][2], float b0, float b1)
+{
+    constexpr int Wi = Wo + 2, P = Wo * Wo, MB = (P + 15) / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4;
+    // first layer: lane group g reads tap 2s + (g >> 1), channels 8 (g & 1) ..; other layers: tap s, channels 8 g ..
+    const int cg = FIRST ? (g & 1) : g;
+    const bool second_tap = FIRST && (g >> 1) != 0;
+    // the whole region on the grid: no zero padding to apply (wave-uniform)
+    const bool inside = gy0 >= 0 && gx0 >= 0 && gy0 + Wo <= n && gx0 + Wo <= n;
     for (int mb = wave; mb < MB; mb += kT / 64) {
         int pa = mb * 16 + (lane & 15);
         pa = pa < P ? pa : P - 1;
         const int oy = pa / Wo, ox = pa - oy * Wo;
+        const bf16_t *base = in + (oy * Wi + ox) * CSin + cg * 8;
         f32x4 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < STEPS; ++s) {
-            int tap, cg;
-            if (FIRST) {
-                tap = 2 * s + (g >> 1);
-                cg = g & 1;
-            } else {
-                tap = s;
-                cg = g;
-            }
             bf16x8 a;
-            if (FIRST && tap > 8) {
-                a = bf16x8{};
+            if (FIRST) {
+                const int t0 = 2 * s, t1 = 2 * s + 1;
+                const int off0 = ((t0 / 3) * Wi + t0 % 3) * CSin;
+                if (t1 > 8) {
+                    a = *(const bf16x8 *)(base + off0);
+                    if (second_tap) a = bf16x8{};  // the padded tenth tap
+                } else {
+                    const int off1 = ((t1 / 3) * Wi + t1 % 3) * CSin;
+                    a = *(const bf16x8 *)(base + off0 + (second_tap ? off1 - off0 : 0));
+                }
             } else {
-                const int ky = tap / 3, kx = tap - 3 * (tap / 3);
-                a = *(const bf16x8 *)(in + ((oy + ky) * Wi + ox + kx) * CSin + cg * 8);
+                a = *(const bf16x8 *)(base + ((s / 3) * Wi + s % 3) * CSin);
             }
             acc0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[s][0], acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[s][1], acc1, 0, 0, 0);
         }
+        const int pix0 = mb * 16 + 4 * g;
+        if (LAST) {
+            // staging [pixel][25] in FP32
+            const int co0 = lane & 15, co1 = 16 + (lane & 15);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int pix = mb * 16 + 4 * g + i;
-            if (pix >= P) continue;
-            const int py = pix / Wo, px = pix - py * Wo;
-            const int gy = gy0 + py, gx = gx0 + px;
-            const bool in_grid = gy >= 0 && gy < n && gx >= 0 && gx < n;
-            float v0 = acc0[i] + b0, v1 = acc1[i] + b1;
-            if (LAST) {
-                // staging [pixel][25] in FP32
-                const int co0 = lane & 15, co1 = 16 + (lane & 15);
-                out_f[pix * 25 + co0] = v0;
-                if (co1 < 25) out_f[pix * 25 + co1] = v1;
-            } else {
-                v0 = (in_grid && v0 > 0.f) ? v0 : 0.f;  // ReLU and zero padding off the grid
-                v1 = (in_grid && v1 > 0.f) ? v1 : 0.f;
-                out_bf[pix * kCS + (lane & 15)] = f32_to_bf16(v0);
-                out_bf[pix * kCS + 16 + (lane & 15)] = f32_to_bf16(v1);
+            for (int i = 0; i < 4; ++i) {
+                if (pix0 + i >= P) continue;
+                out_f[(pix0 + i) * 25 + co0] = acc0[i] + b0;
+                if (co1 < 25) out_f[(pix0 + i) * 25 + co1] = acc1[i] + b1;
+            }
+            continue;
+        }
+        bf16_t *o = out_bf + pix0 * kCS + (lane & 15);
+        if (inside && pix0 + 3 < P) {
+            // ReLU only
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                o[i * kCS] = f32_to_bf16(fmaxf(acc0[i] + b0, 0.f));
+                o[i * kCS + 16] = f32_to_bf16(fmaxf(acc1[i] + b1, 0.f));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int pix = pix0 + i;
+                if (pix >= P) continue;
+                const int py = pix / Wo, px = pix - py * Wo;
+                const int gy = gy0 + py, gx = gx0 + px;
+                const bool in_grid = gy >= 0 && gy < n && gx >= 0 && gx < n;
+                const float v0 = acc0[i] + b0, v1 = acc1[i] + b1;
+                o[i * kCS] = f32_to_bf16((in_grid && v0 > 0.f) ? v0 : 0.f);  // ReLU and zero padding off the grid
+                o[i * kCS + 16] = f32_to_bf16((in_grid && v1 > 0.f) ? v1 : 0.f);
             }
         }
     }
@@ -120,8 +146,14 @@ __device__ inline void cnn_tile(int n, int P, int64_t plane, const float MG_G *A
 {
     __shared__ __align__(16) bf16_t bufX[kBufX];
     __shared__ __align__(16) bf16_t bufY[kBufY];
+    __shared__ float sInv[kTO * kTO];      // 1 / a_C on the tile
+    __shared__ bool sDiff[kTO * kTO];      // the row is a diffusion row (see below)
     const int tid = threadIdx.x;
-    // network input x0 = A / a_C on the tile plus a halo of four (zero off the grid)
+    bf16x8 bw[9][2];
+    float b0, b1;
+    load_layer<5>(pk, 0, bw, b0, b1);
+    // network input x0 = A / a_C on the tile plus a halo of four (zero off the grid); on the
+    // tile itself also 1 / a_C and the row kind for the last step
     for (int q = tid; q < kR0 * kR0; q += kT) {
         const int gy = Y0 - 4 + q / kR0, gx = X0 - 4 + q % kR0;
         const bool ok = gy >= 0 && gy < n && gx >= 0 && gx < n;
@@ -132,33 +164,43 @@ __device__ inline void cnn_tile(int n, int P, int64_t plane, const float MG_G *A
         const float inv = 1.0f / a[kCentre];
 #pragma unroll
         for (int c = 0; c < 16; ++c) bufX[q * kCS0 + c] = f32_to_bf16((ok && c < 9) ? a[c < 9 ? c : 0] * inv : 0.0f);
+        const int ty = q / kR0 - 4, tx = q % kR0 - 4;
+        if (ty >= 0 && ty < kTO && tx >= 0 && tx < kTO) {
+            // a diffusion row's off-centre entries sum to a negative value; other rows (Dirichlet nodes
+            // of a masked domain and their Galerkin images) take damped Jacobi.  Summed in channel order.
+            float off = 0.f;
+#pragma unroll
+            for (int c = 0; c < 9; ++c)
+                if (c != kCentre) off += a[c];
+            sInv[ty * kTO + tx] = inv;
+            sDiff[ty * kTO + tx] = off < 0.f;
+        }
     }
     __syncthreads();
-    conv_layer<5, true, false>(bufX, kCS0, kR1, bufY, nullptr, Y0 - 3, X0 - 3, n, pk, 0);
+    conv_layer<5, kR1, kCS0, true, false>(bufX, bufY, nullptr, Y0 - 3, X0 - 3, n, bw, b0, b1);
+    load_layer<9>(pk, 1, bw, b0, b1);
     __syncthreads();
-    conv_layer<9, false, false>(bufY, kCS, kR2, bufX, nullptr, Y0 - 2, X0 - 2, n, pk, 1);
+    conv_layer<9, kR2, kCS, false, false>(bufY, bufX, nullptr, Y0 - 2, X0 - 2, n, bw, b0, b1);
+    load_layer<9>(pk, 2, bw, b0, b1);
     __syncthreads();
-    conv_layer<9, false, false>(bufX, kCS, kR3, bufY, nullptr, Y0 - 1, X0 - 1, n, pk, 2);
+    conv_layer<9, kR3, kCS, false, false>(bufX, bufY, nullptr, Y0 - 1, X0 - 1, n, bw, b0, b1);
+    load_layer<9>(pk, 3, bw, b0, b1);
     __syncthreads();
     float *stage = (float *)bufX;
-    conv_layer<9, false, true>(bufY, kCS, kTO, nullptr, stage, Y0, X0, n, pk, 3);
+    conv_layer<9, kTO, kCS, false, true>(bufY, nullptr, stage, Y0, X0, n, bw, b0, b1);
     __syncthreads();
-    // H = (omega * delta_0 + y) / a_C, plane by plane
-    for (int q = tid; q < kTO * kTO; q += kT) {
+    // H = (omega * delta_0 + y) / a_C, plane by plane: two threads per node, planes 0..12 and 13..24
+    static_assert(kT == 2 * kTO * kTO, "two threads per output node");
+    {
+        const int q = tid % (kTO * kTO), k0 = tid < kTO * kTO ? 0 : 13, k1 = tid < kTO * kTO ? 13 : 25;
         const int gy = Y0 + q / kTO, gx = X0 + q % kTO;
-        if (gy >= n || gx >= n) continue;
-        const int64_t p = (int64_t)gy * P + gx;
-        const float inv = 1.0f / A32[kCentre * plane + p];
-        // a diffusion row's off-centre entries sum to a negative value; other rows (Dirichlet nodes of
-        // a masked domain and their Galerkin images) take damped Jacobi.  Summed in channel order.
-        float off = 0.f;
-#pragma unroll
-        for (int c = 0; c < 9; ++c)
-            if (c != kCentre) off += A32[c * plane + p];
-        const bool diffusion = off < 0.f;
-#pragma unroll
-        for (int k = 0; k < 25; ++k)
-            H[k * plane + p] = f32_to_bf16(((diffusion ? stage[q * 25 + k] : 0.f) + (k == 12 ? omega : 0.f)) * inv);
+        if (gy < n && gx < n) {
+            const int64_t p = (int64_t)gy * P + gx;
+            const float inv = sInv[q];
+            const bool diffusion = sDiff[q];
+            for (int k = k0; k < k1; ++k)
+                H[k * plane + p] = f32_to_bf16(((diffusion ? stage[q * 25 + k] : 0.f) + (k == 12 ? omega : 0.f)) * inv);
+        }
     }
 }
 

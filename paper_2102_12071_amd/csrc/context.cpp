@@ -514,8 +514,10 @@ mg_status ensure_graph(mg_ctx_s &c)
     }
     if (c.graph_exec || !c.opt.use_graph) return MG_OK;
     hipStream_t st = c.join.internal;
+    // one check block of iterations per graph: consecutive graph launches leave a gap of several
+    // microseconds between them on the device, kernels inside one graph follow each other at once
     MG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    enqueue_iteration_any(c, st);
+    for (int q = 0; q < c.opt.check_every; ++q) enqueue_iteration_any(c, st);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(st, &g);
     if (e != hipSuccess) return set_error(MG_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
@@ -732,12 +734,10 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
     int64_t budget = (int64_t)maxit + 2;
     for (;;) {
         MG_TRY(ensure_graph(c));  // (re)captured with the live classes; the stream is idle here
-        for (int q = 0; q < every; ++q) {
-            if (c.graph_exec)
-                MG_HIP(hipGraphLaunch(c.graph_exec, st));
-            else
-                enqueue_iteration_any(c, st);
-        }
+        if (c.graph_exec)
+            MG_HIP(hipGraphLaunch(c.graph_exec, st));  // every iterations
+        else
+            for (int q = 0; q < every; ++q) enqueue_iteration_any(c, st);
         replays += every;
         MG_HIP(hipMemcpyAsync(hs.data(), c.d_state, sizeof(SolveState) * c.nprob, hipMemcpyDeviceToHost, st));
         MG_HIP(hipStreamSynchronize(st));

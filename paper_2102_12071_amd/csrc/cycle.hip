@@ -131,9 +131,18 @@ __global__ void __launch_bounds__(kThreads)
     const OuterSlot<T> s = slots[blockIdx.x];
     SolveState &st = state[s.prob];
     if (!init && !st.active) return;
-    double acc = 0.0;
-    for (int q = threadIdx.x; q < st.nparts; q += kThreads) acc += s.partial[q];
-    const double rr = block_sum<kThreads>(acc, red);
+    // four independent partial sums per thread, so that its loads are in flight together
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const int np = st.nparts;
+    int q = threadIdx.x;
+    for (; q + 3 * kThreads < np; q += 4 * kThreads) {
+        a0 += s.partial[q];
+        a1 += s.partial[q + kThreads];
+        a2 += s.partial[q + 2 * kThreads];
+        a3 += s.partial[q + 3 * kThreads];
+    }
+    for (; q < np; q += kThreads) a0 += s.partial[q];
+    const double rr = block_sum<kThreads>((a0 + a1) + (a2 + a3), red);
     if (threadIdx.x != 0) return;
     if (init) {
         st.fnorm = sqrt(rr);

@@ -187,7 +187,7 @@ size_t fp32_scratch(const mg_net_s &net, const mg_train_batch *b)
 struct Bf16Layout {
     std::vector<size_t> off;
     size_t desc, pack_fwd[4], pack_bwd[4], bias[4], part, part2, respart;
-    int ntiles, resblk;
+    int ntiles, resblk;  // ntiles: weight-gradient parts (tile groups)
     size_t bytes;
 };
 
@@ -201,8 +201,7 @@ Bf16Layout bf16_layout(const mg_train_batch *b)
     for (int q = 0; q < B; ++q) {
         const size_t v = (size_t)b->n[q] * b->n[q];
         L.off[q] = lay.take(v * (16 * 2 + 96 * 2 + 32 * 4 + 64 * 2 + 2 * J * 4) + J * sizeof(float));
-        const int t = (b->n[q] + 15) / 16;
-        L.ntiles += t * t;
+        L.ntiles += trb_tile_groups(b->n[q]);
     }
     L.desc = lay.take(sizeof(TrainProbB) * B);
     for (int l = 0; l < 4; ++l) {
@@ -237,7 +236,7 @@ mg_status prepare_bf16(mg_net_s &net, const mg_train_batch *b, const Bf16Layout 
     char *base = pl.base;
     classes_of(b, pl.order, pl.classes);
     std::vector<TrainProbB> desc(B);
-    int tile0 = 0;
+    int part0 = 0;
     for (int k = 0; k < B; ++k) {
         const int q = pl.order[k];
         const int n = b->n[q];
@@ -247,8 +246,8 @@ mg_status prepare_bf16(mg_net_s &net, const mg_train_batch *b, const Bf16Layout 
         d.index = q;
         d.n = n;
         d.plane = v;
-        d.tile0 = tile0;
-        tile0 += ((n + 15) / 16) * ((n + 15) / 16);
+        d.part0 = part0;
+        part0 += trb_tile_groups(n);
         d.A = b->stencil[q];
         d.V = b->vectors[q];
         d.x0 = (bf16_t *)p;
@@ -277,12 +276,14 @@ void enqueue_bf16(mg_net_s &net, const mg_train_batch *b, const mg_train_opts &o
     const int B = b->nprob, J = b->nvec;
     char *base = pl.base;
     const TrainProbB *d_desc = pl.d_desc;
+    TrbPackJobs jobs;
     for (int l = 0; l < 4; ++l) {
-        const TrainLayer &ly = pl.layers[l];
-        launch_trb_pack(net.params, ly.woff, ly.cin, ly.cout, l == 0, false, pl.pf[l], st);
-        if (l > 0) launch_trb_pack(net.params, ly.woff, ly.cin, ly.cout, false, true, pl.pb[l], st);
-        launch_trb_bias(net.params, ly.boff, ly.cout, pl.bias[l], st);
+        jobs.layer[l] = pl.layers[l];
+        jobs.fwd[l] = pl.pf[l];
+        jobs.bwd[l] = pl.pb[l];
+        jobs.bias[l] = pl.bias[l];
     }
+    launch_trb_pack_all(net.params, jobs, st);
     const float scale = 1.0f / ((float)B * (float)J);
     for (const Cls &c : pl.classes) launch_trb_input(d_desc + c.first, c.count, c.n, st);
     for (int l = 0; l < 4; ++l)

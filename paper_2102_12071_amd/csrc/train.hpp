@@ -54,13 +54,21 @@ void launch_tr_gather(int n, int count, int J, const float *pool, const int *ind
 namespace mg {
 
 // BF16 training path (train_mfma.hip): channel-last activations.
+// Weight gradients are summed over groups of kTileGroup consecutive 16 x 16 tiles of one problem per
+// workgroup (the convolutions keep one tile per workgroup: more workgroups in flight).
+constexpr int kTileGroup = 4;
+inline int trb_tile_groups(int n)
+{
+    const int t = (n + 15) / 16;
+    return (t * t + kTileGroup - 1) / kTileGroup;
+}
 enum { kTbX0 = 0, kTbAct0 = 1, kTbAct1 = 2, kTbAct2 = 3, kTbDA = 4, kTbDB = 5 };
 
 struct TrainProbB {
     int index;             // position in the batch
     int n;
     int64_t plane;         // n * n
-    int tile0;             // first 16 x 16 tile of this problem in the weight-gradient parts
+    int part0;             // first weight-gradient part of this problem (one per tile group)
     const double MG_G *A;  // stencil [9][n][n] FP64 (caller's)
     const float MG_G *V;   // HF vectors [J][n][n] (caller's)
     bf16_t MG_G *x0;       // [plane][16]
@@ -73,9 +81,14 @@ struct TrainProbB {
     float MG_G *gnorm;     // [J]
 };
 
-void launch_trb_pack(const float *params, int64_t woff, int cin, int cout, bool first, bool transposed, bf16_t *out,
-                     hipStream_t st);
-void launch_trb_bias(const float *params, int64_t boff, int cout, float *out32, hipStream_t st);
+// Per-lane B fragments of every layer (forward; transposed and flipped for the data gradient of
+// layers 1..3, bwd[0] unused) and the biases padded to 32, in one launch.
+struct TrbPackJobs {
+    TrainLayer layer[4];
+    bf16_t *fwd[4], *bwd[4];
+    float *bias[4];
+};
+void launch_trb_pack_all(const float *params, const TrbPackJobs &jobs, hipStream_t st);
 void launch_trb_input(const TrainProbB *probs, int nb, int n, hipStream_t st);
 void launch_trb_conv_fwd(const TrainProbB *probs, int nb, int n, int layer, const bf16_t *wpack, const float *bias,
                          hipStream_t st);

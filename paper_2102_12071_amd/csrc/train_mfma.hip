@@ -27,6 +27,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kT = 256;
 constexpr int kTile = 16;
 constexpr int kHalo = kTile + 2;
+constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 __device__ inline bool in_grid(int n, int i, int j) { return i >= 0 && i < n && j >= 0 && j < n; }
 
@@ -141,10 +142,13 @@ __global__ void __launch_bounds__(kT) k_trb_conv(const TrainProbB *probs, const 
     }
 }
 
-// Weight and bias gradient of one layer on one tile:
-//   part[tap][co][ci] = sum_{p in tile} dY[p][co] X[p + tap][ci],  part_b[co] = sum_p dY[p][co].
-// dY and X are staged channel-major in LDS so that a lane's eight K values
-// (eight consecutive pixels of one channel) are contiguous.
+// Weight and bias gradient of one layer on a group of kTileGroup consecutive
+// 16 x 16 tiles of one problem (row-major tile order):
+//   part[tap][co][ci] = sum_{p in group} dY[p][co] X[p + tap][ci],  part_b[co] = sum_p dY[p][co],
+// accumulated tile after tile in the MFMA accumulators, so that a group writes
+// one part (a quarter of the traffic of one part per tile).  Per tile, dY and X
+// are staged channel-major in LDS so that a lane's eight K values (eight
+// consecutive pixels of one channel) are contiguous.
 // 8 waves per workgroup: the LDS of the shifted input copies allows two workgroups per CU
 constexpr int kTW = 512;
 
@@ -160,70 +164,125 @@ __global__ void __launch_bounds__(kTW) k_trb_wgrad(const TrainProbB *probs, int 
     // 18 * 16 + 8 (148 dwords) keeps the sixteen channels of a lane group on distinct bank groups
     constexpr int XS = kHalo * kTile + 8;
     __shared__ __align__(16) bf16_t xS[3][CIN][XS];
+    __shared__ float bred[16][32];
     const TrainProbB &P = probs[blockIdx.z];
     const int n = P.n;
-    const int X0 = blockIdx.x * kTile, Y0 = blockIdx.y * kTile;
-    const int tiles = (n + kTile - 1) / kTile;
-    float *out = part + ((int64_t)P.tile0 + blockIdx.y * tiles + blockIdx.x) * (9 * 32 * 32 + 32);
-    if (X0 >= n || Y0 >= n) return;
+    const int tiles = (n + kTile - 1) / kTile, ntile = tiles * tiles;
+    const int t0 = blockIdx.x * kTileGroup, t1 = min(ntile, t0 + kTileGroup);
+    if (t0 >= ntile) return;
+    float *out = part + ((int64_t)P.part0 + blockIdx.x) * (9 * 32 * 32 + 32);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4;
     const bf16_t MG_G *dy = bsel(P, dy_sel);
     const bf16_t MG_G *x = bsel(P, x_sel);
-    for (int q = tid; q < kTile * kTile * 4; q += kTW) {
-        const int pix = q / 4, c8 = q % 4;
-        const int gi = X0 + pix % kTile, gj = Y0 + pix / kTile;
-        const bool ok = in_grid(n, gi, gj);
-        const int64_t p = ok ? (int64_t)gj * n + gi : 0;
-        u32x4 v = *(const u32x4 MG_G *)(dy + p * 32 + c8 * 8);
-        if (!ok) v = u32x4{0u, 0u, 0u, 0u};
-        const bf16_t *e8 = (const bf16_t *)&v;
+    // (tap, ci-block) jobs of one co-block per wave (waves 2q and 2q + 1: co-blocks 0 and 1, jobs
+    // q, q + 4, ..), so that a wave's A fragment (dY of its co-block) serves all its jobs per K step
+    constexpr int NB = CIN / 16, NJB = 9 * NB, JPW = (NJB + 3) / 4;
+    const int wmb = wave & 1, wq = wave >> 1;
+    f32x4 acc[JPW];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) dyT[c8 * 8 + e][pix] = e8[e];
-    }
+    for (int jj = 0; jj < JPW; ++jj) acc[jj] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
+    // Staging: a work item loads one 8-channel chunk of 8 consecutive pixels (eight 16-byte loads),
+    // transposes the 8 x 8 block in registers and writes 8 channel rows of 8 pixels (16 bytes each).
     constexpr int CH = CIN / 8;
-    for (int q = tid; q < kHalo * kHalo * CH; q += kTW) {
-        const int pix = q / CH, c8 = q % CH;
-        const int col = pix % kHalo, row = pix / kHalo;
-        const int gi = X0 - 1 + col, gj = Y0 - 1 + row;
-        const bool ok = in_grid(n, gi, gj);
-        const int64_t p = ok ? (int64_t)gj * n + gi : 0;
-        u32x4 v = *(const u32x4 MG_G *)(x + p * CIN + c8 * 8);
-        if (!ok) v = u32x4{0u, 0u, 0u, 0u};
-        const bf16_t *e8 = (const bf16_t *)&v;
+    constexpr int NDY = kTile * kTile / 8 * 4, NXS = 3 * kHalo * 2 * CH;
+    // rows[c] = the 8 values of channel c of the 8 chunks v[0..7] (pixel e in position e)
+    auto transpose8 = [](const u32x4 (&v)[8], u32x4 (&rows)[8]) {
 #pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-            const int px = col - kx;
-            if (px < 0 || px >= kTile) continue;
+        for (int c = 0; c < 8; ++c) {
+            uint32_t w[4];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) xS[kx][c8 * 8 + e][row * kTile + px] = e8[e];
+            for (int h = 0; h < 4; ++h) {
+                const uint32_t a = v[2 * h][c / 2], b = v[2 * h + 1][c / 2];
+                w[h] = (c & 1) ? ((a >> 16) | (b & 0xffff0000u)) : ((a & 0xffffu) | (b << 16));
+            }
+            rows[c] = u32x4{w[0], w[1], w[2], w[3]};
         }
-    }
-    __syncthreads();
-    // bias gradient
-    if (tid < 32) {
-        float sacc = 0.f;
-        for (int p = 0; p < kTile * kTile; ++p) sacc += bf16_to_f32(dyT[tid][p]);
-        out[9 * 32 * 32 + tid] = tid < cout ? sacc : 0.f;
-    }
-    // (tap, co-block, ci-block) jobs spread over the waves
-    constexpr int NB = CIN / 16;
-    for (int job = wave; job < 9 * 2 * NB; job += kTW / 64) {
-        const int tap = job / (2 * NB), mb = (job / NB) % 2, nb = job % NB;
-        const int ky = tap / 3, kx = tap % 3;
-        const int co = mb * 16 + (lane & 15), ci = nb * 16 + (lane & 15);
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    };
+    for (int t = t0; t < t1; ++t) {
+        // (the barrier at the end of the previous tile: its products are done with the LDS)
+        const int X0 = (t % tiles) * kTile, Y0 = (t / tiles) * kTile;
+        for (int item = tid; item < NDY + NXS; item += kTW) {
+          if (item < NDY) {
+            const int pb = item / 4, c8 = item % 4;  // pixels 8 pb .. 8 pb + 7 of the tile (one half row)
+            u32x4 v[8], rows[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int pix = pb * 8 + e;
+                const int gi = X0 + pix % kTile, gj = Y0 + pix / kTile;
+                const bool ok = in_grid(n, gi, gj);
+                const int64_t p = ok ? (int64_t)gj * n + gi : 0;
+                const u32x4 ld = *(const u32x4 MG_G *)(dy + p * 32 + c8 * 8);
+                v[e] = ok ? ld : u32x4{0u, 0u, 0u, 0u};
+            }
+            transpose8(v, rows);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) *(u32x4 *)&dyT[c8 * 8 + c][pb * 8] = rows[c];
+          } else {
+            // xS[kx][ci][row][px0 .. px0 + 7] = x(row, px0 + kx ..) in halo coordinates
+            const int w = item - NDY;
+            const int c8 = w % CH, seg = (w / CH) % 2, row = (w / (2 * CH)) % kHalo, kx = w / (2 * CH * kHalo);
+            const int px0 = seg * 8;
+            u32x4 v[8], rows[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int gi = X0 - 1 + px0 + kx + e, gj = Y0 - 1 + row;
+                const bool ok = in_grid(n, gi, gj);
+                const int64_t p = ok ? (int64_t)gj * n + gi : 0;
+                const u32x4 ld = *(const u32x4 MG_G *)(x + p * CIN + c8 * 8);
+                v[e] = ok ? ld : u32x4{0u, 0u, 0u, 0u};
+            }
+            transpose8(v, rows);
+#pragma unroll
+            for (int c = 0; c < 8; ++c) *(u32x4 *)&xS[kx][c8 * 8 + c][row * kTile + px0] = rows[c];
+          }
+        }
+        __syncthreads();
+        // bias gradient: 16 partial sums of 16 pixels per channel (all threads), combined in order by
+        // the first 32 threads after the tile's products
+        {
+            const int c = tid & 31, part16 = tid >> 5;
+            float sacc = 0.f;
+#pragma unroll
+            for (int p = 0; p < 16; ++p) sacc += bf16_to_f32(dyT[c][part16 * 16 + p]);
+            bred[part16][c] = sacc;
+        }
+        static_assert(kTW == 8 * 64, "eight waves: two co-blocks x four job sets");
+        const int co = wmb * 16 + (lane & 15);
 #pragma unroll 2
         for (int ks = 0; ks < kTile * kTile / 32; ++ks) {
-            const int k0 = ks * 32 + 8 * g;           // eight consecutive pixels of one tile row
+            const int k0 = ks * 32 + 8 * g;  // eight consecutive pixels of one tile row
             const int py = k0 / kTile, px = k0 % kTile;
             const bf16x8 a = *(const bf16x8 *)&dyT[co][k0];
-            const bf16x8 b = *(const bf16x8 *)&xS[kx][ci][(py + ky) * kTile + px];
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+#pragma unroll
+            for (int jj = 0; jj < JPW; ++jj) {
+                const int q = wq + 4 * jj;
+                if (q >= NJB) break;
+                const int tap = q / NB, nb = q % NB;
+                const int ky = tap / 3, kx = tap % 3;
+                const int ci = nb * 16 + (lane & 15);
+                const bf16x8 b = *(const bf16x8 *)&xS[kx][ci][(py + ky) * kTile + px];
+                acc[jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[jj], 0, 0, 0);
+            }
         }
+        __syncthreads();  // bred complete
+        if (tid < 32) {
+            float sacc = 0.f;
+            for (int q = 0; q < 16; ++q) sacc += bred[q][tid];
+            bacc += sacc;
+        }
+    }
+    if (tid < 32) out[9 * 32 * 32 + tid] = tid < cout ? bacc : 0.f;
+    static_assert(kTW == 16 * 32, "one thread per (16-pixel part, channel) of the bias gradient");
+#pragma unroll
+    for (int jj = 0; jj < JPW; ++jj) {
+        const int q = wq + 4 * jj;
+        if (q >= NJB) break;
+        const int tap = q / NB, nb = q % NB;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int co_i = mb * 16 + 4 * g + i;
-            out[(tap * 32 + co_i) * 32 + nb * 16 + (lane & 15)] = acc[i];
+            const int co_i = wmb * 16 + 4 * g + i;
+            out[(tap * 32 + co_i) * 32 + nb * 16 + (lane & 15)] = acc[jj][i];
         }
     }
 }
@@ -268,26 +327,47 @@ __global__ void __launch_bounds__(kT) k_trb_av(const TrainProbB *probs, int J)
     }
 }
 
+// The rows of A v_j that a block of kT consecutive pixels reaches with the 5 x 5 smoother (two
+// above its first row, two below its last), for kVChunk vectors at a time, staged in LDS: one
+// barrier pair per chunk, the chunk's loads in flight together.
+constexpr int kVChunk = 1;
+constexpr int kResRows = 1792;  // >= max over 3 <= n <= 255 of (255 / n + 6) n
+
+struct BlockRows {
+    int r0, nrow;
+};
+
+__device__ inline BlockRows block_rows(int64_t plane, int n)
+{
+    const int64_t p0 = (int64_t)blockIdx.x * kT, p1 = min(p0 + kT, plane) - 1;
+    const int r0 = max(0, (int)(p0 / n) - 2), r1 = min(n - 1, (int)(p1 / n) + 2);
+    return {r0, (r1 - r0 + 1) * n};  // nrow <= (255 / n + 6) n <= 1785 for 3 <= n <= 255
+}
+
+__device__ inline void stage_av(const TrainProbB &P, const BlockRows &br, int jv0, int jn, float *sav)
+{
+    for (int q = 0; q < jn; ++q) {
+        const float MG_G *Av = P.Av + (int64_t)(jv0 + q) * P.plane + (int64_t)br.r0 * P.n;
+        for (int t = threadIdx.x; t < br.nrow; t += kT) sav[q * kResRows + t] = Av[t];
+    }
+}
+
 // g_j = v_j - H A v_j for every vector j of a problem, one thread per pixel:
 // the pixel's 25 smoother taps are read once for all J vectors.  Per block and
 // vector, the sum of g_j^2 (FP64, waves then the block in a fixed order) goes
 // to part[problem][block][j].  grid = (pixel blocks, 1, problems).
-constexpr int kJChunk = 64;
-constexpr int kResRows = 1792;  // >= max over 3 <= n <= 255 of (255 / n + 6) n
 __global__ void __launch_bounds__(kT) k_trb_residual(const TrainProbB *probs, int J, float omega, double *part,
                                                      int nblk)
 {
-    __shared__ double red[kT / 64][kJChunk];
-    __shared__ float sav[kResRows];  // the rows of A v_j the block's pixels reach (two above, two below)
+    __shared__ double red[kT / 64][kVChunk];
+    __shared__ float sav[kVChunk * kResRows];
     const TrainProbB &P = probs[blockIdx.z];
     const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
     const bool live = p < P.plane;
     const int n = P.n;
     const int64_t pc = live ? p : 0;
     const int i = (int)(pc % n), j = (int)(pc / n);
-    const int64_t p0 = (int64_t)blockIdx.x * kT, p1 = min(p0 + kT, P.plane) - 1;
-    const int r0 = max(0, (int)(p0 / n) - 2), r1 = min(n - 1, (int)(p1 / n) + 2);
-    const int nrow = (r1 - r0 + 1) * n;  // <= (255 / n + 6) n <= 1785 for 3 <= n <= 255
+    const BlockRows br = block_rows(P.plane, n);
     float w[25];
 #pragma unroll
     for (int k = 0; k < 25; ++k) w[k] = P.y[pc * 32 + k] + (k == 12 ? omega : 0.0f);
@@ -298,36 +378,33 @@ __global__ void __launch_bounds__(kT) k_trb_residual(const TrainProbB *probs, in
     for (int k = 0; k < 25; ++k) {
         const int ii = i + k % 5 - 2, jj = j + k / 5 - 2;
         ok[k] = live && in_grid(n, ii, jj);
-        off[k] = ok[k] ? (jj - r0) * n + ii : 0;
+        off[k] = ok[k] ? (jj - br.r0) * n + ii : 0;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double *out = part + ((int64_t)P.index * nblk + blockIdx.x) * J;
-    for (int j0 = 0; j0 < J; j0 += kJChunk) {
-        const int jn = min(kJChunk, J - j0);
+    for (int j0 = 0; j0 < J; j0 += kVChunk) {
+        const int jn = min(kVChunk, J - j0);
+        stage_av(P, br, j0, jn, sav);
+        __syncthreads();
         for (int q = 0; q < jn; ++q) {
             const int jv = j0 + q;
-            const float MG_G *Av = P.Av + (int64_t)jv * P.plane + (int64_t)r0 * n;
-            for (int t = threadIdx.x; t < nrow; t += kT) sav[t] = Av[t];
-            __syncthreads();
             float y = 0.0f;
 #pragma unroll
             for (int k = 0; k < 25; ++k) {
-                const float xv = sav[off[k]];
+                const float xv = sav[q * kResRows + off[k]];
                 y += w[k] * (ok[k] ? xv : 0.f);
             }
-            __syncthreads();  // sav is refilled for the next vector
             const float gv = P.V[(int64_t)jv * P.plane + pc] - y * inv_ac;
             if (live) P.g[(int64_t)jv * P.plane + p] = gv;
             const double s = wave_sum(live ? (double)gv * gv : 0.0);
             if (lane == 0) red[wave][q] = s;
         }
-        __syncthreads();
+        __syncthreads();  // red is complete; sav is refilled by the next chunk
         if ((int)threadIdx.x < jn) {
             double s = 0.0;
             for (int w2 = 0; w2 < kT / 64; ++w2) s += red[w2][threadIdx.x];
             out[j0 + threadIdx.x] = s;
         }
-        __syncthreads();
     }
 }
 
@@ -345,31 +422,61 @@ __global__ void k_trb_norms(const TrainProbB *probs, int J, const double *part, 
     }
 }
 
-// dL/dy_p[k] = -(1/(B J)) sum_j (g_j(p)/||g_j||) Av_j(p + k)/a_C(p) -> dA (channel-last BF16, 32 channels).
+// dL/dy_p[k] = -(1/(B J)) sum_j (g_j(p)/||g_j||) Av_j(p + k)/a_C(p) -> dA (channel-last BF16, 32
+// channels), the rows of A v_j staged in LDS as for the residual.
 __global__ void __launch_bounds__(kT) k_trb_dout(const TrainProbB *probs, int J, float scale)
 {
+    __shared__ float sav[kVChunk * kResRows];
     const TrainProbB &P = probs[blockIdx.z];
     const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (p >= P.plane) return;
-    const int n = P.n, i = (int)(p % n), j = (int)(p / n);
-    const float inv_ac = 1.0f / (float)P.A[kCentre * P.plane + p];
+    const bool live = p < P.plane;
+    const int n = P.n;
+    const int64_t pc = live ? p : 0;
+    const int i = (int)(pc % n), j = (int)(pc / n);
+    const BlockRows br = block_rows(P.plane, n);
+    const float inv_ac = 1.0f / (float)P.A[kCentre * P.plane + pc];
+    int off[25];
+    bool ok[25];
+#pragma unroll
+    for (int k = 0; k < 25; ++k) {
+        const int ii = i + k % 5 - 2, jj = j + k / 5 - 2;
+        ok[k] = live && in_grid(n, ii, jj);
+        off[k] = ok[k] ? (jj - br.r0) * n + ii : 0;
+    }
     float acc[25];
 #pragma unroll
     for (int k = 0; k < 25; ++k) acc[k] = 0.0f;
-    for (int jv = 0; jv < J; ++jv) {
-        const float gn = P.gnorm[jv];
-        const float c = gn > 0.f ? -scale * P.g[(int64_t)jv * P.plane + p] / gn * inv_ac : 0.f;
-        const float MG_G *Av = P.Av + (int64_t)jv * P.plane;
+    for (int j0 = 0; j0 < J; j0 += kVChunk) {
+        const int jn = min(kVChunk, J - j0);
+        stage_av(P, br, j0, jn, sav);
+        __syncthreads();
+        for (int q = 0; q < jn; ++q) {
+            const int jv = j0 + q;
+            const float gn = P.gnorm[jv];
+            const float c = gn > 0.f ? -scale * P.g[(int64_t)jv * P.plane + pc] / gn * inv_ac : 0.f;
 #pragma unroll
-        for (int k = 0; k < 25; ++k) {
-            const int ii = i + k % 5 - 2, jj = j + k / 5 - 2;
-            const bool ok = in_grid(n, ii, jj);
-            const float xv = Av[ok ? (int64_t)jj * n + ii : p];
-            acc[k] += c * (ok ? xv : 0.f);
+            for (int k = 0; k < 25; ++k) {
+                const float xv = sav[q * kResRows + off[k]];
+                acc[k] += c * (ok[k] ? xv : 0.f);
+            }
         }
+        __syncthreads();  // sav is refilled by the next chunk
     }
+    if (!live) return;
+    // 32 channels (25 used) in four 16-byte stores
+    u32x4 *o = (u32x4 *)(P.dA + p * 32);
 #pragma unroll
-    for (int k = 0; k < 32; ++k) P.dA[p * 32 + k] = f32_to_bf16(k < 25 ? acc[k < 25 ? k : 0] : 0.f);
+    for (int c8 = 0; c8 < 4; ++c8) {
+        uint32_t w4[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const int k0 = c8 * 8 + 2 * h, k1 = k0 + 1;
+            const uint32_t lo = f32_to_bf16(k0 < 25 ? acc[k0 < 25 ? k0 : 0] : 0.f);
+            const uint32_t hi = f32_to_bf16(k1 < 25 ? acc[k1 < 25 ? k1 : 0] : 0.f);
+            w4[h] = lo | (hi << 16);
+        }
+        o[c8] = u32x4{w4[0], w4[1], w4[2], w4[3]};
+    }
 }
 
 // grad[flat] = sum over tiles of the per-tile parts, in two deterministic
@@ -418,11 +525,23 @@ __global__ void __launch_bounds__(kT) k_trb_reduce(const float *part2, int cin, 
 // Per-lane B fragments: forward weights of layer l (mode 0) or the transposed,
 // flipped weights for the data gradient of layer l (mode 1: B[k = co][n = ci] =
 // W[co][ci][8 - tap]).  Layout [step][n-block][lane][8].
-__global__ void k_trb_pack(const float *params, int64_t woff, int cin, int cout, int first, int mode, bf16_t *out,
-                           int steps)
+// One launch packs every layer: grid.y = job, 0..3 the forward fragments of layers 0..3, 4..6 the
+// transposed ones of layers 1..3, 7..10 the padded biases of layers 0..3.
+__global__ void k_trb_pack_all(const float *params, TrbPackJobs jobs)
 {
+    const int job = blockIdx.y;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (job >= 7) {
+        const TrainLayer &L = jobs.layer[job - 7];
+        if (idx < 32) jobs.bias[job - 7][idx] = idx < L.cout ? params[L.boff + idx] : 0.f;
+        return;
+    }
+    const int mode = job < 4 ? 0 : 1, layer = job < 4 ? job : job - 3;
+    const bool first = mode == 0 && layer == 0;
+    const int steps = first ? 5 : 9;
     if (idx >= steps * 2 * 64 * 8) return;
+    const TrainLayer &L = jobs.layer[layer];
+    const int cin = L.cin, cout = L.cout;
     const int e = idx & 7, lane = (idx >> 3) & 63, nb = (idx >> 9) & 1, s = idx >> 10;
     const int g = lane >> 4, col = nb * 16 + (lane & 15);
     float v = 0.f;
@@ -436,35 +555,21 @@ __global__ void k_trb_pack(const float *params, int64_t woff, int cin, int cout,
             ci = 8 * g + e;
         }
         const int co = col;
-        if (tap < 9 && ci < cin && co < cout) v = params[woff + ((int64_t)co * cin + ci) * 9 + tap];
+        if (tap < 9 && ci < cin && co < cout) v = params[L.woff + ((int64_t)co * cin + ci) * 9 + tap];
     } else {
         const int tap = s, co = 8 * g + e, ci = col;
-        if (co < cout && ci < cin) v = params[woff + ((int64_t)co * cin + ci) * 9 + (8 - tap)];
+        if (co < cout && ci < cin) v = params[L.woff + ((int64_t)co * cin + ci) * 9 + (8 - tap)];
     }
-    out[idx] = f32_to_bf16(v);
-}
-
-__global__ void k_trb_bias(const float *params, int64_t boff, int cout, float *out32)
-{
-    const int co = threadIdx.x;
-    if (co < 32) out32[co] = co < cout ? params[boff + co] : 0.f;
+    (mode == 0 ? jobs.fwd[layer] : jobs.bwd[layer])[idx] = f32_to_bf16(v);
 }
 
 inline unsigned blocks_for(int64_t count) { return (unsigned)((count + kT - 1) / kT); }
 
 }  // namespace
 
-void launch_trb_bias(const float *params, int64_t boff, int cout, float *out32, hipStream_t st)
+void launch_trb_pack_all(const float *params, const TrbPackJobs &jobs, hipStream_t st)
 {
-    k_trb_bias<<<1, 32, 0, st>>>(params, boff, cout, out32);
-}
-
-void launch_trb_pack(const float *params, int64_t woff, int cin, int cout, bool first, bool transposed, bf16_t *out,
-                     hipStream_t st)
-{
-    const int steps = (first && !transposed) ? 5 : 9;
-    k_trb_pack<<<blocks_for(steps * 2 * 64 * 8), kT, 0, st>>>(params, woff, cin, cout, first ? 1 : 0,
-                                                              transposed ? 1 : 0, out, steps);
+    k_trb_pack_all<<<dim3(blocks_for(9 * 2 * 64 * 8), 11), kT, 0, st>>>(params, jobs);
 }
 
 void launch_trb_input(const TrainProbB *probs, int nb, int n, hipStream_t st)
@@ -497,8 +602,7 @@ void launch_trb_conv_bwd_data(const TrainProbB *probs, int nb, int n, int layer,
 
 void launch_trb_wgrad(const TrainProbB *probs, int nb, int n, int layer, int cout, float *part, hipStream_t st)
 {
-    const int t = (n + kTile - 1) / kTile;
-    const dim3 g(t, t, nb);
+    const dim3 g(trb_tile_groups(n), 1, nb);
     const int dy_sel = (layer & 1) ? kTbDA : kTbDB;
     if (layer == 0)
         k_trb_wgrad<16><<<g, kTW, 0, st>>>(probs, dy_sel, kTbX0, cout, part);

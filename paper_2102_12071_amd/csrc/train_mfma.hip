@@ -328,10 +328,12 @@ __global__ void __launch_bounds__(kT) k_trb_av(const TrainProbB *probs, int J)
 }
 
 // The rows of A v_j that a block of kT consecutive pixels reaches with the 5 x 5 smoother (two
-// above its first row, two below its last), for kVChunk vectors at a time, staged in LDS: one
-// barrier pair per chunk, the chunk's loads in flight together.
-constexpr int kVChunk = 1;
+// above its first row, two below its last) are staged in LDS, double-buffered: while vector j is
+// computed from one buffer, the rows of vector j + 1 are loaded into registers and then stored to
+// the other, so that one barrier per vector separates them and the loads overlap the arithmetic.
 constexpr int kResRows = 1792;  // >= max over 3 <= n <= 255 of (255 / n + 6) n
+constexpr int kRowRegs = kResRows / kT;  // staged values per thread
+static_assert(kRowRegs * kT == kResRows, "whole rounds of staging");
 
 struct BlockRows {
     int r0, nrow;
@@ -344,11 +346,22 @@ __device__ inline BlockRows block_rows(int64_t plane, int n)
     return {r0, (r1 - r0 + 1) * n};  // nrow <= (255 / n + 6) n <= 1785 for 3 <= n <= 255
 }
 
-__device__ inline void stage_av(const TrainProbB &P, const BlockRows &br, int jv0, int jn, float *sav)
+__device__ inline void load_rows(const TrainProbB &P, const BlockRows &br, int jv, float (&r)[kRowRegs])
 {
-    for (int q = 0; q < jn; ++q) {
-        const float MG_G *Av = P.Av + (int64_t)(jv0 + q) * P.plane + (int64_t)br.r0 * P.n;
-        for (int t = threadIdx.x; t < br.nrow; t += kT) sav[q * kResRows + t] = Av[t];
+    const float MG_G *Av = P.Av + (int64_t)jv * P.plane + (int64_t)br.r0 * P.n;
+#pragma unroll
+    for (int k = 0; k < kRowRegs; ++k) {
+        const int t = threadIdx.x + k * kT;
+        r[k] = t < br.nrow ? Av[t] : 0.f;
+    }
+}
+
+__device__ inline void store_rows(const BlockRows &br, const float (&r)[kRowRegs], float *buf)
+{
+#pragma unroll
+    for (int k = 0; k < kRowRegs; ++k) {
+        const int t = threadIdx.x + k * kT;
+        if (t < br.nrow) buf[t] = r[k];
     }
 }
 
@@ -356,11 +369,12 @@ __device__ inline void stage_av(const TrainProbB &P, const BlockRows &br, int jv
 // the pixel's 25 smoother taps are read once for all J vectors.  Per block and
 // vector, the sum of g_j^2 (FP64, waves then the block in a fixed order) goes
 // to part[problem][block][j].  grid = (pixel blocks, 1, problems).
+constexpr int kJChunk = 64;
 __global__ void __launch_bounds__(kT) k_trb_residual(const TrainProbB *probs, int J, float omega, double *part,
                                                      int nblk)
 {
-    __shared__ double red[kT / 64][kVChunk];
-    __shared__ float sav[kVChunk * kResRows];
+    __shared__ double red[kT / 64][kJChunk];
+    __shared__ float sav[2][kResRows];
     const TrainProbB &P = probs[blockIdx.z];
     const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
     const bool live = p < P.plane;
@@ -368,6 +382,8 @@ __global__ void __launch_bounds__(kT) k_trb_residual(const TrainProbB *probs, in
     const int64_t pc = live ? p : 0;
     const int i = (int)(pc % n), j = (int)(pc / n);
     const BlockRows br = block_rows(P.plane, n);
+    float rows[kRowRegs];
+    load_rows(P, br, 0, rows);
     float w[25];
 #pragma unroll
     for (int k = 0; k < 25; ++k) w[k] = P.y[pc * 32 + k] + (k == 12 ? omega : 0.0f);
@@ -382,29 +398,38 @@ __global__ void __launch_bounds__(kT) k_trb_residual(const TrainProbB *probs, in
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double *out = part + ((int64_t)P.index * nblk + blockIdx.x) * J;
-    for (int j0 = 0; j0 < J; j0 += kVChunk) {
-        const int jn = min(kVChunk, J - j0);
-        stage_av(P, br, j0, jn, sav);
-        __syncthreads();
+    store_rows(br, rows, sav[0]);
+    float vnext = P.V[pc];
+    __syncthreads();
+    for (int j0 = 0; j0 < J; j0 += kJChunk) {
+        const int jn = min(kJChunk, J - j0);
         for (int q = 0; q < jn; ++q) {
             const int jv = j0 + q;
+            const float vj = vnext;
+            if (jv + 1 < J) {  // the next vector's rows and value, in flight during this one
+                load_rows(P, br, jv + 1, rows);
+                vnext = P.V[(int64_t)(jv + 1) * P.plane + pc];
+            }
+            const float *buf = sav[jv & 1];
             float y = 0.0f;
 #pragma unroll
             for (int k = 0; k < 25; ++k) {
-                const float xv = sav[q * kResRows + off[k]];
+                const float xv = buf[off[k]];
                 y += w[k] * (ok[k] ? xv : 0.f);
             }
-            const float gv = P.V[(int64_t)jv * P.plane + pc] - y * inv_ac;
+            const float gv = vj - y * inv_ac;
             if (live) P.g[(int64_t)jv * P.plane + p] = gv;
             const double s = wave_sum(live ? (double)gv * gv : 0.0);
             if (lane == 0) red[wave][q] = s;
+            if (jv + 1 < J) store_rows(br, rows, sav[(jv + 1) & 1]);
+            __syncthreads();  // the next vector's rows are in LDS; this vector's buffer is free
         }
-        __syncthreads();  // red is complete; sav is refilled by the next chunk
         if ((int)threadIdx.x < jn) {
             double s = 0.0;
             for (int w2 = 0; w2 < kT / 64; ++w2) s += red[w2][threadIdx.x];
             out[j0 + threadIdx.x] = s;
         }
+        __syncthreads();  // red is reused by the next chunk
     }
 }
 
@@ -426,7 +451,7 @@ __global__ void k_trb_norms(const TrainProbB *probs, int J, const double *part, 
 // channels), the rows of A v_j staged in LDS as for the residual.
 __global__ void __launch_bounds__(kT) k_trb_dout(const TrainProbB *probs, int J, float scale)
 {
-    __shared__ float sav[kVChunk * kResRows];
+    __shared__ float sav[2][kResRows];
     const TrainProbB &P = probs[blockIdx.z];
     const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
     const bool live = p < P.plane;
@@ -434,6 +459,8 @@ __global__ void __launch_bounds__(kT) k_trb_dout(const TrainProbB *probs, int J,
     const int64_t pc = live ? p : 0;
     const int i = (int)(pc % n), j = (int)(pc / n);
     const BlockRows br = block_rows(P.plane, n);
+    float rows[kRowRegs];
+    load_rows(P, br, 0, rows);
     const float inv_ac = 1.0f / (float)P.A[kCentre * P.plane + pc];
     int off[25];
     bool ok[25];
@@ -446,21 +473,25 @@ __global__ void __launch_bounds__(kT) k_trb_dout(const TrainProbB *probs, int J,
     float acc[25];
 #pragma unroll
     for (int k = 0; k < 25; ++k) acc[k] = 0.0f;
-    for (int j0 = 0; j0 < J; j0 += kVChunk) {
-        const int jn = min(kVChunk, J - j0);
-        stage_av(P, br, j0, jn, sav);
-        __syncthreads();
-        for (int q = 0; q < jn; ++q) {
-            const int jv = j0 + q;
-            const float gn = P.gnorm[jv];
-            const float c = gn > 0.f ? -scale * P.g[(int64_t)jv * P.plane + pc] / gn * inv_ac : 0.f;
-#pragma unroll
-            for (int k = 0; k < 25; ++k) {
-                const float xv = sav[q * kResRows + off[k]];
-                acc[k] += c * (ok[k] ? xv : 0.f);
-            }
+    store_rows(br, rows, sav[0]);
+    float gnext = P.g[pc];
+    __syncthreads();
+    for (int jv = 0; jv < J; ++jv) {
+        const float gj = gnext;
+        if (jv + 1 < J) {  // the next vector's rows and residual, in flight during this one
+            load_rows(P, br, jv + 1, rows);
+            gnext = P.g[(int64_t)(jv + 1) * P.plane + pc];
         }
-        __syncthreads();  // sav is refilled by the next chunk
+        const float gn = P.gnorm[jv];
+        const float c = gn > 0.f ? -scale * gj / gn * inv_ac : 0.f;
+        const float *buf = sav[jv & 1];
+#pragma unroll
+        for (int k = 0; k < 25; ++k) {
+            const float xv = buf[off[k]];
+            acc[k] += c * (ok[k] ? xv : 0.f);
+        }
+        if (jv + 1 < J) store_rows(br, rows, sav[(jv + 1) & 1]);
+        __syncthreads();  // the next vector's rows are in LDS; this vector's buffer is free
     }
     if (!live) return;
     // 32 channels (25 used) in four 16-byte stores

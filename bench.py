@@ -410,8 +410,11 @@ def stack_block(args, A, f, n, theta, eps, coarsest):
     trained per problem by Algorithm 2; weights/stack_*.json) on this problem,
     for every committed training run that matches it (Algorithm 2's cycle, or
     the symmetric one with H^T after the coarse correction): iterations and
-    time to the tolerance, and the stack kernel's own rate on the finest level
-    (its algorithmic traffic: x read once, e read and written, FP32)."""
+    time to the tolerance, and the rates of the fused stack level kernels on the
+    finest level (FP32 algorithmic traffic per fine node: descend reads r and the
+    nine stencil planes and writes e and a quarter node of r_c, 45 B; the finest
+    ascend reads a quarter node of e_c, e, r, the stencil and reads and writes u
+    in FP64, 61 B)."""
     import glob
 
     import torch
@@ -446,16 +449,18 @@ def stack_block(args, A, f, n, theta, eps, coarsest):
             fg = {"iters": int(r.iters[0]), "status": int(r.status[0]), "relres": float(r.relres[0]),
                   "solve_ms": (time.perf_counter() - t0) * 1e3, "restart": args.restart}
         ctx.close()
-        bytes_per_launch = 12.0 * n * n  # algorithmic, per node: x read once, e read and written (FP32)
+        nn = float(n) * n
+        kern = {name: {"ms": k[name], "algorithmic_bytes": per * nn,
+                       "achieved_gbs": per * nn / (k[name] * 1e-3) / 1e9}
+                for name, per in (("descend", 45.0), ("ascend", 61.0))}
         out.append({"weights": os.path.relpath(path, os.path.dirname(os.path.abspath(__file__))),
                     "symmetric": symmetric, "trained_sizes": sorted(stacks), "iters": int(res.iters[0]),
                     "status": int(res.status[0]), "relres": float(res.relres[0]), "solve_ms": ms,
                     "ms_per_iteration": float(res.ms) / max(int(res.iters[0]), 1), "fgmres": fg,
-                    "kernel": {"name": "k_stack_cycle (accumulating, after the coarse correction)",
-                               "ms": k["smooth_apply"], "algorithmic_bytes": bytes_per_launch,
-                               "achieved_gbs": bytes_per_launch / (k["smooth_apply"] * 1e-3) / 1e9}})
+                    "kernels": kern})
         log(f"alpha-CNN stack ({os.path.basename(path)}): {out[-1]['iters']} iterations, "
-            f"status {out[-1]['status']}, {ms:.1f} ms; stack kernel {k['smooth_apply'] * 1e3:.1f} us"
+            f"status {out[-1]['status']}, {ms:.1f} ms, {out[-1]['ms_per_iteration'] * 1e3:.1f} us per cycle; "
+            f"fused stack descend {k['descend'] * 1e3:.1f} us, ascend {k['ascend'] * 1e3:.1f} us"
             + (f"; FGMRES {fg['iters']} iterations, {fg['solve_ms']:.1f} ms" if fg else ""))
     return out
 

@@ -175,6 +175,16 @@ void enqueue_vcycle(mg_ctx_s &c, hipStream_t st)
         else
             launch_smooth_apply<T>(s, k.nrun, k.n, cnn, w, c.d_state, st);
     };
+    if (c.fused && stack) {
+        for (const SizeClass &k : c.classes)  // descending sizes
+            if (k.live) launch_stack_descend<T>((const CycleSlot<T> *)k.d_run, k.nrun, (k.n - 1) / 2, c.d_state, st);
+        if (c.bottom.live)
+            launch_stack_bottom<T>((const BottomSlot<T> *)c.bottom.d_run, c.bottom.nrun, c.bottom_top_n, 1, 1,
+                                   c.d_state, st);
+        for (auto it = c.classes.rbegin(); it != c.classes.rend(); ++it)  // ascending sizes
+            if (it->live) launch_stack_ascend<T>((const CycleSlot<T> *)it->d_run, it->nrun, it->n, c.d_state, st);
+        return;
+    }
     if (c.fused) {
         for (const SizeClass &k : c.classes)  // descending sizes
             if (k.live)
@@ -584,7 +594,7 @@ mg_status mg_setup(const mg_problem *probs, int32_t nprob, const mg_options *opt
     MG_TRY(require_device());
     mg_ctx c = new mg_ctx_s();
     c->opt = opt;
-    c->fused = opt.nu_pre == 1 && opt.nu_post == 1 && opt.smoother != MG_SMOOTHER_STACK;
+    c->fused = opt.nu_pre == 1 && opt.nu_post == 1;
     c->nprob = nprob;
     mg_status s = setup_impl(*c, probs, (hipStream_t)stream);
     if (s < 0) {
@@ -863,8 +873,18 @@ void launch_timed(mg_ctx_s &c, int k, const SizeClass &cls, const SizeClass &oc,
     switch (k) {
     case 0: launch_outer_residual<T>(o, oc.nslots, n, c.d_state, st); break;
     case 1: launch_check<T>(o, oc.nslots, c.d_state, c.d_params, 1, st); break;
-    case 2: launch_descend<T>(s, cls.nslots, n, cnn, w, c.d_state, st, cls.tile[0]); break;
-    case 3: launch_ascend<T>(s, cls.nslots, n, cnn, w, c.d_state, st, cls.tile[1]); break;
+    case 2:
+        if (c.opt.smoother == MG_SMOOTHER_STACK)
+            launch_stack_descend<T>(s, cls.nslots, (n - 1) / 2, c.d_state, st);
+        else
+            launch_descend<T>(s, cls.nslots, n, cnn, w, c.d_state, st, cls.tile[0]);
+        break;
+    case 3:
+        if (c.opt.smoother == MG_SMOOTHER_STACK)
+            launch_stack_ascend<T>(s, cls.nslots, n, c.d_state, st);
+        else
+            launch_ascend<T>(s, cls.nslots, n, cnn, w, c.d_state, st, cls.tile[1]);
+        break;
     case 4:
         if (c.opt.smoother == MG_SMOOTHER_STACK)
             launch_stack_bottom<T>((const BottomSlot<T> *)c.bottom.d_slots, c.nprob, c.bottom_top_n, c.opt.nu_pre,
@@ -988,7 +1008,8 @@ extern "C" mg_status mg_autotune(mg_ctx ctx, int32_t reps, const char *cache)
     MG_TRY(check_ctx(ctx));
     if (reps < 1) return set_error(MG_ERR_ARG, "reps must be >= 1");
     mg_ctx_s &c = *ctx;
-    if (!c.fused || c.classes.empty()) return MG_OK;  // no fused level kernels to shape
+    if (!c.fused || c.classes.empty() || c.opt.smoother == MG_SMOOTHER_STACK)
+        return MG_OK;  // no fused level kernels with tile choices
     std::map<std::string, int> known;
     if (cache) read_tune_cache(cache, known);
     bool timed = false;

@@ -29,6 +29,66 @@ constexpr int kRun = 8;  // rows per thread in a layer's column walk
 
 __device__ inline bool on_grid(int n, int i, int j) { return i >= 0 && i < n && j >= 0 && j < n; }
 
+// The five composed layers f5(..f1(x)) on a staged W x Hh region whose slot (0, 0)
+// is grid node (i0, j0): x in b0 (zero off the grid); layer L is computed on the
+// region one node narrower per side than layer L - 1, ping-ponging between b1
+// and b2.  Returns the buffer holding the result, valid on [5, W - 5) x [5, Hh - 5).
+// Each layer: a thread walks down one column of the region for kRun rows, keeping
+// three rows of the previous layer in registers (3 LDS reads per output instead
+// of 9).  Unrolled over layers, so every region size is a compile-time constant.
+template <typename T, int W, int Hh, int NT = kST>
+__device__ const T *stack_layers(const T *b0, T *b1, T *b2, const T MG_G *w, int i0, int j0, int n)
+{
+    const int tid = threadIdx.x;
+    const T *src = b0;
+    T *dst = b1;
+#pragma unroll
+    for (int layer = 0; layer < 5; ++layer) {
+        const int m = layer + 1;  // this layer is valid on [m, W - m) x [m, Hh - m)
+        const int rw = W - 2 * m, rh = Hh - 2 * m, chunks = (rh + kRun - 1) / kRun;
+        T k[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) k[t] = w[layer * 9 + t];
+        for (int q = tid; q < rw * chunks; q += NT) {
+            const int xx = m + q % rw, y0 = m + (q / rw) * kRun;
+            const int y1 = min(y0 + kRun, Hh - m);
+            const bool col_in = i0 + xx >= 0 && i0 + xx < n;
+            // rows y0 - 1 and y0 of the previous layer, valid on [m - 1, W - m]
+            const T *c = src + (y0 - 1) * W + (xx - 1);
+            T a0 = c[0], a1 = c[1], a2 = c[2];
+            T b0r = c[W], b1r = c[W + 1], b2r = c[W + 2];
+#pragma unroll
+            for (int r = 0; r < kRun; ++r) {
+                const int yy = y0 + r;
+                if (yy < y1) {
+                    const T *cn = src + (yy + 1) * W + (xx - 1);
+                    const T c0 = cn[0], c1 = cn[1], c2 = cn[2];
+                    const T v = k[0] * a0 + k[1] * a1 + k[2] * a2 + k[3] * b0r + k[4] * b1r + k[5] * b2r +
+                                k[6] * c0 + k[7] * c1 + k[8] * c2;
+                    const int gj = j0 + yy;
+                    dst[yy * W + xx] = col_in && gj >= 0 && gj < n ? v : (T)0;
+                    a0 = b0r, a1 = b1r, a2 = b2r;
+                    b0r = c0, b1r = c1, b2r = c2;
+                }
+            }
+        }
+        __syncthreads();
+        src = dst;
+        dst = dst == b1 ? b2 : b1;
+    }
+    return src;
+}
+
+// f6(x) at region slot (xx, yy) of a staged W-wide region, plus the layers' value lv
+// (the sum in the order of the column walks above).
+template <typename T, int W>
+__device__ inline T stack_out(const T *b0, const T (&k6)[9], T lv, int xx, int yy)
+{
+    const T *c = b0 + (yy - 1) * W + (xx - 1);
+    return lv + k6[0] * c[0] + k6[1] * c[1] + k6[2] * c[2] + k6[3] * c[W] + k6[4] * c[W + 1] + k6[5] * c[W + 2] +
+           k6[6] * c[2 * W] + k6[7] * c[2 * W + 1] + k6[8] * c[2 * W + 2];
+}
+
 // One output tile (tx, ty) of y (+)= H x.
 template <typename T>
 __device__ void stack_tile(const T MG_G *x, T MG_G *y, const T MG_G *w, int n, int P, bool acc, int tx, int ty,
@@ -41,46 +101,7 @@ __device__ void stack_tile(const T MG_G *x, T MG_G *y, const T MG_G *w, int n, i
         b0[q] = on_grid(n, gi, gj) ? x[(int64_t)gj * P + gi] : (T)0;
     }
     __syncthreads();
-    const T *src = b0;
-    T *dst = b1;
-    // Each layer: a thread walks down one column of the region for kRun rows,
-    // keeping three rows of the previous layer in registers (3 LDS reads per
-    // output instead of 9).  Unrolled over layers, so every region size is a
-    // compile-time constant.
-#pragma unroll
-    for (int layer = 0; layer < 5; ++layer) {
-        const int m = layer + 1;  // this layer is valid on [m, kLW - m) x [m, kLH - m)
-        const int rw = kLW - 2 * m, rh = kLH - 2 * m, chunks = (rh + kRun - 1) / kRun;
-        T k[9];
-#pragma unroll
-        for (int t = 0; t < 9; ++t) k[t] = w[layer * 9 + t];
-        for (int q = tid; q < rw * chunks; q += kST) {
-            const int xx = m + q % rw, y0 = m + (q / rw) * kRun;
-            const int y1 = min(y0 + kRun, kLH - m);
-            const bool col_in = i0 + xx >= 0 && i0 + xx < n;
-            // rows y0 - 1 and y0 of the previous layer, valid on [m - 1, kLW - m]
-            const T *c = src + (y0 - 1) * kLW + (xx - 1);
-            T a0 = c[0], a1 = c[1], a2 = c[2];
-            T b0r = c[kLW], b1r = c[kLW + 1], b2r = c[kLW + 2];
-#pragma unroll
-            for (int r = 0; r < kRun; ++r) {
-                const int yy = y0 + r;
-                if (yy < y1) {
-                    const T *cn = src + (yy + 1) * kLW + (xx - 1);
-                    const T c0 = cn[0], c1 = cn[1], c2 = cn[2];
-                    const T v = k[0] * a0 + k[1] * a1 + k[2] * a2 + k[3] * b0r + k[4] * b1r + k[5] * b2r +
-                                k[6] * c0 + k[7] * c1 + k[8] * c2;
-                    const int gj = j0 + yy;
-                    dst[yy * kLW + xx] = col_in && gj >= 0 && gj < n ? v : (T)0;
-                    a0 = b0r, a1 = b1r, a2 = b2r;
-                    b0r = c0, b1r = c1, b2r = c2;
-                }
-            }
-        }
-        __syncthreads();
-        src = dst;
-        dst = dst == b1 ? b2 : b1;
-    }
+    const T *src = stack_layers<T, kLW, kLH>(b0, b1, b2, w, i0, j0, n);
     // output: src holds f5(..f1(x)) on the tile; add f6(x) from the staged x, same column walk
     T k6[9];
 #pragma unroll
@@ -128,6 +149,240 @@ __global__ void __launch_bounds__(kST) k_stack_cycle(const CycleSlot<T> *slots, 
     if (!state[s.prob].active) return;  // uniform over the workgroup
     const T MG_G *w = (const T MG_G *)s.H + (mode == 2 ? kStackWeights : 0);
     stack_tile<T>(mode == 0 ? s.r : s.s, s.e, w, s.n, s.P, mode != 0, t.x, t.y, b0, b1, b2);
+}
+
+// Fused level kernels of the V(1,1) cycle with the stack smoother (the same steps,
+// in the same arithmetic, as the step kernels: stack sweep, residual and
+// restriction going down; prolongation, residual and stack sweep coming up), so
+// that the intermediate vectors stay in LDS and each level takes one launch per
+// direction.  Regions are staged with the halos the next step needs (the stack
+// reaches kHalo = 5 nodes, the stencil 1); neighbouring workgroups recompute the
+// shared halos.
+//
+// Descend, per tile of kSDX x kSDY coarse nodes:
+//   e = H r on the fine nodes the residual needs (the restriction's 2 kSDX + 1
+//   columns plus one on each side), from r staged with 5 more; e written for the
+//   fine nodes the tile owns; s = r - A e; r_c = R s (full weighting).
+constexpr int kSDX = 32, kSDY = 8;
+constexpr int kSSW = 2 * kSDX + 1, kSSH = 2 * kSDY + 1;        // residual region
+constexpr int kSEW = kSSW + 2, kSEH = kSSH + 2;                // e region
+constexpr int kSRW = kSEW + 2 * kHalo, kSRH = kSEH + 2 * kHalo;  // staged r
+static_assert(kSDX * kSDY <= kST, "one thread per coarse node of the tile");
+
+// NT threads: kST on large grids, more on the small ones, where a few workgroups run alone and
+// the length of each step (nodes per thread) sets the time
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_stack_descend(const CycleSlot<T> *slots, const SolveState *state)
+{
+    __shared__ T b0[kSRW * kSRH], b1[kSRW * kSRH], b2[kSRW * kSRH];
+    __shared__ T eb[kSEW * kSEH];
+    __shared__ T sb[kSSW * kSSH];
+    const TileId t = xcd_tile();
+    const CycleSlot<T> s = slots[t.z];
+    if (!state[s.prob].active) return;  // uniform over the workgroup
+    const int n = s.n, nc = s.nc, P = s.P, tid = threadIdx.x;
+    const int I0 = t.x * kSDX, J0 = t.y * kSDY;
+    const int sx0 = 2 * I0, sy0 = 2 * J0;           // residual region origin
+    const int ex0 = sx0 - 1, ey0 = sy0 - 1;         // e region origin
+    const int rx0 = ex0 - kHalo, ry0 = ey0 - kHalo;  // staged r origin
+    const int ox1 = (I0 + kSDX >= nc) ? n : sx0 + 2 * kSDX;  // owned fine nodes [sx0, ox1) x [sy0, oy1)
+    const int oy1 = (J0 + kSDY >= nc) ? n : sy0 + 2 * kSDY;
+    const T MG_G *w = (const T MG_G *)s.H;
+    // every global operand first (the stencil too in FP32), so that the workgroup waits for memory once
+    constexpr int NRQ = (kSRW * kSRH + NT - 1) / NT, NSQ = (kSSW * kSSH + NT - 1) / NT;
+    constexpr bool PA = sizeof(T) == 4;
+    T rq[NRQ], aq[PA ? NSQ : 1][9];
+#pragma unroll
+    for (int k = 0; k < NRQ; ++k) {
+        const int q = tid + k * NT;
+        const int gi = rx0 + q % kSRW, gj = ry0 + q / kSRW;
+        const bool ok = q < kSRW * kSRH && on_grid(n, gi, gj);
+        const T v = s.r[ok ? (int64_t)gj * P + gi : 0];
+        rq[k] = ok ? v : (T)0;
+    }
+    if (PA) {
+#pragma unroll
+        for (int k = 0; k < NSQ; ++k) {
+            const int q = tid + k * NT;
+            const int fx = sx0 + q % kSSW, fy = sy0 + q / kSSW;
+            const int64_t p = q < kSSW * kSSH && fx < n && fy < n ? (int64_t)fy * P + fx : 0;
+#pragma unroll
+            for (int c = 0; c < 9; ++c) aq[PA ? k : 0][c] = s.A[c * s.plane + p];  // unused off the grid
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NRQ; ++k) {
+        const int q = tid + k * NT;
+        if (q < kSRW * kSRH) b0[q] = rq[k];
+    }
+    __syncthreads();
+    const T *lay = stack_layers<T, kSRW, kSRH, NT>(b0, b1, b2, w, rx0, ry0, n);
+    T k6[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) k6[k] = w[45 + k];
+    for (int q = tid; q < kSEW * kSEH; q += NT) {
+        const int x = q % kSEW, y = q / kSEW;
+        const int gi = ex0 + x, gj = ey0 + y;
+        T v = 0;
+        if (on_grid(n, gi, gj)) {
+            const int xx = x + kHalo, yy = y + kHalo;
+            v = (T)0 + stack_out<T, kSRW>(b0, k6, lay[yy * kSRW + xx], xx, yy);  // e = 0 + H r
+            if (gi >= sx0 && gi < ox1 && gj >= sy0 && gj < oy1) s.e[(int64_t)gj * P + gi] = v;
+        }
+        eb[q] = v;
+    }
+    __syncthreads();
+    // s = r - A e (terms in the stencil's channel order)
+#pragma unroll
+    for (int k = 0; k < NSQ; ++k) {
+        const int q = tid + k * NT;
+        if (q >= kSSW * kSSH) break;
+        const int x = q % kSSW, y = q / kSSW;
+        const int fx = sx0 + x, fy = sy0 + y;
+        T v = 0;
+        if (fx < n && fy < n) {
+            const int64_t p = (int64_t)fy * P + fx;
+            T acc = 0;
+#pragma unroll
+            for (int c = 0; c < 9; ++c)
+                acc += (PA ? aq[PA ? k : 0][c] : s.A[c * s.plane + p]) * eb[(y + c / 3) * kSEW + x + c % 3];
+            v = b0[(y + 1 + kHalo) * kSRW + x + 1 + kHalo] - acc;
+        }
+        sb[q] = v;
+    }
+    __syncthreads();
+    const int tx = tid % kSDX, ty = tid / kSDX;
+    const int I = I0 + tx, J = J0 + ty;
+    if (tid >= kSDX * kSDY || I >= nc || J >= nc) return;
+    const int cx = 2 * tx + 1, cy = 2 * ty + 1;
+    auto S = [&](int yy, int xx) { return sb[yy * kSSW + xx]; };
+    const T acc = (T)0.0625 * (S(cy - 1, cx - 1) + S(cy - 1, cx + 1) + S(cy + 1, cx - 1) + S(cy + 1, cx + 1)) +
+                  (T)0.125 * (S(cy - 1, cx) + S(cy + 1, cx) + S(cy, cx - 1) + S(cy, cx + 1)) + (T)0.25 * S(cy, cx);
+    s.rc[(int64_t)J * s.Pc + I] = acc;
+}
+
+// Ascend, per tile of kSAX x kSAY fine nodes: e' = e + P e_c on the tile plus 6
+// nodes, s = r - A e' on the tile plus 5, e = e' + H' s on the tile (the second
+// weight set).  On the finest level the result is added to u; on the others it
+// goes to s, where the next finer level's ascent reads it as e_c (e itself is
+// still read by neighbouring tiles).
+constexpr int kSAX = kTX, kSAY = kTY;
+constexpr int kSAW = kLW, kSAH = kLH;                    // s region: the tile plus kHalo
+constexpr int kSPW = kSAW + 2, kSPH = kSAH + 2;          // e' region
+constexpr int kSCW = kSAX / 2 + 8, kSCH = kSAY / 2 + 8;  // coarse nodes under e'
+
+template <typename T, bool PA, int NT>
+__global__ void __launch_bounds__(NT) k_stack_ascend(const CycleSlot<T> *slots, const SolveState *state)
+{
+    __shared__ T cb[kSCW * kSCH];
+    __shared__ T pb[kSPW * kSPH];
+    __shared__ T b0[kLN], b1[kLN], b2[kLN];
+    const TileId t = xcd_tile();
+    const CycleSlot<T> s = slots[t.z];
+    if (!state[s.prob].active) return;  // uniform over the workgroup
+    const int n = s.n, nc = s.nc, P = s.P, tid = threadIdx.x;
+    const int X0 = t.x * kSAX, Y0 = t.y * kSAY;
+    const int sx0 = X0 - kHalo, sy0 = Y0 - kHalo;  // s region origin
+    const int px0 = sx0 - 1, py0 = sy0 - 1;        // e' region origin
+    const int cx0 = X0 / 2 - 4, cy0 = Y0 / 2 - 4;  // coarse region origin
+    const T MG_G *w = (const T MG_G *)s.H + kStackWeights;
+    // every global operand first (with PA r and the stencil too), so that the workgroup waits for
+    // memory once; without PA (large FP32 grids, where occupancy hides the latency, and FP64) r and
+    // the stencil are read in the residual step
+    constexpr int NCQ = (kSCW * kSCH + NT - 1) / NT, NPQ = (kSPW * kSPH + NT - 1) / NT;
+    constexpr int NSQ = (kLN + NT - 1) / NT;
+    T cq[NCQ], eq[NPQ], rq[PA ? NSQ : 1], aq[PA ? NSQ : 1][9];
+#pragma unroll
+    for (int k = 0; k < NCQ; ++k) {
+        const int q = tid + k * NT;
+        const int I = cx0 + q % kSCW, J = cy0 + q / kSCW;
+        const bool ok = q < kSCW * kSCH && I >= 0 && I < nc && J >= 0 && J < nc;
+        const T v = s.ec[ok ? (int64_t)J * s.Pc + I : 0];
+        cq[k] = ok ? v : (T)0;
+    }
+#pragma unroll
+    for (int k = 0; k < NPQ; ++k) {
+        const int q = tid + k * NT;
+        const int i = px0 + q % kSPW, j = py0 + q / kSPW;
+        const bool ok = q < kSPW * kSPH && on_grid(n, i, j);
+        const T v = s.e[ok ? (int64_t)j * P + i : 0];
+        eq[k] = ok ? v : (T)0;
+    }
+    if (PA) {
+#pragma unroll
+        for (int k = 0; k < NSQ; ++k) {
+            const int q = tid + k * NT;
+            const int i = sx0 + q % kSAW, j = sy0 + q / kSAW;
+            const int64_t p = q < kLN && on_grid(n, i, j) ? (int64_t)j * P + i : 0;
+            rq[PA ? k : 0] = s.r[p];  // unused off the grid
+#pragma unroll
+            for (int c = 0; c < 9; ++c) aq[PA ? k : 0][c] = s.A[c * s.plane + p];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NCQ; ++k) {
+        const int q = tid + k * NT;
+        if (q < kSCW * kSCH) cb[q] = cq[k];
+    }
+    __syncthreads();
+    // e' = e + P e_c: fine node 2I+1 takes e_c(I); even nodes half of each neighbour
+#pragma unroll
+    for (int k = 0; k < NPQ; ++k) {
+        const int q = tid + k * NT;
+        if (q >= kSPW * kSPH) break;
+        const int i = px0 + q % kSPW, j = py0 + q / kSPW;
+        T v = 0;
+        if (on_grid(n, i, j)) {
+            const int ia = (i & 1) ? (i - 1) >> 1 : (i >> 1) - 1, ib = (i & 1) ? ia : ia + 1;
+            const int ja = (j & 1) ? (j - 1) >> 1 : (j >> 1) - 1, jb = (j & 1) ? ja : ja + 1;
+            const T wx = (i & 1) ? (T)1 : (T)0.5, wy = (j & 1) ? (T)1 : (T)0.5;
+            const bool oka = ia >= 0, okb = ib < nc, okj = ja >= 0, okk = jb < nc;
+            const T c00 = cb[(ja - cy0) * kSCW + ia - cx0], c01 = cb[(ja - cy0) * kSCW + ib - cx0];
+            const T c10 = cb[(jb - cy0) * kSCW + ia - cx0], c11 = cb[(jb - cy0) * kSCW + ib - cx0];
+            const bool two_x = !(i & 1), two_y = !(j & 1);
+            T acc = (okj && oka ? c00 : (T)0) + (two_x && okj && okb ? c01 : (T)0) +
+                    (two_y && okk && oka ? c10 : (T)0) + (two_x && two_y && okk && okb ? c11 : (T)0);
+            acc *= wx * wy;
+            v = eq[k] + acc;
+        }
+        pb[q] = v;
+    }
+    __syncthreads();
+    // s = r - A e' (terms in the stencil's channel order), zero off the grid
+#pragma unroll
+    for (int k = 0; k < NSQ; ++k) {
+        const int q = tid + k * NT;
+        if (q >= kLN) break;
+        const int x = q % kSAW, y = q / kSAW;
+        const int i = sx0 + x, j = sy0 + y;
+        T v = 0;
+        if (on_grid(n, i, j)) {
+            const int64_t p = (int64_t)j * P + i;
+            T acc = 0;
+#pragma unroll
+            for (int c = 0; c < 9; ++c)
+                acc += (PA ? aq[PA ? k : 0][c] : s.A[c * s.plane + p]) * pb[(y + c / 3) * kSPW + x + c % 3];
+            v = (PA ? rq[PA ? k : 0] : s.r[p]) - acc;
+        }
+        b0[q] = v;
+    }
+    __syncthreads();
+    const T *lay = stack_layers<T, kSAW, kSAH, NT>(b0, b1, b2, w, sx0, sy0, n);
+    T k6[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) k6[k] = w[45 + k];
+    for (int q = tid; q < kSAX * kSAY; q += NT) {
+        const int i = X0 + q % kSAX, j = Y0 + q / kSAX;
+        if (i >= n || j >= n) continue;
+        const int xx = i - sx0, yy = j - sy0;
+        const T v = stack_out<T, kSAW>(b0, k6, lay[yy * kSAW + xx], xx, yy);
+        const T enew = pb[(yy + 1) * kSPW + xx + 1] + v;
+        const int64_t p = (int64_t)j * P + i;
+        if (s.u)
+            s.u[p] = s.u[p] + (double)enew;
+        else
+            s.s[p] = enew;  // not in place: neighbouring tiles read e in their halos
+    }
 }
 
 __global__ void __launch_bounds__(kST) k_stack_vecs(const double *x, double *y, int64_t vs, const double *w, int n,
@@ -364,7 +619,14 @@ __global__ void __launch_bounds__(kSBT) k_stack_bottom(const BottomSlot<T> *slot
     }
     {
         const int n = S.lev[0].n, P = S.lev[0].P, E = off[0] + sb_vec(n);
-        for (int q = tid; q < n * n; q += kSBT) S.e_out[(int64_t)(q / n) * P + q % n] = sm[E + sb_at(n, q % n, q / n)];
+        for (int q = tid; q < n * n; q += kSBT) {
+            const int64_t p = (int64_t)(q / n) * P + q % n;
+            const T e = sm[E + sb_at(n, q % n, q / n)];
+            if (S.u)
+                S.u[p] = S.u[p] + (double)e;  // the fused cycle of a problem that fits here: u += e
+            else
+                S.e_out[p] = e;
+        }
     }
 }
 
@@ -385,6 +647,31 @@ void launch_stack_cycle(const CycleSlot<T> *slots, int nslots, int n, int mode, 
 }
 template void launch_stack_cycle<float>(const CycleSlot<float> *, int, int, int, const SolveState *, hipStream_t);
 template void launch_stack_cycle<double>(const CycleSlot<double> *, int, int, int, const SolveState *, hipStream_t);
+
+template <typename T>
+void launch_stack_descend(const CycleSlot<T> *slots, int nslots, int nc, const SolveState *state, hipStream_t st)
+{
+    const dim3 g((unsigned)((nc + kSDX - 1) / kSDX), (unsigned)((nc + kSDY - 1) / kSDY), (unsigned)nslots);
+    if (nc <= 255)
+        k_stack_descend<T, 1024><<<g, 1024, 0, st>>>(slots, state);
+    else
+        k_stack_descend<T, kST><<<g, kST, 0, st>>>(slots, state);
+}
+template <typename T>
+void launch_stack_ascend(const CycleSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st)
+{
+    // the stencil in registers costs occupancy: only where the grid is too small to hide latency anyway
+    if (n > 511)
+        k_stack_ascend<T, false, kST><<<tile_grid(n, nslots), kST, 0, st>>>(slots, state);
+    else if (sizeof(T) == 4)
+        k_stack_ascend<T, true, 1024><<<tile_grid(n, nslots), 1024, 0, st>>>(slots, state);
+    else
+        k_stack_ascend<T, false, 1024><<<tile_grid(n, nslots), 1024, 0, st>>>(slots, state);
+}
+template void launch_stack_descend<float>(const CycleSlot<float> *, int, int, const SolveState *, hipStream_t);
+template void launch_stack_descend<double>(const CycleSlot<double> *, int, int, const SolveState *, hipStream_t);
+template void launch_stack_ascend<float>(const CycleSlot<float> *, int, int, const SolveState *, hipStream_t);
+template void launch_stack_ascend<double>(const CycleSlot<double> *, int, int, const SolveState *, hipStream_t);
 
 template <typename T>
 size_t stack_bottom_smem_bytes(int top_n)

@@ -16,6 +16,15 @@ template <typename T>
 void launch_stack_cycle(const CycleSlot<T> *slots, int nslots, int n, int mode, const SolveState *state,
                         hipStream_t st);
 
+// Fused V(1,1) level kernels with the stack smoother (levels with n > kBottomMax):
+// descend (e = H r, s = r - A e, r_c = R s; nc = the coarse size) and ascend
+// (e' = e + P e_c, s = r - A e', e = e' + H' s into u on the finest level, into s
+// on the others, which the next finer ascent reads as e_c).
+template <typename T>
+void launch_stack_descend(const CycleSlot<T> *slots, int nslots, int nc, const SolveState *state, hipStream_t st);
+template <typename T>
+void launch_stack_ascend(const CycleSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st);
+
 // All levels with n <= kBottomMax of every problem in one workgroup each
 // (bottom slots whose H points to each level's two weight sets); the top
 // level's r in, its e out.  prepare_stack_bottom once per compute type before.

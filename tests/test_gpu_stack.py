@@ -61,9 +61,10 @@ def _hierarchy_pair(mg, n, precision, seed, coarsest=7, f32=False):
     return A, h, ctx
 
 
-@pytest.mark.parametrize("n", [31, 63, 255])
+@pytest.mark.parametrize("n", [31, 63, 127, 255])
 def test_fp64_cycle_matches_oracle(mg, n):
-    # n = 31: the whole cycle in the one-workgroup kernel; larger: the step kernels above it
+    # n = 31: the whole cycle in the one-workgroup kernel (which adds e to u); larger: the fused
+    # stack descend / ascend kernels above it (ragged tiles at 127: 64 x 16 fine tiles, 32 x 8 coarse)
     A, h, ctx = _hierarchy_pair(mg, n, mg.PREC_FP64, 3)
     f = mg_inputs.rhs_uniform(n, 1)
     u = torch.zeros((n, n), dtype=torch.float64, device="cuda")

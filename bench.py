@@ -39,13 +39,15 @@ CNN_FLOP_PER_NODE = 2 * 9 * (9 * 32 + 32 * 32 + 32 * 32 + 32 * 25)
 # The V(1,1) solve runs outer_residual, check, descend, ascend (per level) and
 # bottom; the other kernels serve other sweep counts.  descend reads r, the
 # smoother (CNN) and the stencil and writes e and r_c; ascend (finest level)
-# reads e, e_c, r, the stencil and the smoother and updates u in place.
+# reads e, e_c, r, the stencil and the smoother and updates u in place.  The
+# outer residual of a symmetric stencil (every workload here) reads five FP64
+# planes, the other four entries being its neighbours' mirrored ones: 40 B.
 BYTES_PER_NODE = {
-    "cnn": {"outer_residual": 72 + 8 + 8 + 4, "descend": 4 + 50 + 36 + 4 + 1, "ascend": 4 + 1 + 36 + 4 + 50 + 16,
+    "cnn": {"outer_residual": 40 + 8 + 8 + 4, "descend": 4 + 50 + 36 + 4 + 1, "ascend": 4 + 1 + 36 + 4 + 50 + 16,
             "smooth_first": 50 + 4 + 4, "residual_restrict": 36 + 4 + 4 + 1,
             "prolong": 4 + 4 + 1, "residual": 36 + 4 + 4 + 4, "smooth_apply": 50 + 4 + 4 + 4,
             "update_u": 8 + 4 + 8},
-    "jacobi": {"outer_residual": 72 + 8 + 8 + 4, "descend": 4 + 36 + 4 + 1, "ascend": 4 + 1 + 36 + 4 + 16,
+    "jacobi": {"outer_residual": 40 + 8 + 8 + 4, "descend": 4 + 36 + 4 + 1, "ascend": 4 + 1 + 36 + 4 + 16,
                "smooth_first": 4 + 4 + 4, "residual_restrict": 36 + 4 + 4 + 1,
                "prolong": 4 + 4 + 1, "residual": 36 + 4 + 4 + 4, "smooth_apply": 4 + 4 + 4 + 4,
                "update_u": 8 + 4 + 8},

@@ -130,6 +130,8 @@ struct OuterSlot {
     T MG_G *r;               // level-0 inner right-hand side (the residual)
     const T MG_G *e;         // level-0 inner correction
     double MG_G *partial;    // per-block partial sums of squares
+    const int MG_G *sym;     // 1: the FP64 stencil is symmetric, A[c](p) = A[8-c](p + d_c) wherever both
+                             // nodes are on the grid (set at set-up and on a new stencil)
 };
 
 // Levels with n <= kBottomMax run inside one workgroup per problem (bottom.hip).

@@ -115,6 +115,7 @@ mg_status build_slots(mg_ctx_s &c)
         o.r = (T *)L0.r;
         o.e = (const T *)L0.e;
         o.partial = pb.partial;
+        o.sym = pb.sym;
         out[L0.n].push_back(o);
         out_probs[L0.n].push_back(p);
         (void)Lm;
@@ -315,6 +316,7 @@ void rebuild_problem(mg_ctx_s &c, int p, const double *stencil, hipStream_t st)
     const LevelBuf &L0 = pb.lev[0];
     launch_copy_field(pb.n, 9, stencil, pb.n, (int64_t)pb.n * pb.n, L0.A64, L0.P, L0.plane, st);
     launch_validate(pb.n, L0.P, L0.plane, L0.A64, c.d_flag, st);
+    launch_check_symmetric(pb.n, L0.P, L0.plane, L0.A64, pb.sym, st);
     for (int q = 0; q + 1 < pb.nlev; ++q) {
         const LevelBuf &F = pb.lev[q], &Cc = pb.lev[q + 1];
         launch_galerkin(F.n, F.P, F.plane, F.A64, Cc.P, Cc.plane, Cc.A64, st);
@@ -399,6 +401,7 @@ mg_status setup_impl(mg_ctx_s &c, const mg_problem *probs, hipStream_t user)
         MG_TRY(c.arena.alloc((void **)&pb.Ainv, (size_t)mm * mm * sizeof(double)));
         pb.nparts = outer_residual_parts(pb.n);
         MG_TRY(c.arena.alloc((void **)&pb.partial, (size_t)pb.nparts * sizeof(double)));
+        MG_TRY(c.arena.alloc((void **)&pb.sym, sizeof(int)));
         rebuild_problem(c, p, probs[p].stencil, st);
         MG_HIP(hipGetLastError());
     }

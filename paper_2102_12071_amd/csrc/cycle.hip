@@ -50,6 +50,27 @@ __device__ inline Acc apply3x3(PA A, int64_t plane, PX x, int n, int P, int i, i
     return acc;
 }
 
+// apply3x3 for a symmetric stencil: the four entries to the neighbours below and to
+// the left are read from those neighbours' mirrored planes (A[c](p) = A[8-c](p + d_c)),
+// so that only planes 4..8 are read from memory; the same values, summed in the same
+// order, as apply3x3.
+template <typename PA, typename PX, typename Acc>
+__device__ inline Acc apply3x3_sym(PA A, int64_t plane, PX x, int n, int P, int i, int j)
+{
+    const int64_t p = (int64_t)j * P + i;
+    Acc acc = 0;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        const int ii = i + c % 3 - 1, jj = j + c / 3 - 1;
+        const bool ok = ii >= 0 && ii < n && jj >= 0 && jj < n;
+        const int64_t q = ok ? (int64_t)jj * P + ii : p;
+        const Acc a = (Acc)(c < 4 ? A[(8 - c) * plane + q] : A[c * plane + p]);
+        const Acc xv = (Acc)x[q];
+        acc += a * (ok ? xv : (Acc)0);
+    }
+    return acc;
+}
+
 // (H x)_p with H stored as 25 planes of H = W / a_C.
 template <typename PH, typename PX, typename Acc>
 __device__ inline Acc apply5x5(PH H, int64_t plane, PX x, int n, int P, int i, int j)
@@ -79,7 +100,8 @@ __global__ void __launch_bounds__(kThreads) k_outer_residual(const OuterSlot<T> 
     double r = 0.0;
     if (i < s.n && j < s.n) {
         const int64_t p = (int64_t)j * s.P + i;
-        r = s.f[p] - apply3x3<decltype(s.A64), decltype(s.u), double>(s.A64, s.plane, s.u, s.n, s.P, i, j);
+        r = s.f[p] - (*s.sym ? apply3x3_sym<decltype(s.A64), decltype(s.u), double>(s.A64, s.plane, s.u, s.n, s.P, i, j)
+                             : apply3x3<decltype(s.A64), decltype(s.u), double>(s.A64, s.plane, s.u, s.n, s.P, i, j));
         s.r[p] = (T)r;
     }
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
@@ -156,6 +178,22 @@ __global__ void __launch_bounds__(kThreads)
         return;
     }
     stopping_rule(st, rr, prm, s.prob);
+}
+
+__global__ void k_sym_init(int *sym) { *sym = 1; }
+
+__global__ void __launch_bounds__(kThreads) k_sym_check(int n, int P, int64_t plane, const double *A, int *sym)
+{
+    const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (q >= (int64_t)n * n) return;
+    const int i = (int)(q % n), j = (int)(q / n);
+    const int64_t p = (int64_t)j * P + i;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int ii = i + c % 3 - 1, jj = j + c / 3 - 1;
+        if (ii < 0 || ii >= n || jj < 0 || jj >= n) continue;
+        if (!(A[c * plane + p] == A[(8 - c) * plane + (int64_t)jj * P + ii])) *sym = 0;  // every writer writes 0
+    }
 }
 
 template <typename T>
@@ -332,6 +370,12 @@ void launch_check(const OuterSlot<T> *slots, int nslots, SolveState *state, cons
                   hipStream_t st)
 {
     k_check<T><<<nslots, kThreads, 0, st>>>(slots, state, prm, init);
+}
+
+void launch_check_symmetric(int n, int P, int64_t plane, const double *A, int *sym, hipStream_t st)
+{
+    k_sym_init<<<1, 1, 0, st>>>(sym);
+    k_sym_check<<<(unsigned)(((int64_t)n * n + kThreads - 1) / kThreads), kThreads, 0, st>>>(n, P, plane, A, sym);
 }
 
 template <typename T>

@@ -76,6 +76,7 @@ struct ProbBuf {
     double *Ainv = nullptr;
     double *partial = nullptr;
     int nparts = 0;
+    int *sym = nullptr;  // device flag: the finest FP64 stencil is symmetric
 };
 
 struct SizeClass {

@@ -144,6 +144,24 @@ def test_solve_c1_fp64_matches_oracle_iterates(mg):
     assert res.relres[0] <= 1e-10
 
 
+def test_solve_nonsymmetric_stencil_matches_oracle_iterates(mg):
+    # the outer residual reads five FP64 planes when the stencil is symmetric (detected at set-up) and
+    # all nine otherwise: a skewed (non-symmetric) stencil must take the full path and still match
+    p = mg_inputs.config_c1()
+    A = ora.stencil_q1_rotated(p.n, p.theta, p.eps).copy()
+    # (a small skew: the coarsest direct solve is a Cholesky factorisation of the Galerkin matrix)
+    d = 1e-6 * np.abs(A).max()
+    A[5, :, :-1] += d   # east entries (none on the last column, which couples outside)
+    A[3, :, 1:] -= d    # west entries: rows still sum as before, A no longer symmetric
+    f = mg_inputs.rhs_uniform(p.n, p.rhs_seed)
+    ctx = mg.Context([_dev(A)], mg.Options(precision=mg.PREC_FP64, nu_pre=2, nu_post=2))
+    res = ctx.solve([_dev(f)], 1e-10, 1000, history=True)
+    u_ref, k, hist, conv = ora.Hierarchy(A).solve(f, 1e-10, 1000, 2, 2)
+    assert conv and res.status[0] == 0 and res.iters[0] == k
+    assert np.allclose(res.history[0, :k + 1], hist, rtol=1e-9, atol=1e-14)
+    assert _rel(res.u[0].cpu().numpy(), u_ref) <= 1e-11
+
+
 # ------------------------------------------------------------ mixed precision
 def test_solve_c1_mixed_jacobi(mg):
     p = mg_inputs.config_c1()

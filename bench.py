@@ -33,23 +33,28 @@ BF16_MFMA_PEAK_TFLOPS = 2500.0  # MI355X dense BF16
 CNN_FLOP_PER_NODE = 2 * 9 * (9 * 32 + 32 * 32 + 32 * 32 + 32 * 25)
 
 # Algorithmic bytes per finest-level node of each timed kernel (mixed
-# precision: FP64 stencil 72 B and FP64 u/f in the outer residual, FP32
-# stencil 36 B and FP32 vectors in the cycle, BF16 5x5 smoother 50 B; the
-# coarse vector of the restriction/prolongation counts 1/4 of 4 B).
+# precision: FP64 stencil and FP64 u/f in the outer residual, FP32 stencil and
+# FP32 vectors in the cycle, BF16 5x5 smoother 50 B; the coarse vector of the
+# restriction/prolongation counts 1/4 of 4 B).
 # The V(1,1) solve runs outer_residual, check, descend, ascend (per level) and
 # bottom; the other kernels serve other sweep counts.  descend reads r, the
 # smoother (CNN) and the stencil and writes e and r_c; ascend (finest level)
-# reads e, e_c, r, the stencil and the smoother and updates u in place.  The
-# outer residual of a symmetric stencil (every workload here) reads five FP64
-# planes, the other four entries being its neighbours' mirrored ones: 40 B.
+# reads e, e_c, r, the stencil and the smoother and updates u in place.  A
+# symmetric stencil (every workload here) is read as five of its nine planes,
+# the other four entries being the neighbours' mirrored ones: 40 B in FP64,
+# 20 B in FP32 (72 and 36 B for a stencil that is not symmetric).  The step
+# kernels of other sweep counts read all nine FP32 planes.
+A64_SYM, A32_SYM, A32 = 40, 20, 36
 BYTES_PER_NODE = {
-    "cnn": {"outer_residual": 40 + 8 + 8 + 4, "descend": 4 + 50 + 36 + 4 + 1, "ascend": 4 + 1 + 36 + 4 + 50 + 16,
-            "smooth_first": 50 + 4 + 4, "residual_restrict": 36 + 4 + 4 + 1,
-            "prolong": 4 + 4 + 1, "residual": 36 + 4 + 4 + 4, "smooth_apply": 50 + 4 + 4 + 4,
+    "cnn": {"outer_residual": A64_SYM + 8 + 8 + 4, "descend": 4 + 50 + A32_SYM + 4 + 1,
+            "ascend": 4 + 1 + A32_SYM + 4 + 50 + 16,
+            "smooth_first": 50 + 4 + 4, "residual_restrict": A32_SYM + 4 + 4 + 1,
+            "prolong": 4 + 4 + 1, "residual": A32 + 4 + 4 + 4, "smooth_apply": 50 + 4 + 4 + 4,
             "update_u": 8 + 4 + 8},
-    "jacobi": {"outer_residual": 40 + 8 + 8 + 4, "descend": 4 + 36 + 4 + 1, "ascend": 4 + 1 + 36 + 4 + 16,
-               "smooth_first": 4 + 4 + 4, "residual_restrict": 36 + 4 + 4 + 1,
-               "prolong": 4 + 4 + 1, "residual": 36 + 4 + 4 + 4, "smooth_apply": 4 + 4 + 4 + 4,
+    "jacobi": {"outer_residual": A64_SYM + 8 + 8 + 4, "descend": 4 + A32_SYM + 4 + 1,
+               "ascend": 4 + 1 + A32_SYM + 4 + 16,
+               "smooth_first": 4 + 4 + 4, "residual_restrict": A32_SYM + 4 + 4 + 1,
+               "prolong": 4 + 4 + 1, "residual": A32 + 4 + 4 + 4, "smooth_apply": 4 + 4 + 4 + 4,
                "update_u": 8 + 4 + 8},
 }
 SOLVE_KERNELS = ("outer_residual", "descend", "ascend")  # per-node kernels of the V(1,1) solve
@@ -414,9 +419,9 @@ def stack_block(args, A, f, n, theta, eps, coarsest):
     the symmetric one with H^T after the coarse correction): iterations and
     time to the tolerance, and the rates of the fused stack level kernels on the
     finest level (FP32 algorithmic traffic per fine node: descend reads r and the
-    nine stencil planes and writes e and a quarter node of r_c, 45 B; the finest
-    ascend reads a quarter node of e_c, e, r, the stencil and reads and writes u
-    in FP64, 61 B)."""
+    five stencil planes of a symmetric stencil and writes e and a quarter node of
+    r_c, 29 B; the finest ascend reads a quarter node of e_c, e, r, the stencil
+    and reads and writes u in FP64, 45 B)."""
     import glob
 
     import torch
@@ -454,7 +459,7 @@ def stack_block(args, A, f, n, theta, eps, coarsest):
         nn = float(n) * n
         kern = {name: {"ms": k[name], "algorithmic_bytes": per * nn,
                        "achieved_gbs": per * nn / (k[name] * 1e-3) / 1e9}
-                for name, per in (("descend", 45.0), ("ascend", 61.0))}
+                for name, per in (("descend", 4.0 + A32_SYM + 4 + 1), ("ascend", 1.0 + 4 + 4 + A32_SYM + 16))}
         out.append({"weights": os.path.relpath(path, os.path.dirname(os.path.abspath(__file__))),
                     "symmetric": symmetric, "trained_sizes": sorted(stacks), "iters": int(res.iters[0]),
                     "status": int(res.status[0]), "relres": float(res.relres[0]), "solve_ms": ms,

@@ -116,7 +116,21 @@ struct CycleSlot {
     T MG_G *ec;
     int nc, Pc;
     double MG_G *u;                                    // finest level only: the fused ascent adds e to u
+    const int MG_G *sym;                               // 1: A[c](p) = A[8-c](p + d_c) wherever both nodes are
+                                                       // on the grid (set with the level's stencil)
 };
+
+// Index of stencil entry c of node p (row pitch P, plane stride plane).  With a
+// symmetric stencil (CycleSlot::sym) the entries to the row below and to the left
+// neighbour come from the mirrored plane at that neighbour, A[c](p) =
+// A[8-c](p + d_c), so planes 0..3 are never read: the same values.  An entry
+// that points off the grid multiplies a zero correction either way; its
+// mirrored index stays inside the nine planes (planes 5..8, one row and one
+// column out at most), at a finite entry or the zero padding.
+__device__ inline int64_t stencil_index(int c, bool sym, int64_t plane, int P, int64_t p)
+{
+    return (c < 4 && sym) ? (8 - c) * plane + p + (int64_t)(c / 3 - 1) * P + (c % 3 - 1) : c * plane + p;
+}
 
 // Finest level of a problem: FP64 state and the outer residual.
 template <typename T>

@@ -87,6 +87,7 @@ mg_status build_slots(mg_ctx_s &c)
             s.P = L.P;
             s.plane = L.plane;
             s.A = stencil_of<T>(L);
+            s.sym = L.sym;
             // with the stack smoother, H points to the level's 54 weights (type T)
             s.H = c.opt.smoother == MG_SMOOTHER_STACK ? (const HT *)L.phi : (const HT *)L.H;
             s.r = (T *)L.r;
@@ -309,7 +310,7 @@ void destroy_ctx(mg_ctx c)
 }
 
 // Finest stencil into the pitched layout (checked), the Galerkin levels in
-// FP64, their FP32 copies, and the coarsest inverse.
+// FP64, their FP32 copies, each level's symmetry flag, and the coarsest inverse.
 void rebuild_problem(mg_ctx_s &c, int p, const double *stencil, hipStream_t st)
 {
     ProbBuf &pb = c.probs[p];
@@ -321,8 +322,15 @@ void rebuild_problem(mg_ctx_s &c, int p, const double *stencil, hipStream_t st)
         const LevelBuf &F = pb.lev[q], &Cc = pb.lev[q + 1];
         launch_galerkin(F.n, F.P, F.plane, F.A64, Cc.P, Cc.plane, Cc.A64, st);
     }
-    if (c.opt.precision == MG_PREC_MIXED)
-        for (int q = 0; q < pb.nlev; ++q) launch_to_f32(9 * pb.lev[q].plane, pb.lev[q].A64, pb.lev[q].A32, st);
+    for (int q = 0; q < pb.nlev; ++q) {
+        const LevelBuf &L = pb.lev[q];
+        if (c.opt.precision == MG_PREC_MIXED) {
+            launch_to_f32(9 * L.plane, L.A64, L.A32, st);
+            launch_check_symmetric(L.n, L.P, L.plane, L.A32, L.sym, st);
+        } else {
+            launch_check_symmetric(L.n, L.P, L.plane, L.A64, L.sym, st);
+        }
+    }
     const LevelBuf &Lm = pb.lev[pb.nlev - 1];
     launch_coarse_factor(Lm.n, Lm.P, Lm.plane, Lm.A64, pb.Ainv, c.d_flag, st);
 }
@@ -386,6 +394,7 @@ mg_status setup_impl(mg_ctx_s &c, const mg_problem *probs, hipStream_t user)
             if (mixed) MG_TRY(c.arena.alloc((void **)&L.A32, 9 * v * sizeof(float)));
             MG_TRY(c.arena.alloc(&L.r, v * tsize(c)));
             MG_TRY(c.arena.alloc(&L.e, v * tsize(c)));
+            MG_TRY(c.arena.alloc((void **)&L.sym, sizeof(int)));
             ++l;
             if (m == c.opt.coarsest_n) break;
             MG_TRY(c.arena.alloc(&L.H, kSmoother * v * hsize(c)));

@@ -182,7 +182,8 @@ __global__ void __launch_bounds__(kThreads)
 
 __global__ void k_sym_init(int *sym) { *sym = 1; }
 
-__global__ void __launch_bounds__(kThreads) k_sym_check(int n, int P, int64_t plane, const double *A, int *sym)
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_sym_check(int n, int P, int64_t plane, const T *A, int *sym)
 {
     const int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (q >= (int64_t)n * n) return;
@@ -372,11 +373,14 @@ void launch_check(const OuterSlot<T> *slots, int nslots, SolveState *state, cons
     k_check<T><<<nslots, kThreads, 0, st>>>(slots, state, prm, init);
 }
 
-void launch_check_symmetric(int n, int P, int64_t plane, const double *A, int *sym, hipStream_t st)
+template <typename T>
+void launch_check_symmetric(int n, int P, int64_t plane, const T *A, int *sym, hipStream_t st)
 {
     k_sym_init<<<1, 1, 0, st>>>(sym);
-    k_sym_check<<<(unsigned)(((int64_t)n * n + kThreads - 1) / kThreads), kThreads, 0, st>>>(n, P, plane, A, sym);
+    k_sym_check<T><<<(unsigned)(((int64_t)n * n + kThreads - 1) / kThreads), kThreads, 0, st>>>(n, P, plane, A, sym);
 }
+template void launch_check_symmetric<float>(int, int, int64_t, const float *, int *, hipStream_t);
+template void launch_check_symmetric<double>(int, int, int64_t, const double *, int *, hipStream_t);
 
 template <typename T>
 void launch_update_u(const OuterSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st)

@@ -39,11 +39,17 @@ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 // Tile shapes (threads per workgroup kT; descend: kCX x kCY coarse nodes,
 // ascend: kFX x kFY fine nodes).  Every shape computes each node with the same
 // arithmetic in the same order, so the choice changes speed only; the
-// autotuner picks one per level size.
-#define MG_DESCEND_TILES(X) X(0, 32, 8, 512) X(1, 32, 4, 256) X(2, 16, 8, 256) X(3, 32, 16, 1024) X(4, 64, 8, 1024)
+// autotuner picks one per level size.  The descent's thread counts are its
+// correction region's pair count rounded up to whole waves (646 pairs for
+// 32 x 8 coarse nodes: 704 threads, 11 waves), so that each thread smooths one
+// pair and loads one pair's smoother taps: no second pass over the region with
+// most of its lanes idle, and half the registers (two passes of 512 threads
+// needed 120 VGPRs).  Some ascent shapes are fitted the same way (128 x 8 fine
+// nodes: 952 correction pairs, 960 threads).
+#define MG_DESCEND_TILES(X) X(0, 32, 8, 704) X(1, 32, 4, 384) X(2, 16, 8, 384) X(3, 30, 8, 640) X(4, 28, 8, 576)
 #define MG_ASCEND_TILES(X)                                                                                     \
     X(0, 64, 16, 512) X(1, 64, 8, 256) X(2, 128, 8, 512) X(3, 64, 32, 1024) X(4, 128, 16, 1024)            \
-    X(5, 256, 8, 1024) X(6, 32, 16, 256) X(7, 128, 32, 1024) X(8, 256, 16, 1024)
+    X(5, 256, 8, 1024) X(6, 32, 16, 256) X(7, 128, 8, 960) X(8, 32, 16, 448)
 // The descent split in two launches: the pre-smoothing sweep on owned fine
 // tiles of FX x FY nodes (NT1 threads), then residual and restriction on
 // coarse tiles of CX x CY nodes (NT2 threads) reading e back.  It moves 8 more
@@ -84,6 +90,25 @@ __device__ inline void st2(T MG_G *b, int64_t p, typename Pair<T>::type v)
     *(typename Pair<T>::type MG_G *)(b + p) = v;
 }
 
+// The nine stencil entries of a pair of nodes at p (stencil_index: five planes
+// of a symmetric stencil).  A mirrored pair starts at an odd column for the
+// diagonal and left entries: a 4-byte aligned load.
+template <typename T> struct PairU;
+template <> struct PairU<float> { typedef float type __attribute__((ext_vector_type(2), aligned(4))); };
+template <> struct PairU<double> { typedef double type __attribute__((ext_vector_type(2), aligned(8))); };
+template <typename T>
+__device__ inline void ld_stencil(const T MG_G *A, int64_t plane, int P, bool sym, int64_t p,
+                                  typename Pair<T>::type (&a)[9])
+{
+    typedef typename PairU<T>::type U;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        const U v = *(const U MG_G *)(A + stencil_index(c, sym, plane, P, p));
+        a[c].x = v.x;
+        a[c].y = v.y;
+    }
+}
+
 // The FP64 parity cycle keeps its smoother taps in memory until they are used
 // (two doubles per tap and pair would not fit the register file).
 template <typename T> struct PrefetchH { static constexpr bool value = sizeof(T) == 4; };
@@ -116,6 +141,7 @@ __global__ void __launch_bounds__(kT) k_descend(const CycleSlot<T> *slots, const
     const TileId tile = xcd_tile();
     const CycleSlot<T> s = slots[tile.z];
     if (!state[s.prob].active) return;
+    const bool sym = *s.sym != 0;
     const int n = s.n, nc = s.nc;
     const int I0 = tile.x * kCX, J0 = tile.y * kCY;
     const int sx0 = 2 * I0, sy0 = 2 * J0;
@@ -160,8 +186,7 @@ __global__ void __launch_bounds__(kT) k_descend(const CycleSlot<T> *slots, const
         const int q = tid + k * kT;
         const int i = sx0 + 2 * (q % SXP), j = sy0 + q / SXP;
         const int64_t p = q < NS && pair_ok(i, j) ? (int64_t)j * s.P + i : 0;
-#pragma unroll
-        for (int c = 0; c < 9; ++c) av[k][c] = ld2(s.A, c * s.plane + p);  // unused off the grid
+        ld_stencil(s.A, s.plane, s.P, sym, p, av[k]);  // unused off the grid
     }
     // ---- r tile
 #pragma unroll
@@ -363,6 +388,7 @@ __global__ void __launch_bounds__(kT) k_resrestrict(const CycleSlot<T> *slots, c
     const TileId tile = xcd_tile();
     const CycleSlot<T> s = slots[tile.z];
     if (!state[s.prob].active) return;
+    const bool sym = *s.sym != 0;
     const int n = s.n, nc = s.nc;
     const int I0 = tile.x * kCX, J0 = tile.y * kCY;
     const int sx0 = 2 * I0, sy0 = 2 * J0;
@@ -387,8 +413,7 @@ __global__ void __launch_bounds__(kT) k_resrestrict(const CycleSlot<T> *slots, c
         const int i = sx0 + 2 * (q % SXP), j = sy0 + q / SXP;
         const int64_t p = q < NS && pair_ok(i, j) ? (int64_t)j * s.P + i : 0;
         rv[k] = ld2(s.r, p);  // unused off the grid
-#pragma unroll
-        for (int c = 0; c < 9; ++c) av[k][c] = ld2(s.A, c * s.plane + p);
+        ld_stencil(s.A, s.plane, s.P, sym, p, av[k]);
     }
 #pragma unroll
     for (int k = 0; k < IE; ++k) {
@@ -466,6 +491,7 @@ __global__ void __launch_bounds__(kT) k_ascend(const CycleSlot<T> *slots, const 
     const TileId tile = xcd_tile();
     const CycleSlot<T> s = slots[tile.z];
     if (!state[s.prob].active) return;
+    const bool sym = *s.sym != 0;
     const int n = s.n, nc = s.nc;
     const int X0 = tile.x * kFX, Y0 = tile.y * kFY;
     const int sxo = X0 - SH, syo = Y0 - SH;          // s region origin
@@ -504,8 +530,7 @@ __global__ void __launch_bounds__(kT) k_ascend(const CycleSlot<T> *slots, const 
         const T2 v = ld2(s.r, p);
         rv[k].x = ok ? v.x : (T)0;
         rv[k].y = ok && i + 1 < n ? v.y : (T)0;
-#pragma unroll
-        for (int c = 0; c < 9; ++c) av[k][c] = ld2(s.A, c * s.plane + p);  // unused off the grid
+        ld_stencil(s.A, s.plane, s.P, sym, p, av[k]);  // unused off the grid
     }
     H2 hv[IO][PH ? NH : 1];
     T2 acv[IO];

@@ -67,6 +67,8 @@ struct LevelBuf {
     void *phi = nullptr;   // stack smoother: 2 x 54 weights (float or double; before and after the coarse
                            // correction), levels above the coarsest
     bool phi_set = false;  // mg_set_stack has installed them
+    int *sym = nullptr;    // device flag: the stencil the cycle reads on this level (FP32 in the mixed
+                           // cycle, FP64 otherwise) is symmetric
 };
 
 struct ProbBuf {

@@ -19,7 +19,8 @@ void launch_copy_field(int n, int nch, const double *src, int Ps, int64_t planes
 void launch_to_f32(int64_t count, const double *src, float *dst, hipStream_t st);
 void launch_validate(int n, int P, int64_t plane, const double *A, int *flag, hipStream_t st);
 // *sym = 1 if A[c](p) == A[8-c](p + d_c) for c < 4 wherever both nodes are on the grid, else 0.
-void launch_check_symmetric(int n, int P, int64_t plane, const double *A, int *sym, hipStream_t st);
+template <typename T>
+void launch_check_symmetric(int n, int P, int64_t plane, const T *A, int *sym, hipStream_t st);
 // Dirichlet nodes of a domain mask (0 = outside) on a dense [9][n][n] stencil; out may alias A.
 void launch_mask(int n, const uint8_t *mask, const double *A, double *out, hipStream_t st);
 

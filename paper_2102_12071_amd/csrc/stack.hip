@@ -180,6 +180,7 @@ __global__ void __launch_bounds__(NT) k_stack_descend(const CycleSlot<T> *slots,
     const TileId t = xcd_tile();
     const CycleSlot<T> s = slots[t.z];
     if (!state[s.prob].active) return;  // uniform over the workgroup
+    const bool sym = *s.sym != 0;
     const int n = s.n, nc = s.nc, P = s.P, tid = threadIdx.x;
     const int I0 = t.x * kSDX, J0 = t.y * kSDY;
     const int sx0 = 2 * I0, sy0 = 2 * J0;           // residual region origin
@@ -207,7 +208,7 @@ __global__ void __launch_bounds__(NT) k_stack_descend(const CycleSlot<T> *slots,
             const int fx = sx0 + q % kSSW, fy = sy0 + q / kSSW;
             const int64_t p = q < kSSW * kSSH && fx < n && fy < n ? (int64_t)fy * P + fx : 0;
 #pragma unroll
-            for (int c = 0; c < 9; ++c) aq[PA ? k : 0][c] = s.A[c * s.plane + p];  // unused off the grid
+            for (int c = 0; c < 9; ++c) aq[PA ? k : 0][c] = s.A[stencil_index(c, sym, s.plane, P, p)];  // unused off the grid
         }
     }
 #pragma unroll
@@ -245,7 +246,7 @@ __global__ void __launch_bounds__(NT) k_stack_descend(const CycleSlot<T> *slots,
             T acc = 0;
 #pragma unroll
             for (int c = 0; c < 9; ++c)
-                acc += (PA ? aq[PA ? k : 0][c] : s.A[c * s.plane + p]) * eb[(y + c / 3) * kSEW + x + c % 3];
+                acc += (PA ? aq[PA ? k : 0][c] : s.A[stencil_index(c, sym, s.plane, P, p)]) * eb[(y + c / 3) * kSEW + x + c % 3];
             v = b0[(y + 1 + kHalo) * kSRW + x + 1 + kHalo] - acc;
         }
         sb[q] = v;
@@ -280,6 +281,7 @@ __global__ void __launch_bounds__(NT) k_stack_ascend(const CycleSlot<T> *slots, 
     const TileId t = xcd_tile();
     const CycleSlot<T> s = slots[t.z];
     if (!state[s.prob].active) return;  // uniform over the workgroup
+    const bool sym = *s.sym != 0;
     const int n = s.n, nc = s.nc, P = s.P, tid = threadIdx.x;
     const int X0 = t.x * kSAX, Y0 = t.y * kSAY;
     const int sx0 = X0 - kHalo, sy0 = Y0 - kHalo;  // s region origin
@@ -316,7 +318,7 @@ __global__ void __launch_bounds__(NT) k_stack_ascend(const CycleSlot<T> *slots, 
             const int64_t p = q < kLN && on_grid(n, i, j) ? (int64_t)j * P + i : 0;
             rq[PA ? k : 0] = s.r[p];  // unused off the grid
 #pragma unroll
-            for (int c = 0; c < 9; ++c) aq[PA ? k : 0][c] = s.A[c * s.plane + p];
+            for (int c = 0; c < 9; ++c) aq[PA ? k : 0][c] = s.A[stencil_index(c, sym, s.plane, P, p)];
         }
     }
 #pragma unroll
@@ -361,7 +363,7 @@ __global__ void __launch_bounds__(NT) k_stack_ascend(const CycleSlot<T> *slots, 
             T acc = 0;
 #pragma unroll
             for (int c = 0; c < 9; ++c)
-                acc += (PA ? aq[PA ? k : 0][c] : s.A[c * s.plane + p]) * pb[(y + c / 3) * kSPW + x + c % 3];
+                acc += (PA ? aq[PA ? k : 0][c] : s.A[stencil_index(c, sym, s.plane, P, p)]) * pb[(y + c / 3) * kSPW + x + c % 3];
             v = (PA ? rq[PA ? k : 0] : s.r[p]) - acc;
         }
         b0[q] = v;

@@ -56,10 +56,12 @@ constexpr int ceil_div(int a, int b) { return (a + b - 1) / b; }
 // bytes per node (e written and read) but reads every smoother entry once, on
 // aligned rows, instead of recomputing e on a one-node ring around each tile.
 // Taller residual tiles recompute fewer shared rows (a tile's residual region overlaps the next one's by
-// one fine row and one pair of columns).
+// one fine row and one pair of columns).  The residual-restriction thread counts are fitted to the
+// residual region as the descent's are to its correction region (56 x 8 coarse nodes: 969 pairs on
+// 1024 threads).
 #define MG_SPLIT_TILES(X)                                                                                      \
-    X(5, 64, 16, 512, 32, 8, 512) X(6, 128, 8, 512, 64, 8, 1024) X(7, 128, 8, 512, 64, 16, 1024)          \
-    X(8, 128, 8, 512, 32, 32, 1024)
+    X(5, 64, 16, 512, 32, 8, 704) X(6, 128, 8, 512, 56, 8, 1024) X(7, 128, 8, 512, 28, 16, 960)           \
+    X(8, 128, 8, 512, 64, 8, 1024)
 
 template <typename T> struct Pair { typedef T type __attribute__((ext_vector_type(2))); };
 

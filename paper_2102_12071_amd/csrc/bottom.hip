@@ -16,6 +16,15 @@
 // inverse goes to LDS.  The FP64 parity cycle, whose entries are twice as
 // wide, reads them from memory in each step instead.
 //
+// With prm given, the workgroup also applies the solver's stopping rule to the
+// residual the outer residual kernel left in its block sums (the rule of the
+// iteration, folded in here to save a launch per cycle): every thread loads
+// and sums its share of the block sums with its other loads, the waves' sums
+// meet in LDS, one thread otherwise idle in the first smoothing step applies
+// the rule, and the correction reaches u only if the problem goes on.  The
+// finer levels' descent has run on that residual either way; when the problem
+// stops here, its ascent kernels find it inactive and skip.
+//
 // LDS vectors of a level with n nodes per side have pitch W = n + 5: the
 // n + 1 slots of a row (the last one is padding) plus a border of two zero
 // slots on each side and two zero rows above and below, so the 3x3 and 5x5
@@ -49,9 +58,11 @@ __device__ inline Lay lay_of(int n)
 __device__ inline int at(const Lay &L, int i, int j) { return (j + 2) * L.W + i + 2; }
 
 template <typename T, bool CNN>
-__global__ void __launch_bounds__(kBT) k_bottom(const BottomSlot<T> *slots, const SolveState *state, T omega,
-                                                int nu1, int nu2)
+__global__ void __launch_bounds__(kBT) k_bottom(const BottomSlot<T> *slots, SolveState *state, T omega, int nu1,
+                                                int nu2, const SolveParams *prm)
 {
+    __shared__ double wsum[kBT / 64];
+    __shared__ int go;
     typedef typename SmootherStore<T>::type HT;
     typedef typename Vec2<T>::type T2;
     typedef typename Vec2<HT>::type H2;
@@ -136,6 +147,21 @@ __global__ void __launch_bounds__(kBT) k_bottom(const BottomSlot<T> *slots, cons
             for (int t = 0; t < (PF && CNN ? 25 : 1); ++t) hreg[t] = *(const uint32_t MG_G *)(Hb + t * hplane + pp);
         }
     }
+    // the outer residual's block sums, four independent partial sums per thread (the order of k_check
+    // with kBT threads); summed per wave once the loads are in
+    const bool check = prm != nullptr;  // uniform
+    double rr0 = 0.0, rr1 = 0.0, rr2 = 0.0, rr3 = 0.0;
+    if (check) {
+        const int np = state[S.prob].nparts;
+        int q = tid;
+        for (; q + 3 * kBT < np; q += 4 * kBT) {
+            rr0 += S.partial[q];
+            rr1 += S.partial[q + kBT];
+            rr2 += S.partial[q + 2 * kBT];
+            rr3 += S.partial[q + 3 * kBT];
+        }
+        for (; q < np; q += kBT) rr0 += S.partial[q];
+    }
     // ---- LDS: clear every vector (borders and padding stay zero), the inverse, r of the top level
     for (int q = tid; q < total_vec; q += kBT) sm[q] = (T)0;
 #pragma unroll
@@ -143,7 +169,18 @@ __global__ void __launch_bounds__(kBT) k_bottom(const BottomSlot<T> *slots, cons
         const int q = tid + k * kBT;
         if (q < mm * mm) ainv[q] = av[k];
     }
+    if (check) {
+        const double w = wave_sum((rr0 + rr1) + (rr2 + rr3));
+        if ((tid & 63) == 0) wsum[tid >> 6] = w;
+    }
     __syncthreads();
+    if (check && tid == kBT - 1) {  // a thread with no node on any level (they number at most 512 + 340)
+        double rr = 0.0;
+        for (int w = 0; w < kBT / 64; ++w) rr += wsum[w];
+        SolveState &st = state[S.prob];
+        stopping_rule(st, rr, prm, S.prob);
+        go = st.active;
+    }
     if (in0) {
         T2 v = rin;
         v.y = pi + 1 < L0.n ? v.y : (T)0;
@@ -339,6 +376,7 @@ __global__ void __launch_bounds__(kBT) k_bottom(const BottomSlot<T> *slots, cons
             __syncthreads();
         }
     }
+    if (check && !go) return;  // stopped by the rule: u keeps its value (read after the barriers above)
     if (in0) {
         const T2 e = *(const T2 *)(sm + L0.vec + at(L0, pi, pj));
         if (S.u) {
@@ -369,13 +407,13 @@ size_t bottom_smem_bytes(int top_n)
 
 template <typename T>
 void launch_bottom(const BottomSlot<T> *slots, int nslots, int top_n, bool cnn, double omega, int nu1, int nu2,
-                   const SolveState *state, hipStream_t st)
+                   SolveState *state, const SolveParams *prm, hipStream_t st)
 {
     const size_t smem = bottom_smem_bytes<T>(top_n);
     if (cnn)
-        k_bottom<T, true><<<nslots, kBT, smem, st>>>(slots, state, (T)omega, nu1, nu2);
+        k_bottom<T, true><<<nslots, kBT, smem, st>>>(slots, state, (T)omega, nu1, nu2, prm);
     else
-        k_bottom<T, false><<<nslots, kBT, smem, st>>>(slots, state, (T)omega, nu1, nu2);
+        k_bottom<T, false><<<nslots, kBT, smem, st>>>(slots, state, (T)omega, nu1, nu2, prm);
 }
 
 template <typename T>
@@ -390,10 +428,10 @@ void prepare_bottom()
 
 template size_t bottom_smem_bytes<float>(int);
 template size_t bottom_smem_bytes<double>(int);
-template void launch_bottom<float>(const BottomSlot<float> *, int, int, bool, double, int, int, const SolveState *,
-                                   hipStream_t);
-template void launch_bottom<double>(const BottomSlot<double> *, int, int, bool, double, int, int,
-                                    const SolveState *, hipStream_t);
+template void launch_bottom<float>(const BottomSlot<float> *, int, int, bool, double, int, int, SolveState *,
+                                   const SolveParams *, hipStream_t);
+template void launch_bottom<double>(const BottomSlot<double> *, int, int, bool, double, int, int, SolveState *,
+                                    const SolveParams *, hipStream_t);
 template void prepare_bottom<float>();
 template void prepare_bottom<double>();
 

@@ -169,6 +169,7 @@ struct BottomSlot {
     const T MG_G *r_in;                        // top level right-hand side (pitch lev[0].P)
     T MG_G *e_out;                             // top level correction
     double MG_G *u;                            // when the top level is the finest of a fused cycle: u += e
+    const double MG_G *partial;                // the outer residual's block sums (the stopping rule folded in)
 };
 
 // Per-problem solver state on the device.
@@ -200,5 +201,39 @@ struct SolveParams {
     double *history;  // [nprob][hist_stride] or null
     int fallback;     // 1: a stalled or diverging learned smoother requests the switch to damped Jacobi
 };
+
+// The stopping rule of the solver (section 6.1) for one problem, given
+// rr = ||f - A u||^2; called by one thread.
+__device__ inline void stopping_rule(SolveState &st, double rr, const SolveParams *prm, int prob)
+{
+    const double rel = st.fnorm > 0.0 ? sqrt(rr) / st.fnorm : 0.0;
+    st.relres = rel;
+    if (prm->history) prm->history[(int64_t)prob * prm->hist_stride + st.iters] = rel;
+    if (rel < st.best * (1.0 - kStallGain)) {
+        st.best = rel;
+        st.stall = 0;
+    } else {
+        st.stall += 1;
+    }
+    const bool diverging = !isfinite(rel) || rel > kDivergeFactor * st.best;
+    if (rel <= prm->tol) {
+        st.active = 0;
+        st.status = 0;
+    } else if (prm->fallback && st.fallback == 0 && (diverging || st.stall >= kStallCycles) &&
+               st.iters < prm->maxit) {
+        // pause (no cycle is applied); the host switches the problem to damped Jacobi and resumes it
+        st.active = 0;
+        st.status = 2;
+        st.fallback = diverging ? 3 : 1;
+    } else if (!isfinite(rel) || rel > 1e3) {
+        st.active = 0;
+        st.status = -4;
+    } else if (st.iters >= prm->maxit) {
+        st.active = 0;
+        st.status = 1;
+    } else {
+        st.iters += 1;
+    }
+}
 
 }  // namespace mg

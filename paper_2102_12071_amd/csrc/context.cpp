@@ -135,6 +135,7 @@ mg_status build_slots(mg_ctx_s &c)
         b.r_in = (const T *)pb.lev[top].r;
         b.e_out = (T *)pb.lev[top].e;
         b.u = (c.fused && top == 0) ? pb.u : nullptr;
+        b.partial = pb.partial;
         bottom.push_back(b);
         c.bottom_top_n = std::max(c.bottom_top_n, pb.lev[top].n);
     }
@@ -162,9 +163,10 @@ mg_status build_slots(mg_ctx_s &c)
 // One V-cycle e = V(r) on every active problem (Algorithm 1, correction form).
 // V(1,1) runs the fused level kernels (descend, bottom, ascend), which add
 // the finest correction to u themselves; other sweep counts run the
-// step-by-step kernels and leave u += e to enqueue_update.
+// step-by-step kernels and leave u += e to enqueue_update.  check: the fused
+// bottom kernel also applies the stopping rule (see enqueue_iteration).
 template <typename T>
-void enqueue_vcycle(mg_ctx_s &c, hipStream_t st)
+void enqueue_vcycle(mg_ctx_s &c, hipStream_t st, const SolveParams *check = nullptr)
 {
     const bool cnn = c.opt.smoother == MG_SMOOTHER_CNN, stack = c.opt.smoother == MG_SMOOTHER_STACK;
     const double w = c.opt.omega;
@@ -193,7 +195,7 @@ void enqueue_vcycle(mg_ctx_s &c, hipStream_t st)
                 launch_descend<T>((const CycleSlot<T> *)k.d_run, k.nrun, k.n, cnn, w, c.d_state, st, k.tile[0]);
         if (c.bottom.live)
             launch_bottom<T>((const BottomSlot<T> *)c.bottom.d_run, c.bottom.nrun, c.bottom_top_n, cnn, w, 1, 1,
-                             c.d_state, st);
+                             c.d_state, check, st);
         for (auto it = c.classes.rbegin(); it != c.classes.rend(); ++it)  // ascending sizes
             if (it->live)
                 launch_ascend<T>((const CycleSlot<T> *)it->d_run, it->nrun, it->n, cnn, w, c.d_state, st,
@@ -220,7 +222,7 @@ void enqueue_vcycle(mg_ctx_s &c, hipStream_t st)
                                    c.opt.nu_post, c.d_state, st);
         else
             launch_bottom<T>((const BottomSlot<T> *)c.bottom.d_run, c.bottom.nrun, c.bottom_top_n, cnn, w,
-                             c.opt.nu_pre, c.opt.nu_post, c.d_state, st);
+                             c.opt.nu_pre, c.opt.nu_post, c.d_state, nullptr, st);
     }
     for (auto it = c.classes.rbegin(); it != c.classes.rend(); ++it) {  // ascending sizes
         const SizeClass &k = *it;
@@ -257,16 +259,22 @@ void enqueue_update(mg_ctx_s &c, hipStream_t st)
         if (k.live) launch_update_u<T>((const OuterSlot<T> *)k.d_run, k.nrun, k.n, c.d_state, st);
 }
 
-// One solver iteration: residual and stopping rule, V-cycle, update.
+// One solver iteration: residual and stopping rule, V-cycle, update.  The
+// fused V(1,1) cycle with the network or Jacobi smoother applies the rule in
+// its bottom kernel (one workgroup per problem, which has the time to sum the
+// residual's block sums while its own loads arrive): one launch fewer per
+// iteration.  The descent has then already run on a residual that meets the
+// tolerance; only the ascent and u depend on the rule, and they follow it.
+// (A completion counter shared by every block of the residual kernel, to apply
+// the rule there instead, serialises thousands of atomics and costs more than
+// a launch.)
 template <typename T>
 void enqueue_iteration(mg_ctx_s &c, hipStream_t st)
 {
-    // (A completion counter shared by every block of the residual kernel, to apply
-    // the rule without this extra launch, serialises thousands of atomics and costs
-    // more than the launch does.)
+    const bool folded = c.fused && c.opt.smoother != MG_SMOOTHER_STACK;
     enqueue_outer_residual<T>(c, st);
-    enqueue_check<T>(c, 0, st);
-    enqueue_vcycle<T>(c, st);
+    if (!folded) enqueue_check<T>(c, 0, st);
+    enqueue_vcycle<T>(c, st, folded ? c.d_params : nullptr);
     enqueue_update<T>(c, st);
 }
 
@@ -903,7 +911,7 @@ void launch_timed(mg_ctx_s &c, int k, const SizeClass &cls, const SizeClass &oc,
                                    c.opt.nu_post, c.d_state, st);
         else
             launch_bottom<T>((const BottomSlot<T> *)c.bottom.d_slots, c.nprob, c.bottom_top_n, cnn, w,
-                             c.opt.nu_pre, c.opt.nu_post, c.d_state, st);
+                             c.opt.nu_pre, c.opt.nu_post, c.d_state, nullptr, st);
         break;
     case 5:
         if (c.opt.smoother == MG_SMOOTHER_STACK)

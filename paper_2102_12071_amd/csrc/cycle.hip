@@ -109,40 +109,6 @@ __global__ void __launch_bounds__(kThreads) k_outer_residual(const OuterSlot<T> 
     if (tid == 0) s.partial[tile.y * gridDim.x + tile.x] = sum;
 }
 
-// The stopping rule of the solver (section 6.1) for one problem, given
-// rr = ||f - A u||^2; called by one thread.
-__device__ inline void stopping_rule(SolveState &st, double rr, const SolveParams *prm, int prob)
-{
-    const double rel = st.fnorm > 0.0 ? sqrt(rr) / st.fnorm : 0.0;
-    st.relres = rel;
-    if (prm->history) prm->history[(int64_t)prob * prm->hist_stride + st.iters] = rel;
-    if (rel < st.best * (1.0 - kStallGain)) {
-        st.best = rel;
-        st.stall = 0;
-    } else {
-        st.stall += 1;
-    }
-    const bool diverging = !isfinite(rel) || rel > kDivergeFactor * st.best;
-    if (rel <= prm->tol) {
-        st.active = 0;
-        st.status = 0;
-    } else if (prm->fallback && st.fallback == 0 && (diverging || st.stall >= kStallCycles) &&
-               st.iters < prm->maxit) {
-        // pause (no cycle is applied); the host switches the problem to damped Jacobi and resumes it
-        st.active = 0;
-        st.status = 2;
-        st.fallback = diverging ? 3 : 1;
-    } else if (!isfinite(rel) || rel > 1e3) {
-        st.active = 0;
-        st.status = -4;
-    } else if (st.iters >= prm->maxit) {
-        st.active = 0;
-        st.status = 1;
-    } else {
-        st.iters += 1;
-    }
-}
-
 // One block per slot.  init = 1: the partial sums are ||f||^2 (u = 0); set up
 // the problem's state.  init = 0: the stopping rule of the solver.
 template <typename T>

@@ -96,8 +96,9 @@ void launch_zero_e(const CycleSlot<T> *slots, int nslots, int n, const SolveStat
 template <typename T>
 size_t bottom_smem_bytes(int top_n);
 template <typename T>
+// prm: also apply the solver's stopping rule to the outer residual's block sums (null: the cycle only).
 void launch_bottom(const BottomSlot<T> *slots, int nslots, int top_n, bool cnn, double omega, int nu1, int nu2,
-                   const SolveState *state, hipStream_t st);
+                   SolveState *state, const SolveParams *prm, hipStream_t st);
 template <typename T>
 void prepare_bottom();
 

@@ -74,12 +74,27 @@ __global__ void __launch_bounds__(kBT) k_bottom(const BottomSlot<T> *slots, Solv
     if (!state[S.prob].active) return;
     const int NL = S.nlev;
     const int tid = threadIdx.x;
-    auto voff = [&](int l) {  // r of level l; e at + vec, s at + 2 vec
-        int off = 0;
-        for (int q = 0; q < l; ++q) off += 3 * lay_of(S.lev[q].n).vec;
-        return off;
-    };
-    const int total_vec = voff(NL);
+    // Level sizes and LDS offsets (r of level l at lvo[l]; e at + vec, s at + 2 vec), read from the slot
+    // once and kept in LDS for the steps: the slot lives in global memory, and since the kernel also
+    // writes global memory its loads go through the vector memory path, a round trip of a microsecond
+    // or so that every step behind a barrier would otherwise wait for again.
+    __shared__ int lvn[kMaxBottomLevels], lvo[kMaxBottomLevels + 1];
+    int total_vec = 0;
+    {
+        int nq[kMaxBottomLevels];
+#pragma unroll
+        for (int q = 0; q < kMaxBottomLevels; ++q) nq[q] = S.lev[q].n;  // entries past nlev: unused
+#pragma unroll
+        for (int q = 0; q < kMaxBottomLevels; ++q) {
+            if (tid == 0) {
+                lvn[q] = nq[q];
+                lvo[q] = total_vec;
+            }
+            total_vec += q < NL ? 3 * lay_of(nq[q]).vec : 0;
+        }
+        if (tid == 0) lvo[kMaxBottomLevels] = total_vec;
+    }
+    auto voff = [&](int l) { return lvo[l]; };  // after the first barrier
 
     // ---- roles
     const Lay L0 = lay_of(S.lev[0].n);
@@ -128,7 +143,9 @@ __global__ void __launch_bounds__(kBT) k_bottom(const BottomSlot<T> *slots, Solv
     const int64_t p0 = in0 ? (int64_t)pj * S.lev[0].P + pi : 0;
     const T2 rin = *(const T2 MG_G *)(S.r_in + p0);
     typedef typename Vec2<double>::type D2;
-    const D2 uin = S.u ? *(const D2 MG_G *)(S.u + p0) : D2{0.0, 0.0};  // uniform branch
+    double MG_G *const uout = S.u;  // the outputs' addresses, read with the other slot fields
+    T MG_G *const eout = S.e_out;
+    const D2 uin = uout ? *(const D2 MG_G *)(uout + p0) : D2{0.0, 0.0};  // uniform branch
     const int mc = S.lev[NL - 1].n, mm = mc * mc;
     constexpr int IA = (kAinvMax + kBT - 1) / kBT;
     double av[IA];
@@ -223,7 +240,7 @@ __global__ void __launch_bounds__(kBT) k_bottom(const BottomSlot<T> *slots, Solv
     // ---- the per-level steps (x: source vector offset, y: destination)
     // residual: s = r - A e
     auto residual = [&](int l) {
-        const Lay L = lay_of(S.lev[l].n);
+        const Lay L = lay_of(lvn[l]);
         const int R = voff(l), E = R + L.vec, Sx = R + 2 * L.vec;
         if (l == 0 && pair_role) {
             if (pj >= L.n) return;
@@ -255,7 +272,7 @@ __global__ void __launch_bounds__(kBT) k_bottom(const BottomSlot<T> *slots, Solv
     };
     // smoothing: e = M^{-1} x (first) or e += M^{-1} x
     auto smooth = [&](int l, bool from_r, bool first) {
-        const Lay L = lay_of(S.lev[l].n);
+        const Lay L = lay_of(lvn[l]);
         const int R = voff(l), E = R + L.vec, X = from_r ? R : R + 2 * L.vec;
         if (l == 0 && pair_role) {
             if (pj >= L.n) return;
@@ -328,7 +345,7 @@ __global__ void __launch_bounds__(kBT) k_bottom(const BottomSlot<T> *slots, Solv
         }  // nu1 = 0: e keeps the zeros of the clearing at the start
         residual(l);
         __syncthreads();
-        const Lay L = lay_of(S.lev[l].n), Lc = lay_of(S.lev[l + 1].n);
+        const Lay L = lay_of(lvn[l]), Lc = lay_of(lvn[l + 1]);
         const int Sx = voff(l) + 2 * L.vec, Rc = voff(l + 1);
         for (int q = tid; q < Lc.n * Lc.n; q += kBT) {
             const int I = q % Lc.n, J = q / Lc.n;
@@ -354,7 +371,7 @@ __global__ void __launch_bounds__(kBT) k_bottom(const BottomSlot<T> *slots, Solv
     __syncthreads();
     // ----------------------------------------------------------- ascend
     for (int l = NL - 2; l >= 0; --l) {
-        const Lay L = lay_of(S.lev[l].n), Lc = lay_of(S.lev[l + 1].n);
+        const Lay L = lay_of(lvn[l]), Lc = lay_of(lvn[l + 1]);
         const int E = voff(l) + L.vec, Ec = voff(l + 1) + Lc.vec;
         for (int q = tid; q < L.n * L.n; q += kBT) {
             const int i = q % L.n, j = q / L.n;
@@ -379,15 +396,15 @@ __global__ void __launch_bounds__(kBT) k_bottom(const BottomSlot<T> *slots, Solv
     if (check && !go) return;  // stopped by the rule: u keeps its value (read after the barriers above)
     if (in0) {
         const T2 e = *(const T2 *)(sm + L0.vec + at(L0, pi, pj));
-        if (S.u) {
+        if (uout) {
             D2 u2;
             u2.x = uin.x + (double)e.x;
             u2.y = pi + 1 < L0.n ? uin.y + (double)e.y : uin.y;
-            *(D2 MG_G *)(S.u + p0) = u2;
+            *(D2 MG_G *)(uout + p0) = u2;
         } else {
             T2 v = e;
             v.y = pi + 1 < L0.n ? v.y : (T)0;
-            *(T2 MG_G *)(S.e_out + p0) = v;
+            *(T2 MG_G *)(eout + p0) = v;
         }
     }
 }

@@ -109,6 +109,76 @@ __global__ void __launch_bounds__(kThreads) k_outer_residual(const OuterSlot<T> 
     if (tid == 0) s.partial[tile.y * gridDim.x + tile.x] = sum;
 }
 
+// Row tiles of node pairs for the outer residual on large grids: 64 threads cover 128 columns.
+constexpr int kPairResidualMin = 2047;  // below, one node per thread was faster (cache-resident grids)
+inline RowTile pair_tile(int) { return {64, kThreads / 64}; }
+inline dim3 pair_grid(int n, RowTile t, int nslots)
+{
+    return dim3(((n + 1) / 2 + t.bx - 1) / t.bx, (n + t.by - 1) / t.by, nslots);
+}
+
+// k_outer_residual on pairs of horizontally adjacent nodes (i, i+1), i even,
+// one pair per thread, for n >= kPairResidualMin: stencil planes, u and f
+// load as 16-byte words (a pair's right node may be the zero padding column).
+// Each node's nine terms are summed in stencil order, as apply3x3 does.  For
+// a symmetric stencil (OuterSlot::sym) only planes 4..8 are read: the entries
+// to the row below and the left neighbour come from those neighbours'
+// mirrored planes (stencil_index), pairs that start one column off.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_outer_residual_pairs(const OuterSlot<T> *slots, const SolveState *state)
+{
+    typedef double D2 __attribute__((ext_vector_type(2)));
+    typedef double D2u __attribute__((ext_vector_type(2), aligned(8)));
+    typedef T T2 __attribute__((ext_vector_type(2)));
+    __shared__ double red[kThreads / 64];
+    const TileId tile = xcd_tile();
+    const OuterSlot<T> s = slots[tile.z];
+    if (!state[s.prob].active) return;
+    const int n = s.n, P = s.P;
+    const int i = 2 * (tile.x * blockDim.x + threadIdx.x);
+    const int j = tile.y * blockDim.y + threadIdx.y;
+    const bool on = i < n && j < n;  // the pair's left node is on the grid
+    const int64_t p = on ? (int64_t)j * P + i : 0;
+    const bool sym = *s.sym != 0;
+    // every load first, unconditionally (clamped addresses, values selected afterwards)
+    D2 a[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) a[c] = *(const D2u MG_G *)(s.A64 + stencil_index(c, sym, s.plane, P, p));
+    D2 uv[3][3];  // u pairs at columns i-2, i, i+2 of rows j-1 .. j+1 (zero off the grid)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int row = j + dy - 1, col = i + 2 * k - 2;
+            const bool ok = on && row >= 0 && row < n && col >= 0 && col < n;
+            const D2 v = *(const D2 MG_G *)(s.u + (ok ? (int64_t)row * P + col : p));
+            uv[dy][k] = ok ? v : D2{0.0, 0.0};
+        }
+    }
+    const D2 fv = *(const D2 MG_G *)(s.f + p);
+    double r0 = 0.0, r1 = 0.0;
+    if (on) {
+        double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+            const int dy = c / 3, dx = c % 3;  // neighbour (i + dx - 1, j + dy - 1)
+            const double x0 = dx == 0 ? uv[dy][0].y : dx == 1 ? uv[dy][1].x : uv[dy][1].y;
+            const double x1 = dx == 0 ? uv[dy][1].x : dx == 1 ? uv[dy][1].y : uv[dy][2].x;
+            acc0 += a[c].x * x0;
+            acc1 += a[c].y * x1;
+        }
+        r0 = fv.x - acc0;
+        r1 = i + 1 < n ? fv.y - acc1 : 0.0;
+        T2 rv;
+        rv.x = (T)r0;
+        rv.y = (T)r1;
+        *(T2 MG_G *)(s.r + p) = rv;
+    }
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const double sum = block_sum<kThreads>(r0 * r0 + r1 * r1, red);
+    if (tid == 0) s.partial[tile.y * gridDim.x + tile.x] = sum;
+}
+
 // One block per slot.  init = 1: the partial sums are ||f||^2 (u = 0); set up
 // the problem's state.  init = 0: the stopping rule of the solver.
 template <typename T>
@@ -320,16 +390,21 @@ void launch_zero_f64(double *x, int64_t count, hipStream_t st)
 
 int outer_residual_parts(int n)
 {
-    const RowTile t = row_tile(n);
-    const dim3 g = row_grid(n, t, 1);
+    const RowTile t = n >= kPairResidualMin ? pair_tile(n) : row_tile(n);
+    const dim3 g = n >= kPairResidualMin ? pair_grid(n, t, 1) : row_grid(n, t, 1);
     return (int)(g.x * g.y);
 }
 
 template <typename T>
 void launch_outer_residual(const OuterSlot<T> *slots, int nslots, int n, const SolveState *state, hipStream_t st)
 {
-    const RowTile t = row_tile(n);
-    k_outer_residual<T><<<row_grid(n, t, nslots), dim3(t.bx, t.by), 0, st>>>(slots, state);
+    if (n >= kPairResidualMin) {
+        const RowTile t = pair_tile(n);
+        k_outer_residual_pairs<T><<<pair_grid(n, t, nslots), dim3(t.bx, t.by), 0, st>>>(slots, state);
+    } else {
+        const RowTile t = row_tile(n);
+        k_outer_residual<T><<<row_grid(n, t, nslots), dim3(t.bx, t.by), 0, st>>>(slots, state);
+    }
 }
 
 template <typename T>

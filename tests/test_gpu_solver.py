@@ -162,6 +162,25 @@ def test_solve_nonsymmetric_stencil_matches_oracle_iterates(mg):
     assert _rel(res.u[0].cpu().numpy(), u_ref) <= 1e-11
 
 
+@pytest.mark.parametrize("skew", [False, True])
+def test_outer_residual_pairs_match_oracle_history(mg, skew):
+    # from n = 2047 the outer residual runs on node pairs (16-byte loads, mirrored stencil pairs that
+    # start one column off): the residual history of a few FP64 cycles must match the oracle's, with
+    # the five-plane reads of a symmetric stencil and the nine-plane path of a skewed one
+    n = 2047
+    A = ora.stencil_q1_rotated(n, 0.7, 0.05).copy()
+    if skew:
+        d = 1e-6 * np.abs(A).max()
+        A[5, :, :-1] += d
+        A[3, :, 1:] -= d
+    f = mg_inputs.rhs_uniform(n, 8)
+    ctx = mg.Context([_dev(A)], mg.Options(precision=mg.PREC_FP64))
+    res = ctx.solve([_dev(f)], 1e-14, 3, history=True)
+    _, k, hist, _ = ora.Hierarchy(A).solve(f, 1e-14, 3, 1, 1)
+    assert int(res.iters[0]) == k == 3
+    assert np.allclose(res.history[0, :k + 1], hist, rtol=1e-9, atol=0)
+
+
 # ------------------------------------------------------------ mixed precision
 def test_solve_c1_mixed_jacobi(mg):
     p = mg_inputs.config_c1()

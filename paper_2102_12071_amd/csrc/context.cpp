@@ -164,7 +164,8 @@ mg_status build_slots(mg_ctx_s &c)
 // V(1,1) runs the fused level kernels (descend, bottom, ascend), which add
 // the finest correction to u themselves; other sweep counts run the
 // step-by-step kernels and leave u += e to enqueue_update.  check: the fused
-// bottom kernel also applies the stopping rule (see enqueue_iteration).
+// bottom kernel (network, Jacobi or stack smoother) also applies the stopping
+// rule (see enqueue_iteration).
 template <typename T>
 void enqueue_vcycle(mg_ctx_s &c, hipStream_t st, const SolveParams *check = nullptr)
 {
@@ -184,7 +185,7 @@ void enqueue_vcycle(mg_ctx_s &c, hipStream_t st, const SolveParams *check = null
             if (k.live) launch_stack_descend<T>((const CycleSlot<T> *)k.d_run, k.nrun, (k.n - 1) / 2, c.d_state, st);
         if (c.bottom.live)
             launch_stack_bottom<T>((const BottomSlot<T> *)c.bottom.d_run, c.bottom.nrun, c.bottom_top_n, 1, 1,
-                                   c.d_state, st);
+                                   c.d_state, check, st);
         for (auto it = c.classes.rbegin(); it != c.classes.rend(); ++it)  // ascending sizes
             if (it->live) launch_stack_ascend<T>((const CycleSlot<T> *)it->d_run, it->nrun, it->n, c.d_state, st);
         return;
@@ -219,7 +220,7 @@ void enqueue_vcycle(mg_ctx_s &c, hipStream_t st, const SolveParams *check = null
     if (c.bottom.live) {
         if (stack)
             launch_stack_bottom<T>((const BottomSlot<T> *)c.bottom.d_run, c.bottom.nrun, c.bottom_top_n, c.opt.nu_pre,
-                                   c.opt.nu_post, c.d_state, st);
+                                   c.opt.nu_post, c.d_state, nullptr, st);
         else
             launch_bottom<T>((const BottomSlot<T> *)c.bottom.d_run, c.bottom.nrun, c.bottom_top_n, cnn, w,
                              c.opt.nu_pre, c.opt.nu_post, c.d_state, nullptr, st);
@@ -260,10 +261,9 @@ void enqueue_update(mg_ctx_s &c, hipStream_t st)
 }
 
 // One solver iteration: residual and stopping rule, V-cycle, update.  The
-// fused V(1,1) cycle with the network or Jacobi smoother applies the rule in
-// its bottom kernel (one workgroup per problem, which has the time to sum the
-// residual's block sums while its own loads arrive): one launch fewer per
-// iteration.  The descent has then already run on a residual that meets the
+// fused V(1,1) cycle applies the rule in its bottom kernel (one workgroup per
+// problem, which has the time to sum the residual's block sums while its own
+// loads arrive): one launch fewer per iteration.  The descent has then already run on a residual that meets the
 // tolerance; only the ascent and u depend on the rule, and they follow it.
 // (A completion counter shared by every block of the residual kernel, to apply
 // the rule there instead, serialises thousands of atomics and costs more than
@@ -271,7 +271,7 @@ void enqueue_update(mg_ctx_s &c, hipStream_t st)
 template <typename T>
 void enqueue_iteration(mg_ctx_s &c, hipStream_t st)
 {
-    const bool folded = c.fused && c.opt.smoother != MG_SMOOTHER_STACK;
+    const bool folded = c.fused;
     enqueue_outer_residual<T>(c, st);
     if (!folded) enqueue_check<T>(c, 0, st);
     enqueue_vcycle<T>(c, st, folded ? c.d_params : nullptr);
@@ -908,7 +908,7 @@ void launch_timed(mg_ctx_s &c, int k, const SizeClass &cls, const SizeClass &oc,
     case 4:
         if (c.opt.smoother == MG_SMOOTHER_STACK)
             launch_stack_bottom<T>((const BottomSlot<T> *)c.bottom.d_slots, c.nprob, c.bottom_top_n, c.opt.nu_pre,
-                                   c.opt.nu_post, c.d_state, st);
+                                   c.opt.nu_post, c.d_state, nullptr, st);
         else
             launch_bottom<T>((const BottomSlot<T> *)c.bottom.d_slots, c.nprob, c.bottom_top_n, cnn, w,
                              c.opt.nu_pre, c.opt.nu_post, c.d_state, nullptr, st);

@@ -482,7 +482,11 @@ __global__ void k_stack_adam(double *w, double *m, double *v, const double *g, i
 // elements with a zero border of one node, which is the zero padding of every
 // layer; one thread per node (n^2 <= 961 < 1024 threads).  The V-cycle of
 // these levels (Algorithm 1) runs with a workgroup barrier between steps
-// instead of a launch per step; the coarsest inverse is read into LDS.
+// instead of a launch per step; the coarsest inverse is read into LDS.  With
+// prm given it also applies the solver's stopping rule to the outer residual's
+// block sums, as the network smoother's bottom kernel does (k_bottom): summed
+// with the first loads, applied by a thread with no top-level node, and u
+// changes only if the problem goes on.
 constexpr int kSBT = 1024;
 constexpr int kSBVec = 5;
 constexpr size_t kSBAinvBytes = ((size_t)kMaxCoarseUnknowns * kMaxCoarseUnknowns * sizeof(double) + 15) / 16 * 16;
@@ -491,9 +495,11 @@ __host__ __device__ inline int sb_vec(int n) { return (n + 2) * (n + 2); }
 __device__ inline int sb_at(int n, int i, int j) { return (j + 1) * (n + 2) + i + 1; }
 
 template <typename T>
-__global__ void __launch_bounds__(kSBT) k_stack_bottom(const BottomSlot<T> *slots, const SolveState *state, int nu1,
-                                                       int nu2)
+__global__ void __launch_bounds__(kSBT) k_stack_bottom(const BottomSlot<T> *slots, SolveState *state, int nu1, int nu2,
+                                                       const SolveParams *prm)
 {
+    __shared__ double wsum[kSBT / 64];
+    __shared__ int go;
     extern __shared__ __align__(16) unsigned char sb_raw[];
     double *ainv = (double *)sb_raw;
     T *sm = (T *)(sb_raw + kSBAinvBytes);
@@ -507,9 +513,33 @@ __global__ void __launch_bounds__(kSBT) k_stack_bottom(const BottomSlot<T> *slot
         if (l < NL) total += kSBVec * sb_vec(S.lev[l].n);
     }
     const int mc = S.lev[NL - 1].n, mm = mc * mc;
+    const bool check = prm != nullptr;  // uniform
+    double rr0 = 0.0, rr1 = 0.0, rr2 = 0.0, rr3 = 0.0;
+    if (check) {
+        const int np = state[S.prob].nparts;
+        int q = tid;
+        for (; q + 3 * kSBT < np; q += 4 * kSBT) {
+            rr0 += S.partial[q];
+            rr1 += S.partial[q + kSBT];
+            rr2 += S.partial[q + 2 * kSBT];
+            rr3 += S.partial[q + 3 * kSBT];
+        }
+        for (; q < np; q += kSBT) rr0 += S.partial[q];
+    }
     for (int q = tid; q < total; q += kSBT) sm[q] = (T)0;
     for (int q = tid; q < mm * mm; q += kSBT) ainv[q] = S.Ainv[q];
+    if (check) {
+        const double w = wave_sum((rr0 + rr1) + (rr2 + rr3));
+        if ((tid & 63) == 0) wsum[tid >> 6] = w;
+    }
     __syncthreads();
+    if (check && tid == kSBT - 1) {  // no top-level node (n^2 <= 961)
+        double rr = 0.0;
+        for (int w = 0; w < kSBT / 64; ++w) rr += wsum[w];
+        SolveState &st = state[S.prob];
+        stopping_rule(st, rr, prm, S.prob);
+        go = st.active;
+    }
     {
         const int n = S.lev[0].n, P = S.lev[0].P;
         for (int q = tid; q < n * n; q += kSBT) sm[off[0] + sb_at(n, q % n, q / n)] = S.r_in[(int64_t)(q / n) * P + q % n];
@@ -619,6 +649,7 @@ __global__ void __launch_bounds__(kSBT) k_stack_bottom(const BottomSlot<T> *slot
             stack(l, off[l] + 2 * V, off[l] + V, true, true);
         }
     }
+    if (check && !go) return;  // stopped by the rule: u keeps its value (read after the barriers above)
     {
         const int n = S.lev[0].n, P = S.lev[0].P, E = off[0] + sb_vec(n);
         for (int q = tid; q < n * n; q += kSBT) {
@@ -694,16 +725,17 @@ void prepare_stack_bottom()
 }
 
 template <typename T>
-void launch_stack_bottom(const BottomSlot<T> *slots, int nslots, int top_n, int nu1, int nu2, const SolveState *state,
-                         hipStream_t st)
+void launch_stack_bottom(const BottomSlot<T> *slots, int nslots, int top_n, int nu1, int nu2, SolveState *state,
+                         const SolveParams *prm, hipStream_t st)
 {
-    k_stack_bottom<T><<<nslots, kSBT, stack_bottom_smem_bytes<T>(top_n), st>>>(slots, state, nu1, nu2);
+    k_stack_bottom<T><<<nslots, kSBT, stack_bottom_smem_bytes<T>(top_n), st>>>(slots, state, nu1, nu2, prm);
 }
 template void prepare_stack_bottom<float>();
 template void prepare_stack_bottom<double>();
-template void launch_stack_bottom<float>(const BottomSlot<float> *, int, int, int, int, const SolveState *, hipStream_t);
-template void launch_stack_bottom<double>(const BottomSlot<double> *, int, int, int, int, const SolveState *,
-                                          hipStream_t);
+template void launch_stack_bottom<float>(const BottomSlot<float> *, int, int, int, int, SolveState *,
+                                         const SolveParams *, hipStream_t);
+template void launch_stack_bottom<double>(const BottomSlot<double> *, int, int, int, int, SolveState *,
+                                          const SolveParams *, hipStream_t);
 
 void launch_stack_vecs(const double *x, double *y, int64_t vs, const double *w, int n, int P, int count,
                        bool accumulate, const int *active, hipStream_t st)

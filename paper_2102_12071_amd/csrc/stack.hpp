@@ -31,8 +31,9 @@ void launch_stack_ascend(const CycleSlot<T> *slots, int nslots, int n, const Sol
 template <typename T>
 void prepare_stack_bottom();
 template <typename T>
-void launch_stack_bottom(const BottomSlot<T> *slots, int nslots, int top_n, int nu1, int nu2, const SolveState *state,
-                         hipStream_t st);
+// prm: also apply the solver's stopping rule to the outer residual's block sums (null: the cycle only).
+void launch_stack_bottom(const BottomSlot<T> *slots, int nslots, int top_n, int nu1, int nu2, SolveState *state,
+                         const SolveParams *prm, hipStream_t st);
 
 // y_z (+)= H x_z for z < count, vectors of pitch P at stride vs, one weight
 // set w (device, [54]); active (or null) skips vectors.  x and y must not overlap.

@@ -163,6 +163,15 @@ mg_status mg_smoother_infer(mg_ctx ctx, mg_net net);
  * no level above the coarsest has size n. */
 mg_status mg_smoother_infer_size(mg_ctx ctx, mg_net net, int32_t n);
 
+/* Per-level networks in one call (section 3.3's adaptive training yields one
+ * network per level): the smoothing levels of size sizes[k] take nets[k], for
+ * k < count (host arrays; count <= 16).  Every smoothing level size of the
+ * context must be listed, each once, and every listed size must occur
+ * (MG_ERR_ARG otherwise, before any work).  The same smoothers as one
+ * mg_smoother_infer_size call per size; in mixed precision one launch covers
+ * every level. */
+mg_status mg_smoother_infer_levels(mg_ctx ctx, const mg_net *nets, const int32_t *sizes, int32_t count);
+
 /* Installs an explicit smoother field W for one level (device [25][n_l][n_l]
  * FP64; stored as the context's precision).  Replaces what inference gave. */
 mg_status mg_set_smoother(mg_ctx ctx, int32_t prob, int32_t level, const double *W);

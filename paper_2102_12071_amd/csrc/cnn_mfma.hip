@@ -207,9 +207,11 @@ __device__ inline void cnn_tile(int n, int P, int64_t plane, const float MG_G *A
 // One launch for every level of every problem: block b takes tile
 // b - tile0 of the level whose [tile0, tile0 + tiles) holds b (levels in
 // launch order, largest first, so the small ones fill the tail).  With
-// size_filter != 0 only the levels of that size are computed.
+// size_filter != 0 only the levels of that size are computed.  With map.count
+// > 0 each level takes the network listed for its size (per-level networks in
+// one launch instead of one launch per size).
 __global__ void __launch_bounds__(kT) k_cnn_fused_levels(const CnnLevelDesc *desc, int ndesc, int size_filter,
-                                                         const PackedNet *pkg, float omega)
+                                                         const PackedNet *pkg, CnnNetMap map, float omega)
 {
     const int b = blockIdx.x;
     int lo = 0, hi = ndesc - 1;  // last level with tile0 <= b
@@ -219,6 +221,8 @@ __global__ void __launch_bounds__(kT) k_cnn_fused_levels(const CnnLevelDesc *des
     }
     const CnnLevelDesc L = desc[lo];
     if (size_filter != 0 && L.n != size_filter) return;
+    for (int k = 0; k < map.count; ++k)  // uniform
+        if (map.n[k] == L.n) pkg = (const PackedNet *)map.packed[k];
     const int t = b - L.tile0, tx = (L.n + kTO - 1) / kTO;
     cnn_tile(L.n, L.P, L.plane, L.A32, (const PackedNet MG_G *)pkg, omega, L.H, (t % tx) * kTO, (t / tx) * kTO);
 }
@@ -270,10 +274,11 @@ void launch_pack_weights_mfma(const float *params, void *packed, hipStream_t st)
 int cnn_level_tiles(int n) { return ((n + kTO - 1) / kTO) * ((n + kTO - 1) / kTO); }
 
 void launch_cnn_fused_levels(const CnnLevelDesc *desc, int ndesc, int total_tiles, int size_filter, const void *packed,
-                             double omega, hipStream_t st)
+                             const CnnNetMap &map, double omega, hipStream_t st)
 {
     if (ndesc < 1 || total_tiles < 1) return;
-    k_cnn_fused_levels<<<total_tiles, kT, 0, st>>>(desc, ndesc, size_filter, (const PackedNet *)packed, (float)omega);
+    k_cnn_fused_levels<<<total_tiles, kT, 0, st>>>(desc, ndesc, size_filter, (const PackedNet *)packed, map,
+                                                   (float)omega);
 }
 
 }  // namespace mg

@@ -1181,9 +1181,55 @@ mg_status ctx_infer(mg_ctx_s &c, mg_net net, int n, hipStream_t st, int *count)
             ++done;
         }
     }
-    if (!fp64) launch_cnn_fused_levels(c.d_cnn_levels, c.n_cnn_levels, c.cnn_tiles, n, net->packed, c.opt.omega, st);
+    if (!fp64)
+        launch_cnn_fused_levels(c.d_cnn_levels, c.n_cnn_levels, c.cnn_tiles, n, net->packed, CnnNetMap{},
+                                c.opt.omega, st);
     MG_HIP(hipGetLastError());
     if (count) *count = done;
+    return MG_OK;
+}
+
+// Inference with one network per level size (sizes[k] takes nets[k]); every smoothing level size of
+// the context must be listed, each once.  Mixed precision: one launch over every level.
+mg_status ctx_infer_levels(mg_ctx_s &c, const mg_net *nets, const int32_t *sizes, int count, hipStream_t st)
+{
+    if (count < 1 || count > kMaxNetSizes)
+        return set_error(MG_ERR_ARG, "count must be in [1, %d], got %d", kMaxNetSizes, count);
+    for (int k = 0; k < count; ++k) {
+        if (!nets[k]) return set_error(MG_ERR_ARG, "nets[%d] is null", k);
+        for (int q = 0; q < k; ++q)
+            if (sizes[q] == sizes[k]) return set_error(MG_ERR_ARG, "size %d is listed twice", sizes[k]);
+    }
+    auto net_of = [&](int n) -> int {
+        for (int k = 0; k < count; ++k)
+            if (sizes[k] == n) return k;
+        return -1;
+    };
+    for (int k = 0; k < count; ++k) {
+        bool found = false;
+        for (const ProbBuf &pb : c.probs)
+            for (int l = 0; l + 1 < pb.nlev; ++l) found = found || pb.lev[l].n == sizes[k];
+        if (!found) return set_error(MG_ERR_ARG, "no smoothing level of size %d in this context", sizes[k]);
+    }
+    for (const ProbBuf &pb : c.probs)
+        for (int l = 0; l + 1 < pb.nlev; ++l)
+            if (net_of(pb.lev[l].n) < 0) return set_error(MG_ERR_ARG, "level size %d has no network", pb.lev[l].n);
+    if (c.opt.precision == MG_PREC_FP64) {  // the direct FP64 path runs level by level anyway
+        for (int k = 0; k < count; ++k) MG_TRY(ctx_infer(c, nets[k], sizes[k], st, nullptr));
+        return MG_OK;
+    }
+    CnnNetMap map{};
+    map.count = count;
+    for (int k = 0; k < count; ++k) {
+        mg_net net = nets[k];
+        MG_HIP(hipEventRecord(net->join.ev, net->join.internal));
+        MG_HIP(hipStreamWaitEvent(st, net->join.ev, 0));
+        MG_TRY(net_pack_mfma(net, st));
+        map.n[k] = sizes[k];
+        map.packed[k] = net->packed;
+    }
+    launch_cnn_fused_levels(c.d_cnn_levels, c.n_cnn_levels, c.cnn_tiles, 0, nets[0]->packed, map, c.opt.omega, st);
+    MG_HIP(hipGetLastError());
     return MG_OK;
 }
 
@@ -1198,6 +1244,19 @@ extern "C" mg_status mg_smoother_infer(mg_ctx ctx, mg_net net)
     if (!net) return set_error(MG_ERR_ARG, "net is null");
     MG_TRY(ctx->join.enter());
     MG_TRY(ctx_infer(*ctx, net, 0, ctx->join.internal, nullptr));
+    ctx->smoother_ready = true;
+    return ctx->join.leave();
+}
+
+extern "C" mg_status mg_smoother_infer_levels(mg_ctx ctx, const mg_net *nets, const int32_t *sizes, int32_t count)
+{
+    clear_error();
+    MG_TRY(check_ctx(ctx));
+    if (ctx->opt.smoother == MG_SMOOTHER_STACK)
+        return set_error(MG_ERR_STATE, "the stack smoother is not produced by a network (mg_set_stack)");
+    if (!nets || !sizes) return set_error(MG_ERR_ARG, "nets and sizes must not be null");
+    MG_TRY(ctx->join.enter());
+    MG_TRY(ctx_infer_levels(*ctx, nets, sizes, count, ctx->join.internal));
     ctx->smoother_ready = true;
     return ctx->join.leave();
 }

@@ -128,10 +128,19 @@ struct CnnLevelDesc {
     int tile0;
 };
 
+// Packed networks by level size, for one inference launch over levels that take different networks.
+constexpr int kMaxNetSizes = 16;
+struct CnnNetMap {
+    int count;                       // 0: every level takes the launch's single network
+    int n[kMaxNetSizes];             // level size
+    const void *packed[kMaxNetSizes];  // its network (packed_net_bytes() each, device)
+};
+
 // One launch over the levels of desc (device, tile0 ascending; size_filter != 0: only levels of that size).
+// map.count > 0: a level of size map.n[k] takes map.packed[k] (every level's size must be listed).
 int cnn_level_tiles(int n);
 void launch_cnn_fused_levels(const CnnLevelDesc *desc, int ndesc, int total_tiles, int size_filter, const void *packed,
-                             double omega, hipStream_t st);
+                             const CnnNetMap &map, double omega, hipStream_t st);
 // Smoother field conversions for mg_set_smoother / mg_get_smoother.
 // H = W / a_C (a_C from the FP64 stencil), and back.
 template <typename T>

@@ -94,6 +94,7 @@ SIGNATURES = {
     "mg_get_stencil": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p]),
     "mg_smoother_infer": (C.c_int, [C.c_void_p, C.c_void_p]),
     "mg_smoother_infer_size": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32]),
+    "mg_smoother_infer_levels": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "mg_smoother_transpose": (C.c_int, [C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mg_alpha_step": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(AlphaBatch),
                                 C.POINTER(TrainOpts), _c_dp, _c_dp, _c_fp]),
@@ -389,9 +390,10 @@ class Context:
         else:
             _check(load_library().mg_smoother_infer_size(self._h, net._h, int(size)))
 
-    def infer_levels(self, nets: dict) -> None:
+    def infer_levels(self, nets: dict, one_call: bool = True) -> None:
         """Per-level networks keyed by level size (adaptive training gives one per level): every
-        smoothing level takes the network of its size, or of the nearest trained size."""
+        smoothing level takes the network of its size, or of the nearest trained size.  One
+        mg_smoother_infer_levels call (one_call), or one mg_smoother_infer_size call per size."""
         if not nets:
             raise ValueError("no networks")
         sizes = sorted(nets)
@@ -399,9 +401,16 @@ class Context:
         for p in range(self.nprob):
             for l in range(self.num_levels(p) - 1):
                 have.add(self.level_n(p, l))
-        for m in sorted(have):
-            key = min(sizes, key=lambda s: (abs(math.log2(s + 1) - math.log2(m + 1)), -s))
-            _check(load_library().mg_smoother_infer_size(self._h, nets[key]._h, int(m)))
+        pick = {m: nets[min(sizes, key=lambda s: (abs(math.log2(s + 1) - math.log2(m + 1)), -s))]
+                for m in sorted(have)}
+        if one_call:
+            ms = sorted(pick)
+            hs = (C.c_void_p * len(ms))(*[pick[m]._h for m in ms])
+            ns = (C.c_int32 * len(ms))(*ms)
+            _check(load_library().mg_smoother_infer_levels(self._h, hs, ns, len(ms)))
+        else:
+            for m, net in pick.items():
+                _check(load_library().mg_smoother_infer_size(self._h, net._h, int(m)))
 
     def _vecs(self, xs, name):
         if len(xs) != self.nprob:

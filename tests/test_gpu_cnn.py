@@ -148,3 +148,27 @@ def test_per_level_networks(mg):
         ctx.infer(nb, size=3)  # the coarsest level has no smoother
     ctx.infer_levels({7: na, 15: nb, 31: nc})
     check([pc, pc, pb, pa])  # 63 takes the largest trained size
+
+
+def test_per_level_networks_one_launch_matches_per_size_calls(mg):
+    # mg_smoother_infer_levels runs every level in one launch, each level taking the network of its
+    # size: the BF16 smoothers must equal those of one mg_smoother_infer_size call per size, bit for
+    # bit, on a batch whose problems share some level sizes and not others
+    A1, A2 = _problem("q1", 255), _problem("cell", 127)
+    nets = {m: _net(mg, mg_inputs.cnn_random(20 + k)) for k, m in enumerate((127, 63, 31, 15))}
+    nets[255] = _net(mg, mg_inputs.cnn_random(30))
+    opt = mg.Options(smoother=mg.SMOOTHER_CNN, precision=mg.PREC_MIXED, coarsest_n=7)
+    one, per = mg.Context([_dev(A1), _dev(A2)], opt), mg.Context([_dev(A1), _dev(A2)], opt)
+    one.infer_levels(nets, one_call=True)
+    per.infer_levels(nets, one_call=False)
+    for p in range(2):
+        for l in range(one.num_levels(p) - 1):
+            assert torch.equal(one.smoother(p, l), per.smoother(p, l)), (p, l)
+    lib = mg.load_library()
+    import ctypes as C
+    hs = (C.c_void_p * 2)(nets[255]._h, nets[127]._h)
+    assert lib.mg_smoother_infer_levels(one._h, hs, (C.c_int32 * 2)(255, 127), 2) != 0  # sizes 63.. missing
+    hs5 = (C.c_void_p * 6)(*[nets[m]._h for m in (255, 127, 63, 31, 15)], nets[15]._h)
+    assert lib.mg_smoother_infer_levels(one._h, hs5, (C.c_int32 * 6)(255, 127, 63, 31, 15, 15), 6) != 0  # twice
+    hs7 = (C.c_void_p * 6)(*[nets[m]._h for m in (255, 127, 63, 31, 15)], nets[15]._h)
+    assert lib.mg_smoother_infer_levels(one._h, hs7, (C.c_int32 * 6)(255, 127, 63, 31, 15, 9), 6) != 0  # no 9

@@ -76,8 +76,8 @@ __global__ void __launch_bounds__(kBT) k_bottom(const BottomSlot<T> *slots, Solv
     const int tid = threadIdx.x;
     // Level sizes and LDS offsets (r of level l at lvo[l]; e at + vec, s at + 2 vec), read from the slot
     // once and kept in LDS for the steps: the slot lives in global memory, and since the kernel also
-    // writes global memory its loads go through the vector memory path, a round trip of a microsecond
-    // or so that every step behind a barrier would otherwise wait for again.
+    // writes global memory the compiler reloads its fields through the vector memory path after each
+    // barrier (12.3 instead of 14.0 us per C2 cycle with the table in LDS).
     __shared__ int lvn[kMaxBottomLevels], lvo[kMaxBottomLevels + 1];
     int total_vec = 0;
     {
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(kBT) k_bottom(const BottomSlot<T> *slots, Solv
         if ((tid & 63) == 0) wsum[tid >> 6] = w;
     }
     __syncthreads();
-    if (check && tid == kBT - 1) {  // a thread with no node on any level (they number at most 512 + 340)
+    if (check && tid == kBT - 1) {  // no node on any level: 512 threads own the top level, at most 340 the rest
         double rr = 0.0;
         for (int w = 0; w < kBT / 64; ++w) rr += wsum[w];
         SolveState &st = state[S.prob];

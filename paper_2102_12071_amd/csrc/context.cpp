@@ -263,8 +263,9 @@ void enqueue_update(mg_ctx_s &c, hipStream_t st)
 // One solver iteration: residual and stopping rule, V-cycle, update.  The
 // fused V(1,1) cycle applies the rule in its bottom kernel (one workgroup per
 // problem, which has the time to sum the residual's block sums while its own
-// loads arrive): one launch fewer per iteration.  The descent has then already run on a residual that meets the
-// tolerance; only the ascent and u depend on the rule, and they follow it.
+// loads arrive): one launch fewer per iteration.  The descent has then
+// already run on a residual that may meet the tolerance; only the ascent and
+// u depend on the rule, and they follow it.
 // (A completion counter shared by every block of the residual kernel, to apply
 // the rule there instead, serialises thousands of atomics and costs more than
 // a launch.)

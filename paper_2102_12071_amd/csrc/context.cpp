@@ -318,20 +318,21 @@ void destroy_ctx(mg_ctx c)
     delete c;
 }
 
-// Finest stencil into the pitched layout (checked), the Galerkin levels in
-// FP64, their FP32 copies, each level's symmetry flag, and the coarsest inverse.
+// Finest stencil into the pitched layout (checked; its FP32 copy and symmetry
+// flags in the same pass), the Galerkin levels in FP64, their FP32 copies and
+// symmetry flags, and the coarsest inverse.
 void rebuild_problem(mg_ctx_s &c, int p, const double *stencil, hipStream_t st)
 {
     ProbBuf &pb = c.probs[p];
     const LevelBuf &L0 = pb.lev[0];
-    launch_copy_field(pb.n, 9, stencil, pb.n, (int64_t)pb.n * pb.n, L0.A64, L0.P, L0.plane, st);
-    launch_validate(pb.n, L0.P, L0.plane, L0.A64, c.d_flag, st);
-    launch_check_symmetric(pb.n, L0.P, L0.plane, L0.A64, pb.sym, st);
+    const bool mixed = c.opt.precision == MG_PREC_MIXED;
+    // level 0 in one pass over the caller's stencil: copies, checks, both symmetry flags
+    launch_ingest(pb.n, stencil, L0.P, L0.plane, L0.A64, mixed ? L0.A32 : nullptr, c.d_flag, pb.sym, L0.sym, st);
     for (int q = 0; q + 1 < pb.nlev; ++q) {
         const LevelBuf &F = pb.lev[q], &Cc = pb.lev[q + 1];
         launch_galerkin(F.n, F.P, F.plane, F.A64, Cc.P, Cc.plane, Cc.A64, st);
     }
-    for (int q = 0; q < pb.nlev; ++q) {
+    for (int q = 1; q < pb.nlev; ++q) {
         const LevelBuf &L = pb.lev[q];
         if (c.opt.precision == MG_PREC_MIXED) {
             launch_to_f32(9 * L.plane, L.A64, L.A32, st);

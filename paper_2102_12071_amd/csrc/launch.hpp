@@ -18,6 +18,11 @@ void launch_copy_field(int n, int nch, const double *src, int Ps, int64_t planes
                        int64_t planed, hipStream_t st);
 void launch_to_f32(int64_t count, const double *src, float *dst, hipStream_t st);
 void launch_validate(int n, int P, int64_t plane, const double *A, int *flag, hipStream_t st);
+// Level 0 from the caller's dense [9][n][n] stencil in one pass: pitched FP64 copy, FP32 copy (A32 not
+// null), the checks of launch_validate into *flag, and the symmetry flags of launch_check_symmetric for
+// the FP64 entries (*sym64) and for the entries the cycle reads (*symc: FP32 when A32 is given).
+void launch_ingest(int n, const double *src, int P, int64_t plane, double *A64, float *A32, int *flag, int *sym64,
+                   int *symc, hipStream_t st);
 // *sym = 1 if A[c](p) == A[8-c](p + d_c) for c < 4 wherever both nodes are on the grid, else 0.
 template <typename T>
 void launch_check_symmetric(int n, int P, int64_t plane, const T *A, int *sym, hipStream_t st);

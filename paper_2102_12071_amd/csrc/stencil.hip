@@ -166,6 +166,50 @@ __global__ void k_validate(int n, int P, int64_t plane, const double *A, int *fl
     if (bad) atomicOr(flag, bad);
 }
 
+// Level 0 of a problem from the caller's dense [9][n][n] stencil in one pass
+// over it: the pitched FP64 copy, its FP32 copy (A32 not null), the checks of
+// k_validate, and the symmetry flags, A[c](p) == A[8-c](p + d_c) wherever both
+// nodes are on the grid, of the FP64 entries (sym64) and of the ones the cycle
+// reads (symc: their FP32 roundings when A32 is given, else the FP64 ones).
+// Both flags start at 1 (k_flags_init); a node that fails writes 0.
+__global__ void k_flags_init(int *a, int *b)
+{
+    *a = 1;
+    *b = 1;
+}
+__global__ void k_ingest(int n, const double *src, int P, int64_t plane, double *A64, float *A32, int *flag,
+                         int *sym64, int *symc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y * blockDim.y + threadIdx.y;
+    if (i >= n || j >= n) return;
+    const int64_t nn = (int64_t)n * n, q = (int64_t)j * n + i, p = (int64_t)j * P + i;
+    double v[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) v[c] = src[c * nn + q];
+    int bad = 0;
+#pragma unroll
+    for (int c = 0; c < 9; ++c) {
+        if (!isfinite(v[c])) bad |= 4;
+        if (!inside(n, i + c % 3 - 1, j + c / 3 - 1) && v[c] != 0.0) bad |= 1;
+        A64[c * plane + p] = v[c];
+        if (A32) A32[c * plane + p] = (float)v[c];
+    }
+    if (!(v[kCentre] > 0.0)) bad |= 2;
+    if (bad) atomicOr(flag, bad);
+    bool s64 = true, s32 = true;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int ii = i + c % 3 - 1, jj = j + c / 3 - 1;
+        if (!inside(n, ii, jj)) continue;
+        const double m = src[(8 - c) * nn + (int64_t)jj * n + ii];
+        s64 = s64 && v[c] == m;
+        s32 = s32 && (float)v[c] == (float)m;
+    }
+    if (!s64) *sym64 = 0;  // every writer writes 0
+    if (!(A32 ? s32 : s64)) *symc = 0;
+}
+
 // Dirichlet condition on the nodes outside a domain (mask 0): their rows keep
 // only the centre entry, and the rows of the nodes inside drop the couplings to
 // them.  Dense [9][n][n] in and out (may alias: each thread reads and writes
@@ -247,6 +291,14 @@ void launch_mask(int n, const uint8_t *mask, const double *A, double *out, hipSt
 {
     dim3 blk(64, 4);
     k_mask<<<node_grid(n, blk), blk, 0, st>>>(n, mask, A, out);
+}
+
+void launch_ingest(int n, const double *src, int P, int64_t plane, double *A64, float *A32, int *flag, int *sym64,
+                   int *symc, hipStream_t st)
+{
+    k_flags_init<<<1, 1, 0, st>>>(sym64, symc);
+    dim3 blk(64, 4);
+    k_ingest<<<node_grid(n, blk), blk, 0, st>>>(n, src, P, plane, A64, A32, flag, sym64, symc);
 }
 
 void launch_validate(int n, int P, int64_t plane, const double *A, int *flag, hipStream_t st)

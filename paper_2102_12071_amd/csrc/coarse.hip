@@ -12,19 +12,27 @@ namespace {
 
 constexpr int kN = kMaxCoarseUnknowns;
 
-__global__ void __launch_bounds__(64) k_coarse_factor(int m, int P, int64_t plane, const double *A, double *Ainv,
-                                                      int *flag)
+// One workgroup of kCT threads; every step's work is spread over all of them (right-looking forms):
+// the factor subtracts the same products in the same order as the dot-product form L[i][k] = (A[i][k]
+// - sum_{q<k} L[i][q] L[k][q]) / L[k][k], and the forward substitution likewise; the backward one
+// subtracts the later rows' terms from the last row down.
+constexpr int kCT = 256;
+__global__ void __launch_bounds__(kCT) k_coarse_factor(int m, int P, int64_t plane, const double *A, double *Ainv,
+                                                       int *flag)
 {
-    __shared__ double L[kN][kN + 1];
+    __shared__ double L[kN][kN + 1];  // the matrix, overwritten by its Cholesky factor (lower triangle)
     __shared__ double X[kN][kN + 1];
     __shared__ int bad;
     const int mm = m * m;
     const int t = threadIdx.x;
     if (t == 0) bad = 0;
-    for (int q = t; q < mm * mm; q += 64) L[q / mm][q % mm] = 0.0;
+    for (int q = t; q < mm * mm; q += kCT) {
+        L[q / mm][q % mm] = 0.0;
+        X[q / mm][q % mm] = q / mm == q % mm ? 1.0 : 0.0;
+    }
     __syncthreads();
     // dense matrix: row p = j*m + i, column of the neighbour (i+dx, j+dy)
-    for (int p = t; p < mm; p += 64) {
+    for (int p = t; p < mm; p += kCT) {
         const int i = p % m, j = p / m;
         for (int c = 0; c < 9; ++c) {
             const int ii = i + c % 3 - 1, jj = j + c / 3 - 1;
@@ -33,11 +41,10 @@ __global__ void __launch_bounds__(64) k_coarse_factor(int m, int P, int64_t plan
         }
     }
     __syncthreads();
-    // Cholesky, column by column: L[k][k] then the entries below it
+    // Cholesky: column k is final once the updates of columns 0 .. k-1 are in
     for (int k = 0; k < mm; ++k) {
         if (t == 0) {
             double d = L[k][k];
-            for (int q = 0; q < k; ++q) d -= L[k][q] * L[k][q];
             if (!(d > 0.0)) {
                 bad = 1;
                 d = 1.0;
@@ -45,28 +52,36 @@ __global__ void __launch_bounds__(64) k_coarse_factor(int m, int P, int64_t plan
             L[k][k] = sqrt(d);
         }
         __syncthreads();
-        for (int i = k + 1 + t; i < mm; i += 64) {
-            double s = L[i][k];
-            for (int q = 0; q < k; ++q) s -= L[i][q] * L[k][q];
-            L[i][k] = s / L[k][k];
+        for (int i = k + 1 + t; i < mm; i += kCT) L[i][k] /= L[k][k];
+        __syncthreads();
+        const int r = mm - k - 1;  // trailing block, lower triangle: L[i][j] -= L[i][k] L[j][k], k < j <= i
+        for (int q = t; q < r * r; q += kCT) {
+            const int i = k + 1 + q / r, j = k + 1 + q % r;
+            if (j <= i) L[i][j] -= L[i][k] * L[j][k];
         }
         __syncthreads();
     }
-    // inverse: thread c solves L L^T x = e_c
-    for (int c = t; c < mm; c += 64) {
-        for (int i = 0; i < mm; ++i) {
-            double s = (i == c) ? 1.0 : 0.0;
-            for (int q = 0; q < i; ++q) s -= L[i][q] * X[q][c];
-            X[i][c] = s / L[i][i];
+    // inverse, all columns at once: L Y = I (rows in increasing order), then L^T X = Y (decreasing)
+    for (int q = 0; q < mm; ++q) {
+        for (int c = t; c < mm; c += kCT) X[q][c] /= L[q][q];
+        __syncthreads();
+        const int r = mm - q - 1;
+        for (int e = t; e < r * mm; e += kCT) {
+            const int i = q + 1 + e / mm, c = e % mm;
+            X[i][c] -= L[i][q] * X[q][c];
         }
-        for (int i = mm - 1; i >= 0; --i) {
-            double s = X[i][c];
-            for (int q = i + 1; q < mm; ++q) s -= L[q][i] * X[q][c];
-            X[i][c] = s / L[i][i];
-        }
+        __syncthreads();
     }
-    __syncthreads();
-    for (int q = t; q < mm * mm; q += 64) Ainv[q] = X[q / mm][q % mm];
+    for (int q = mm - 1; q >= 0; --q) {
+        for (int c = t; c < mm; c += kCT) X[q][c] /= L[q][q];
+        __syncthreads();
+        for (int e = t; e < q * mm; e += kCT) {
+            const int i = e / mm, c = e % mm;
+            X[i][c] -= L[q][i] * X[q][c];
+        }
+        __syncthreads();
+    }
+    for (int q = t; q < mm * mm; q += kCT) Ainv[q] = X[q / mm][q % mm];
     if (t == 0 && bad) atomicOr(flag, 8);
 }
 
@@ -74,7 +89,7 @@ __global__ void __launch_bounds__(64) k_coarse_factor(int m, int P, int64_t plan
 
 void launch_coarse_factor(int m, int P, int64_t plane, const double *A, double *Ainv, int *flag, hipStream_t st)
 {
-    k_coarse_factor<<<1, 64, 0, st>>>(m, P, plane, A, Ainv, flag);
+    k_coarse_factor<<<1, kCT, 0, st>>>(m, P, plane, A, Ainv, flag);
 }
 
 }  // namespace mg

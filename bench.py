@@ -15,6 +15,7 @@ Prints one JSON line (see the repository's measurement notes).
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import math
 import os
@@ -173,6 +174,10 @@ def main():
 
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
+    # Python's cyclic collector stays off: once the earlier blocks have left many objects behind, a
+    # collection triggered inside a timed loop paused the interpreter for ~45 ms (seen in the drawn
+    # training step: one step of ten took 45 ms, the rest 0.85).  Each block collects before it times.
+    gc.disable()
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -250,6 +255,7 @@ def main():
             r = step(ctx, cnn)
             log(f"{name} warmup {w}: {int(r[0].iters[0])} iterations, relres {r[0].relres[0]:.2e}, "
                 f"solve {r[3]:.1f} ms")
+        gc.collect()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = []
@@ -366,6 +372,7 @@ def main():
 def inference_block(ctx, infer, n, coarsest, reps=10):
     """Smoother inference (the network on every level but the coarsest, BF16
     MFMA) timed on its own: useful FLOP per second against the dense BF16 peak."""
+    gc.collect()
     import torch
     nodes, m = 0, n
     while m > coarsest:
@@ -390,6 +397,7 @@ def sweeps_block(args, A, f, n, cnn_s, coarsest):
     V(1,1): a smoother that costs more per application should be compared at
     equal cost (the paper matches its convolution layers with as many Jacobi
     steps); here the comparison is simply time to the same tolerance."""
+    gc.collect()
     import torch
 
     from paper_2102_12071_amd import mgcnn
@@ -422,6 +430,7 @@ def stack_block(args, A, f, n, theta, eps, coarsest):
     five stencil planes of a symmetric stencil and writes e and a quarter node of
     r_c, 29 B; the finest ascend reads a quarter node of e_c, e, r, the stencil
     and reads and writes u in FP64, 45 B)."""
+    gc.collect()
     import glob
 
     import torch
@@ -478,6 +487,7 @@ def redblack_block(args, n, theta, eps):
     the deepest trained level of their kind, rescaled to their centre entry) in V(1,1), against
     damped Jacobi V(1,1) and the cost-matched V(2,2) (two Jacobi sweeps per smoothing step, as the
     smoother has two convolutions), all with the same red-black hierarchy."""
+    gc.collect()
     from paper_2102_12071_amd import rb_train
     path = os.path.join(os.path.dirname(args.weights), f"rb_theta{theta:.3f}_eps{eps:g}.json")
     if not os.path.exists(path):
@@ -523,6 +533,7 @@ def training_block(args):
     caller-made stencils and vectors (mg_train_step).  Useful FLOP: forward and
     the two backward convolutions (data and weight gradients), 3 x 56,448 per
     point."""
+    gc.collect()
     import numpy as np
     import torch
 
@@ -601,6 +612,7 @@ def hf_block(args, net, f, n, theta, eps):
     """The single network trained on the high-frequency loss, on the headline
     problem and tolerance (its own 7 x 7 coarsest grid), beside the per-level
     networks of the headline."""
+    gc.collect()
     import torch
 
     from paper_2102_12071_amd import mgcnn
@@ -627,6 +639,7 @@ def geometry_block(args, net, alpha_nets, n):
     iterations and solve time to the headline tolerance of the single
     network, of the per-level networks when given (with the fallback to
     damped Jacobi), and of damped Jacobi; 7 x 7 coarsest grid."""
+    gc.collect()
     import torch
 
     import mg_inputs
@@ -670,6 +683,7 @@ def fgmres_block(args, ctx_cnn, ctx_jac, f, n):
     """The same problem solved by flexible GMRES(restart) preconditioned by one
     V(1,1) cycle per iteration (the paper's incorporation with FGMRES), to the
     same tolerance: beside the headline, not part of it."""
+    gc.collect()
     import torch
     out = {"restart": args.restart, "tol": args.tol}
     for name, ctx in (("cnn", ctx_cnn), ("jacobi", ctx_jac)):
@@ -706,6 +720,7 @@ def workload_c4(args):
     (squared-exponential covariance, length 0.1, sigma 1, seed 7); CNN smoother
     on every level, V(1,1), FP64 iterative refinement to 1e-10; damped Jacobi
     beside it."""
+    gc.collect()
     import torch
 
     import mg_inputs
@@ -756,6 +771,7 @@ def workload_c5(args):
     U[0, pi), log10 eps ~ U[-4, 0], RHS U(-1, 1), all in one context (one
     launch per size class and kernel), solved to 1e-8 with the CNN smoother and
     with damped Jacobi."""
+    gc.collect()
     import numpy as np
     import torch
 

@@ -313,6 +313,9 @@ void destroy_ctx(mg_ctx c)
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->t0) (void)hipEventDestroy(c->t0);
     if (c->t1) (void)hipEventDestroy(c->t1);
+    for (hipEvent_t e : c->ev_state)
+        if (e) (void)hipEventDestroy(e);
+    if (c->h_state) (void)hipHostFree(c->h_state);
     c->arena.release();
     c->join.destroy();
     delete c;
@@ -385,6 +388,8 @@ mg_status setup_impl(mg_ctx_s &c, const mg_problem *probs, hipStream_t user)
     c.arena.stream = c.join.internal;
     MG_HIP(hipEventCreate(&c.t0));
     MG_HIP(hipEventCreate(&c.t1));
+    for (hipEvent_t &e : c.ev_state) MG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    MG_HIP(hipHostMalloc((void **)&c.h_state, 2 * sizeof(SolveState) * c.nprob, hipHostMallocDefault));
     MG_TRY(c.join.enter());
     hipStream_t st = c.join.internal;
     const bool mixed = c.opt.precision == MG_PREC_MIXED;
@@ -758,25 +763,45 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
         enqueue_check<float>(c, 1, st);
     }
     std::vector<SolveState> hs(c.nprob);
-    std::vector<char> act(c.nprob);
+    std::vector<char> act(c.nprob), live(c.nprob, 1);
     const int every = c.opt.check_every;
     int64_t replays = 0;
     // maxit cycles and the last check take maxit + 1 replays; a problem paused for the fallback
     // spends the rest of its check block without cycling, so each switch adds one block
     int64_t budget = (int64_t)maxit + 2;
-    for (;;) {
-        MG_TRY(ensure_graph(c));  // (re)captured with the live classes; the stream is idle here
+    // One check block of iterations, then the problems' states copied to pinned host memory and an
+    // event behind the copy.  Without the fallback the host only reads those states, so the next block
+    // is queued before the host waits for the last one's copy and the device does not idle while the
+    // host decides; a block queued after the one that finished the solve finds every problem inactive
+    // and its kernels return at once.  A change of the live set waits until the stream has drained,
+    // since it rewrites slot tables that a queued block reads.
+    const bool ahead = !prm.fallback;
+    SolveState *const hbuf[2] = {c.h_state, c.h_state + c.nprob};
+    int64_t rep[2] = {0, 0};
+    auto enqueue_block = [&](int b) -> mg_status {
+        MG_TRY(ensure_graph(c));  // (re)captured with the live classes; the stream is idle whenever it changes
         if (c.graph_exec)
             MG_HIP(hipGraphLaunch(c.graph_exec, st));  // every iterations
         else
             for (int q = 0; q < every; ++q) enqueue_iteration_any(c, st);
         replays += every;
-        MG_HIP(hipMemcpyAsync(hs.data(), c.d_state, sizeof(SolveState) * c.nprob, hipMemcpyDeviceToHost, st));
-        MG_HIP(hipStreamSynchronize(st));
-        // problems paused by the fallback rule: damped Jacobi from now on
+        rep[b] = replays;
+        MG_HIP(hipMemcpyAsync(hbuf[b], c.d_state, sizeof(SolveState) * c.nprob, hipMemcpyDeviceToHost, st));
+        MG_HIP(hipEventRecord(c.ev_state[b], st));
+        return MG_OK;
+    };
+    int cur = 0;
+    MG_TRY(enqueue_block(cur));
+    for (;;) {
+        const int nxt = 1 - cur;
+        const bool queued = ahead;
+        if (queued) MG_TRY(enqueue_block(nxt));
+        MG_HIP(hipEventSynchronize(c.ev_state[cur]));
+        SolveState *const hsb = hbuf[cur];
+        // problems paused by the fallback rule: damped Jacobi from now on (the stream is idle here)
         bool resumed = false;
-        for (int p = 0; p < c.nprob; ++p) {
-            SolveState &s = hs[p];
+        for (int p = 0; p < c.nprob && !ahead; ++p) {
+            SolveState &s = hsb[p];
             if (s.status != 2 || (s.fallback != 1 && s.fallback != 3)) continue;
             const ProbBuf &pb = c.probs[p];
             for (int l = 0; l + 1 < pb.nlev; ++l) {
@@ -797,17 +822,23 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
             resumed = true;
         }
         if (resumed) {
-            MG_HIP(hipMemcpyAsync(c.d_state, hs.data(), sizeof(SolveState) * c.nprob, hipMemcpyHostToDevice, st));
+            MG_HIP(hipMemcpyAsync(c.d_state, hsb, sizeof(SolveState) * c.nprob, hipMemcpyHostToDevice, st));
             MG_HIP(hipStreamSynchronize(st));
             budget += every;
         }
         bool any = false;
         for (int p = 0; p < c.nprob; ++p) {
-            act[p] = hs[p].active != 0;
+            act[p] = hsb[p].active != 0;
             any |= act[p] != 0;
         }
-        if (!any || replays > budget) break;
-        MG_TRY(update_live(c, act));
+        if (!any || rep[cur] > budget) break;
+        if (act != live) {
+            if (queued) MG_HIP(hipStreamSynchronize(st));
+            MG_TRY(update_live(c, act));
+            live = act;
+        }
+        if (!queued) MG_TRY(enqueue_block(nxt));
+        cur = nxt;
     }
     copy_out(c, u, st);
     MG_HIP(hipEventRecord(c.t1, st));

@@ -176,6 +176,10 @@ struct mg_ctx_s {
     bool graph_stale = false;            // the live set changed: mg_solve re-captures before its next replay
     hipEvent_t t0 = nullptr, t1 = nullptr;
     double last_ms = 0.0;
+    // mg_solve: two pinned copies of the per-problem state, each with the event that follows its copy,
+    // so that the next check block can be queued before the host reads the last one
+    mg::SolveState *h_state = nullptr;   // [2][nprob], hipHostMalloc
+    hipEvent_t ev_state[2] = {nullptr, nullptr};
     // CNN inference scratch (direct path)
     void *cnn_scratch = nullptr;
     size_t cnn_scratch_bytes = 0;

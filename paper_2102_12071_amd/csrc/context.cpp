@@ -770,12 +770,16 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
     // spends the rest of its check block without cycling, so each switch adds one block
     int64_t budget = (int64_t)maxit + 2;
     // One check block of iterations, then the problems' states copied to pinned host memory and an
-    // event behind the copy.  Without the fallback the host only reads those states, so the next block
-    // is queued before the host waits for the last one's copy and the device does not idle while the
-    // host decides; a block queued after the one that finished the solve finds every problem inactive
-    // and its kernels return at once.  A change of the live set waits until the stream has drained,
-    // since it rewrites slot tables that a queued block reads.
+    // event behind the copy.  Without the fallback the host only reads those states, so when some
+    // problem is expected to iterate beyond the block in flight, the next block is queued before the
+    // host waits for the last one's copy and the device does not idle while the host decides.  The
+    // expectation: its relative residual after the last block, reduced once more by that block's
+    // factor, still above 4 tol, and maxit not reached (a block queued behind the one that ends the
+    // solve would run with every problem inactive: 1.5 ms at n = 4095).  A change of the live set
+    // waits until the stream has drained, since it rewrites slot tables that a queued block reads.
     const bool ahead = !prm.fallback;
+    std::vector<double> rel1(c.nprob, 0.0), rel2(c.nprob, 0.0);  // after the last two blocks read
+    bool more = false;
     SolveState *const hbuf[2] = {c.h_state, c.h_state + c.nprob};
     int64_t rep[2] = {0, 0};
     auto enqueue_block = [&](int b) -> mg_status {
@@ -794,7 +798,7 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
     MG_TRY(enqueue_block(cur));
     for (;;) {
         const int nxt = 1 - cur;
-        const bool queued = ahead;
+        const bool queued = ahead && more;
         if (queued) MG_TRY(enqueue_block(nxt));
         MG_HIP(hipEventSynchronize(c.ev_state[cur]));
         SolveState *const hsb = hbuf[cur];
@@ -832,6 +836,14 @@ mg_status mg_solve(mg_ctx ctx, const double *const *f, double *const *u, double 
             any |= act[p] != 0;
         }
         if (!any || rep[cur] > budget) break;
+        more = false;
+        for (int p = 0; p < c.nprob; ++p) {
+            rel2[p] = rel1[p];
+            rel1[p] = hsb[p].relres;
+            if (act[p] && rel2[p] > 0.0 && (int64_t)hsb[p].iters + every < maxit &&
+                rel1[p] * (rel1[p] / rel2[p]) > 4.0 * rtol)
+                more = true;
+        }
         if (act != live) {
             if (queued) MG_HIP(hipStreamSynchronize(st));
             MG_TRY(update_live(c, act));
